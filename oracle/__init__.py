@@ -1,0 +1,273 @@
+"""CPU oracle for the bi-fluid finite-volume step: ctypes binding.
+
+TEST INFRASTRUCTURE ONLY.  Only ``tests/``, ``__graft_entry__.smoke()`` and the
+CPU-baseline leg of ``bench.py`` may import this package.  It shares no code
+with the HIP library; the only module both read is the seeded input module
+``paper_2207_04252_amd.synth`` (configurations and noise, no arithmetic of the
+method).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+from paper_2207_04252_amd import synth
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liboracle.so")
+SRC_PATH = os.path.join(_HERE, "oracle.cpp")
+
+OK, EINVAL, ENEGATIVE, EVACUUM, ENOCONV, ESTIFF = 0, -1, -4, -5, -6, -7
+DT_CFL, DT_FIXED, DT_LIST = 0, 1, 2
+
+
+def build(verbose: bool = False) -> str:
+    """Compile the oracle with g++ (portable x86-64 code, no FMA contraction)."""
+    cmd = ["g++", "-O2", "-std=c++17", "-fopenmp", "-ffp-contract=off", "-fno-fast-math",
+           "-fPIC", "-shared", "-Wall", "-o", LIB_PATH + ".tmp", SRC_PATH]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.run(cmd, check=True)
+    os.replace(LIB_PATH + ".tmp", LIB_PATH)
+    return LIB_PATH
+
+
+class OrConfig(ctypes.Structure):
+    _fields_ = [
+        ("nr", ctypes.c_int32), ("nth", ctypes.c_int32), ("nz", ctypes.c_int32),
+        ("log_r", ctypes.c_int32), ("init_kind", ctypes.c_int32), ("balanced", ctypes.c_int32),
+        ("n_dust", ctypes.c_int32), ("pad0", ctypes.c_int32),
+        ("r_in", ctypes.c_double), ("r_out", ctypes.c_double), ("z_half", ctypes.c_double),
+        ("gamma", ctypes.c_double), ("GM", ctypes.c_double), ("cfl", ctypes.c_double),
+        ("sod_r0", ctypes.c_double), ("sod_left", ctypes.c_double * 3),
+        ("sod_right", ctypes.c_double * 3),
+        ("h0", ctypes.c_double), ("beta_T", ctypes.c_double), ("rho_mid0", ctypes.c_double),
+        ("beta_rho", ctypes.c_double),
+        ("vortex_amp", ctypes.c_double), ("vortex_r0", ctypes.c_double),
+        ("vortex_th0", ctypes.c_double), ("vortex_sig_r", ctypes.c_double),
+        ("vortex_sig_a", ctypes.c_double), ("noise_amp", ctypes.c_double),
+        ("stokes", ctypes.c_double * 4), ("eps_dust", ctypes.c_double * 4),
+        ("hd_over_h", ctypes.c_double * 4),
+    ]
+
+
+class OrDiag(ctypes.Structure):
+    _fields_ = [
+        ("t", ctypes.c_double), ("step", ctypes.c_int64), ("flags", ctypes.c_int32),
+        ("first_bad_step", ctypes.c_int32), ("first_bad_cell", ctypes.c_int64),
+        ("fallbacks", ctypes.c_int64), ("vacuum_faces", ctypes.c_int64),
+        ("max_newton", ctypes.c_int32), ("pad", ctypes.c_int32),
+        ("mass", ctypes.c_double * 5), ("outflow", ctypes.c_double * 5),
+        ("dt_last", ctypes.c_double),
+    ]
+
+
+def to_struct(cfg: synth.Config) -> OrConfig:
+    s = OrConfig()
+    s.nr, s.nth, s.nz = cfg.nr, cfg.nth, cfg.nz
+    s.log_r = int(cfg.log_r)
+    s.init_kind = cfg.init_kind
+    s.balanced = int(cfg.balanced)
+    s.n_dust = cfg.n_dust
+    s.r_in, s.r_out, s.z_half = cfg.r_in, cfg.r_out, cfg.z_half
+    s.gamma, s.GM, s.cfl = cfg.gamma, cfg.GM, cfg.cfl
+    s.sod_r0 = cfg.sod_r0
+    for q in range(3):
+        s.sod_left[q] = cfg.sod_left[q]
+        s.sod_right[q] = cfg.sod_right[q]
+    s.h0, s.beta_T, s.rho_mid0, s.beta_rho = cfg.h0, cfg.beta_T, cfg.rho_mid0, cfg.beta_rho
+    s.vortex_amp, s.vortex_r0, s.vortex_th0 = cfg.vortex_amp, cfg.vortex_r0, cfg.vortex_th0
+    s.vortex_sig_r, s.vortex_sig_a, s.noise_amp = cfg.vortex_sig_r, cfg.vortex_sig_a, cfg.noise_amp
+    for q in range(cfg.n_dust):
+        s.stokes[q] = cfg.stokes[q]
+        s.eps_dust[q] = cfg.eps_dust[q]
+        s.hd_over_h[q] = cfg.hd_over_h[q]
+    return s
+
+
+_lib = None
+_D = ctypes.POINTER(ctypes.c_double)
+
+
+def lib() -> ctypes.CDLL:
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            build()
+        L = ctypes.CDLL(LIB_PATH)
+        L.or_create.restype = ctypes.c_void_p
+        L.or_create.argtypes = [ctypes.POINTER(OrConfig), _D, _D]
+        L.or_destroy.argtypes = [ctypes.c_void_p]
+        L.or_step.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_double, _D, _D]
+        for name in ("or_get_state", "or_set_state", "or_get_residual", "or_mass"):
+            getattr(L, name).argtypes = [ctypes.c_void_p, _D]
+        L.or_get_background.argtypes = [ctypes.c_void_p, ctypes.c_int, _D]
+        L.or_get_geometry.argtypes = [ctypes.c_void_p] + [_D] * 7
+        L.or_eval_G.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, _D]
+        L.or_cfl_dt.restype = ctypes.c_double
+        L.or_cfl_dt.argtypes = [ctypes.c_void_p]
+        L.or_min_stopping_time.restype = ctypes.c_double
+        L.or_min_stopping_time.argtypes = [ctypes.c_void_p]
+        L.or_diag.argtypes = [ctypes.c_void_p, ctypes.POINTER(OrDiag)]
+        L.or_core_dust_mass.restype = ctypes.c_double
+        L.or_core_dust_mass.argtypes = [ctypes.c_void_p, ctypes.c_double, ctypes.c_double,
+                                        ctypes.c_double]
+        L.or_riemann_gas.restype = ctypes.c_int
+        L.or_riemann_gas.argtypes = [ctypes.c_double, _D, _D, _D, _D, _D]
+        L.or_pressure_fn.restype = ctypes.c_double
+        L.or_pressure_fn.argtypes = [ctypes.c_double] * 4 + [_D]
+        L.or_riemann_dust.argtypes = [_D, _D, _D]
+        L.or_parabola_increment.restype = ctypes.c_double
+        L.or_parabola_increment.argtypes = [ctypes.c_double] * 7
+        L.or_equilibrium.argtypes = [ctypes.POINTER(OrConfig), ctypes.c_double, ctypes.c_double, _D]
+        L.or_tangent.restype = ctypes.c_int
+        L.or_tangent.argtypes = [ctypes.POINTER(OrConfig), _D, _D, _D, _D, ctypes.c_int, _D,
+                                 ctypes.c_double, ctypes.c_double, ctypes.c_double, _D, _D]
+        L.or_threads.restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def _ptr(a):
+    if a is None:
+        return None
+    return a.ctypes.data_as(_D)
+
+
+def _f64(a):
+    return None if a is None else np.ascontiguousarray(a, dtype=np.float64)
+
+
+class Oracle:
+    """One oracle simulation (state on the host, FP64, [field][k][i][j])."""
+
+    def __init__(self, cfg: synth.Config, noise: np.ndarray | None = None,
+                 amp: np.ndarray | None = None):
+        self.cfg = cfg
+        self._s = to_struct(cfg)
+        self._noise = _f64(noise)
+        self._amp = _f64(amp)
+        self.h = lib().or_create(ctypes.byref(self._s), _ptr(self._noise), _ptr(self._amp))
+        if not self.h:
+            raise ValueError(f"oracle rejected config {cfg.name}")
+        self.nf = cfg.n_fields
+        self.shape = (self.nf, cfg.nz, cfg.nr, cfg.nth)
+
+    def __del__(self):
+        h = getattr(self, "h", None)
+        if h:
+            lib().or_destroy(h)
+            self.h = None
+
+    def step(self, n: int, dt: float | None = None, dt_list=None):
+        """Advance n steps: CFL (default), fixed dt, or a list of dt. Returns (status, dts)."""
+        dts = np.zeros(max(n, 1))
+        if dt_list is not None:
+            lst = _f64(dt_list)
+            st = lib().or_step(self.h, n, DT_LIST, 0.0, _ptr(lst), _ptr(dts))
+        elif dt is not None:
+            st = lib().or_step(self.h, n, DT_FIXED, float(dt), None, _ptr(dts))
+        else:
+            st = lib().or_step(self.h, n, DT_CFL, 0.0, None, _ptr(dts))
+        return st, dts[:n]
+
+    def state(self) -> np.ndarray:
+        out = np.empty(self.shape)
+        lib().or_get_state(self.h, _ptr(out))
+        return out
+
+    def set_state(self, s: np.ndarray):
+        s = _f64(s)
+        assert s.size == int(np.prod(self.shape))
+        lib().or_set_state(self.h, _ptr(s))
+
+    def residual(self) -> np.ndarray:
+        out = np.empty((self.cfg.nz, self.cfg.nr, 5))
+        lib().or_get_residual(self.h, _ptr(out))
+        return out
+
+    def background(self, where: int) -> np.ndarray:
+        c = self.cfg
+        shape = [(c.nz, c.nr, self.nf), (c.nz, c.nr + 1, self.nf), (c.nz + 1, c.nr, self.nf)][where]
+        out = np.empty(shape)
+        lib().or_get_background(self.h, where, _ptr(out))
+        return out
+
+    def geometry(self) -> dict:
+        c = self.cfg
+        g = dict(rf=np.empty(c.nr + 1), rc=np.empty(c.nr), zc=np.empty(c.nz), V=np.empty(c.nr),
+                 Ar=np.empty(c.nr + 1), Ath=np.empty(c.nr), Az=np.empty(c.nr))
+        lib().or_get_geometry(self.h, *[_ptr(g[k]) for k in ("rf", "rc", "zc", "V", "Ar", "Ath", "Az")])
+        return g
+
+    def eval_G(self, with_dust: bool = True, subtract_R0: bool = True) -> np.ndarray:
+        out = np.empty(self.shape)
+        lib().or_eval_G(self.h, int(with_dust), int(subtract_R0), _ptr(out))
+        return out
+
+    def cfl_dt(self) -> float:
+        return lib().or_cfl_dt(self.h)
+
+    def min_stopping_time(self) -> float:
+        return lib().or_min_stopping_time(self.h)
+
+    def mass(self) -> np.ndarray:
+        out = np.zeros(5)
+        lib().or_mass(self.h, _ptr(out))
+        return out[: 1 + self.cfg.n_dust]
+
+    def diag(self) -> OrDiag:
+        d = OrDiag()
+        lib().or_diag(self.h, ctypes.byref(d))
+        return d
+
+    def core_dust_mass(self) -> float:
+        return lib().or_core_dust_mass(self.h, synth.CORE_R[0], synth.CORE_R[1], synth.CORE_DTH)
+
+
+def riemann_gas(gamma, WL, WR):
+    """Exact gas Riemann problem: returns (W at x/t=0, flux, (p*, u*), iterations)."""
+    WL = _f64(WL); WR = _f64(WR)
+    W = np.zeros(5); F = np.zeros(5); star = np.zeros(2)
+    it = lib().or_riemann_gas(gamma, _ptr(WL), _ptr(WR), _ptr(W), _ptr(F), _ptr(star))
+    return W, F, star, it
+
+
+def pressure_fn(gamma, p, rhoK, pK):
+    d = np.zeros(1)
+    f = lib().or_pressure_fn(gamma, p, rhoK, pK, _ptr(d))
+    return f, d[0]
+
+
+def riemann_dust(WL, WR):
+    WL = _f64(WL); WR = _f64(WR)
+    F = np.zeros(4)
+    lib().or_riemann_dust(_ptr(WL), _ptr(WR), _ptr(F))
+    return F
+
+
+def parabola_increment(em, e0, ep, xm, x0, xp, xf):
+    return lib().or_parabola_increment(em, e0, ep, xm, x0, xp, xf)
+
+
+def equilibrium(cfg: synth.Config, r: float, z: float):
+    s = to_struct(cfg)
+    out = np.zeros(3)
+    lib().or_equilibrium(ctypes.byref(s), r, z, _ptr(out))
+    return out
+
+
+def tangent(cfg: synth.Config, noise, amp, amp_dot, st_dot, dt_list):
+    """Forward-mode (dual number) derivative of the core dust mass after len(dt_list) steps."""
+    s = to_struct(cfg)
+    noise = _f64(noise); amp = _f64(amp); amp_dot = _f64(amp_dot)
+    st = _f64(np.zeros(4) if st_dot is None else np.pad(np.asarray(st_dot, float), (0, 4 - len(st_dot))))
+    dts = _f64(dt_list)
+    J = np.zeros(1); dJ = np.zeros(1)
+    status = lib().or_tangent(ctypes.byref(s), _ptr(noise), _ptr(amp), _ptr(amp_dot), _ptr(st),
+                              len(dts), _ptr(dts), synth.CORE_R[0], synth.CORE_R[1], synth.CORE_DTH,
+                              _ptr(J), _ptr(dJ))
+    return status, J[0], dJ[0]

@@ -1,0 +1,149 @@
+"""Seeded synthetic inputs for the bi-fluid disc step.
+
+This module holds the named workload configurations and the seeded noise
+generator.  It is the only module that both the HIP library binding and the
+CPU oracle read: it contains parameters and random numbers, and none of the
+method's arithmetic (no mesh, no equilibrium, no flux).
+
+Noise: SplitMix64 (Steele, Lea & Flood, "Fast splittable pseudorandom number
+generators", OOPSLA 2014), keyed by ``seed XOR global cell index`` with the
+global index ``(k*nr + i)*ntheta + j``; the top 53 bits give a uniform double
+in [0, 1) which is mapped to [-1, 1).
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+from dataclasses import dataclass, field, replace
+from typing import Tuple
+
+import numpy as np
+
+INIT_SOD = 0
+INIT_DISC = 1
+
+DEFAULT_SEED = 220704252
+
+
+@dataclass(frozen=True)
+class Config:
+    """One workload: grid, physics constants, initial-state recipe."""
+    name: str
+    nr: int
+    nth: int
+    nz: int
+    log_r: bool
+    r_in: float
+    r_out: float
+    z_half: float
+    init_kind: int
+    gamma: float = 1.4
+    GM: float = 1.0
+    cfl: float = 0.5
+    balanced: bool = True
+    # Sod annulus (init_kind == INIT_SOD): (rho, p, u_r) left/right of sod_r0
+    sod_r0: float = 1.5
+    sod_left: Tuple[float, float, float] = (1.0, 1.0, 0.0)
+    sod_right: Tuple[float, float, float] = (0.125, 0.1, 0.0)
+    # disc (init_kind == INIT_DISC): H/r = h0 at r = 1, T ~ r^beta_T,
+    # midplane density rho_mid0 * r^beta_rho
+    h0: float = 0.05
+    beta_T: float = -0.5
+    rho_mid0: float = 1.0
+    beta_rho: float = -1.5
+    # column Gaussian vortex (streamfunction), amplitude = -Rossby number
+    vortex_amp: float = 0.0
+    vortex_r0: float = 1.0
+    vortex_th0: float = math.pi
+    vortex_sig_r: float = 0.05
+    vortex_sig_a: float = 0.15
+    noise_amp: float = 0.0
+    seed: int = DEFAULT_SEED
+    stokes: Tuple[float, ...] = ()
+    eps_dust: Tuple[float, ...] = ()
+    hd_over_h: Tuple[float, ...] = ()
+    steps: int = 100
+
+    @property
+    def n_dust(self) -> int:
+        return len(self.stokes)
+
+    @property
+    def n_fields(self) -> int:
+        return 5 + 4 * self.n_dust
+
+    @property
+    def n_cells(self) -> int:
+        return self.nr * self.nth * self.nz
+
+    def scaled(self, nr: int, nth: int, nz: int, name: str | None = None) -> "Config":
+        """Same physics on another grid (for tests that the oracle finishes in seconds)."""
+        return replace(self, nr=nr, nth=nth, nz=nz,
+                       name=name or f"{self.name}@{nr}x{nth}x{nz}")
+
+    def with_(self, **kw) -> "Config":
+        return replace(self, **kw)
+
+
+def _disc(name, nr, nth, nz, **kw) -> Config:
+    base = dict(log_r=True, r_in=0.5, r_out=2.0, z_half=0.15, init_kind=INIT_DISC,
+                GM=1.0, balanced=True, vortex_amp=1e-3, noise_amp=1e-6)
+    base.update(kw)
+    return Config(name=name, nr=nr, nth=nth, nz=nz, **base)
+
+
+# The five workloads (grid sizes and physics as the paper's test outlines,
+# at the resolutions used for measurement).
+C1_SOD = Config(name="sod_annulus_256x64x1", nr=256, nth=64, nz=1, log_r=False,
+                r_in=1.0, r_out=2.0, z_half=0.5, init_kind=INIT_SOD, GM=0.0,
+                balanced=False, steps=100)
+C2_DISC = _disc("gas_disc_128x256x64", 128, 256, 64, steps=200)
+C3_BIFLUID = _disc("bifluid_disc_256x512x64", 256, 512, 64, stokes=(0.1,),
+                   eps_dust=(0.01,), hd_over_h=(0.3,), steps=500)
+C4_LARGE = _disc("bifluid3_disc_512x1024x128", 512, 1024, 128, vortex_amp=1e-2,
+                 stokes=(0.01, 0.1, 1.0), eps_dust=(0.0033, 0.0033, 0.0033),
+                 hd_over_h=(0.3, 0.3, 0.3), steps=1000)
+C5_ADJOINT = _disc("adjoint_disc_128x256x32", 128, 256, 32, stokes=(0.1,),
+                   eps_dust=(0.01,), hd_over_h=(0.3,), steps=200)
+
+CONFIGS = {c.name: c for c in (C1_SOD, C2_DISC, C3_BIFLUID, C4_LARGE, C5_ADJOINT)}
+
+# vortex core region used by the adjoint objective (dust mass in the core)
+CORE_R = (0.9, 1.1)
+CORE_DTH = 0.3
+
+_M64 = np.uint64(0xFFFFFFFFFFFFFFFF)
+
+
+def splitmix64(x: np.ndarray) -> np.ndarray:
+    """SplitMix64 output function applied elementwise to uint64 keys."""
+    with np.errstate(over="ignore"):
+        z = (x + np.uint64(0x9E3779B97F4A7C15)) & _M64
+        z = ((z ^ (z >> np.uint64(30))) * np.uint64(0xBF58476D1CE4E5B9)) & _M64
+        z = ((z ^ (z >> np.uint64(27))) * np.uint64(0x94D049BB133111EB)) & _M64
+        return z ^ (z >> np.uint64(31))
+
+
+def noise(cfg: Config) -> np.ndarray:
+    """Uniform noise xi in [-1, 1), shape (nz, nr, nth), float64, C order."""
+    n = cfg.n_cells
+    idx = np.arange(n, dtype=np.uint64)
+    z = splitmix64(np.uint64(cfg.seed) ^ idx)
+    u = (z >> np.uint64(11)).astype(np.float64) * (1.0 / 9007199254740992.0)
+    return (2.0 * u - 1.0).reshape(cfg.nz, cfg.nr, cfg.nth)
+
+
+def amplitude_field(cfg: Config, amp: float | None = None) -> np.ndarray:
+    """Per-cell vortex amplitude field (uniform at the config's amplitude)."""
+    a = cfg.vortex_amp if amp is None else amp
+    return np.full((cfg.nz, cfg.nr, cfg.nth), a, dtype=np.float64)
+
+
+def random_direction(cfg: Config, seed: int = 7) -> np.ndarray:
+    """Seeded random field in [-1, 1) used as a tangent direction in gradient checks."""
+    rng = np.random.default_rng(seed)
+    return rng.uniform(-1.0, 1.0, size=(cfg.nz, cfg.nr, cfg.nth))
+
+
+def config_dict(cfg: Config) -> dict:
+    return dataclasses.asdict(cfg)

@@ -1,0 +1,259 @@
+"""Pins of the oracle's exact Riemann solvers (Sect. 2.6 and 2.9 of the paper).
+
+Nothing here reuses the oracle's formulas: the pins are the Sod values, an
+independent bisection of the textbook pressure function, conservation of the
+self-similar solution over its fan (which fixes every wave speed and star
+state through the Rankine-Hugoniot relations), Riemann invariants and
+isentropy across a sonic fan, Galilean and mirror invariance, and the
+delta-shock jump condition of the pressureless system.
+"""
+import math
+
+import numpy as np
+import pytest
+
+G = 1.4
+
+# Sod problem (rho, u, p) = (1, 0, 1) | (0.125, 0, 0.1), gamma = 1.4: exact star state,
+# Godunov flux at x/t = 0 and wave speeds, as obtained by bisection of the pressure
+# function (textbook values, e.g. Toro, Riemann Solvers and Numerical Methods, ch. 4).
+SOD_PSTAR, SOD_USTAR = 0.303130, 0.927453
+SOD_RHOSL, SOD_RHOSR = 0.426319, 0.265574
+SOD_FLUX = (0.395391, 0.669837, 1.154038)  # mass, momentum, energy
+SOD_SHOCK, SOD_HEAD, SOD_TAIL = 1.752156, -1.183216, -0.070273
+
+
+def _bisect_pstar(rL, uL, pL, rR, uR, pR, g=G):
+    """Independent bisection of f_L(p) + f_R(p) + du = 0 (textbook pressure function)."""
+    def fK(p, r, pk):
+        c = math.sqrt(g * pk / r)
+        if p > pk:
+            A = 2.0 / ((g + 1.0) * r)
+            B = (g - 1.0) / (g + 1.0) * pk
+            return (p - pk) * math.sqrt(A / (p + B))
+        return 2.0 * c / (g - 1.0) * ((p / pk) ** ((g - 1.0) / (2.0 * g)) - 1.0)
+    lo, hi = 1e-12, 100.0 * max(pL, pR) + 10.0
+    for _ in range(300):
+        mid = 0.5 * (lo + hi)
+        if fK(mid, rL, pL) + fK(mid, rR, pR) + (uR - uL) > 0.0:
+            hi = mid
+        else:
+            lo = mid
+    p = 0.5 * (lo + hi)
+    u = 0.5 * (uL + uR) + 0.5 * (fK(p, rR, pR) - fK(p, rL, pL))
+    return p, u
+
+
+def test_sod_star_state_and_flux(oracle_mod):
+    W, F, star, it = oracle_mod.riemann_gas(G, [1, 0, 0, 0, 1], [0.125, 0, 0, 0, 0.1])
+    pb, ub = _bisect_pstar(1, 0, 1, 0.125, 0, 0.1)
+    assert abs(star[0] - pb) < 1e-12 and abs(star[1] - ub) < 1e-12
+    assert abs(star[0] - SOD_PSTAR) < 1e-6 and abs(star[1] - SOD_USTAR) < 1e-6
+    # x/t = 0 lies in the left star region (not transonic): W = (rho*_L, u*, p*)
+    assert abs(W[0] - SOD_RHOSL) < 1e-6 and abs(W[1] - SOD_USTAR) < 1e-6
+    assert abs(W[4] - SOD_PSTAR) < 1e-6
+    assert abs(F[0] - SOD_FLUX[0]) < 1e-6 and abs(F[1] - SOD_FLUX[1]) < 1e-6
+    assert abs(F[4] - SOD_FLUX[2]) < 1e-6
+    assert 1 <= it <= 50
+
+
+def _shifted(oracle_mod, WL, WR, xi):
+    """Solution at x/t = xi, by Galilean shift of both states (the solver samples x/t = 0)."""
+    L = np.array(WL, float); R = np.array(WR, float)
+    L[1] -= xi; R[1] -= xi
+    W, _, _, _ = oracle_mod.riemann_gas(G, L, R)
+    W = W.copy()
+    W[1] += xi
+    return W
+
+
+def _cons(W):
+    rho, un, t1, t2, p = W
+    E = p / (G - 1.0) + 0.5 * rho * (un * un + t1 * t1 + t2 * t2)
+    return np.array([rho, rho * un, rho * t1, rho * t2, E])
+
+
+def _flux(W):
+    rho, un, t1, t2, p = W
+    E = p / (G - 1.0) + 0.5 * rho * (un * un + t1 * t1 + t2 * t2)
+    return np.array([rho * un, rho * un * un + p, rho * un * t1, rho * un * t2, (E + p) * un])
+
+
+def test_sod_wave_speeds_by_sampling(oracle_mod):
+    """The sampled solution changes exactly at the printed wave speeds."""
+    L, R = [1, 0, 0, 0, 1], [0.125, 0, 0, 0, 0.1]
+    eps = 1e-7
+    # shock: right star state just left of the shock, right state just right of it
+    a = _shifted(oracle_mod, L, R, SOD_SHOCK - 1e-5)
+    b = _shifted(oracle_mod, L, R, SOD_SHOCK + 1e-5)
+    assert abs(a[0] - SOD_RHOSR) < 1e-5 and abs(b[0] - 0.125) < 1e-12
+    # rarefaction head and tail
+    assert _shifted(oracle_mod, L, R, SOD_HEAD - 1e-5)[0] == 1.0
+    assert _shifted(oracle_mod, L, R, SOD_HEAD + 1e-4)[0] < 1.0 - eps
+    c = _shifted(oracle_mod, L, R, SOD_TAIL + 1e-5)
+    assert abs(c[0] - SOD_RHOSL) < 1e-5
+    d = _shifted(oracle_mod, L, R, SOD_TAIL - 1e-3)
+    assert d[0] > SOD_RHOSL + 1e-5
+
+
+def _random_problems(n, seed):
+    rng = np.random.default_rng(seed)
+    out = []
+    while len(out) < n:
+        rL, rR = rng.uniform(0.1, 2.0, 2)
+        pL, pR = 10.0 ** rng.uniform(-2, 1, 2)
+        uL, uR = rng.uniform(-2.0, 2.0, 2)
+        cL, cR = math.sqrt(G * pL / rL), math.sqrt(G * pR / rR)
+        if 2.0 / (G - 1.0) * (cL + cR) <= (uR - uL) * 1.2:
+            continue
+        tL = rng.uniform(-1, 1, 2); tR = rng.uniform(-1, 1, 2)
+        out.append(([rL, uL, tL[0], tL[1], pL], [rR, uR, tR[0], tR[1], pR]))
+    # strong-shock and colliding-stream families
+    out.append(([1.0, 0, 0.3, 0.0, 1000.0], [1.0, 0, -0.2, 0.1, 0.01]))
+    out.append(([5.99924, 19.5975, 0, 0, 460.894], [5.99242, -6.19633, 0, 0, 46.0950]))
+    out.append(([1.0, 2.0, 0.1, 0.2, 0.4], [1.0, -2.0, -0.1, 0.3, 0.4]))
+    out.append(([1.0, -1.5, 0.0, 0.0, 0.4], [1.0, 1.5, 0.0, 0.0, 0.4]))  # strong rarefactions
+    return out
+
+
+@pytest.mark.parametrize("case", range(12))
+def test_fan_conservation(oracle_mod, case):
+    """Integral conservation over the self-similar fan:
+    int_{-a}^{a} U(xi) dxi = a (U_L + U_R) - (F(U_R) - F(U_L)) for a beyond all waves.
+    This fixes the star states and every wave speed (Rankine-Hugoniot, isentropes)."""
+    WL, WR = _random_problems(12, 2207)[case]
+    sp = max(abs(WL[1]) + math.sqrt(G * WL[4] / WL[0]), abs(WR[1]) + math.sqrt(G * WR[4] / WR[0]))
+    W, F, star, it = oracle_mod.riemann_gas(G, WL, WR)
+    a = 3.0 * sp + 2.0 * abs(star[1]) + 1.0
+    M = 6000
+    xs = -a + (np.arange(M) + 0.5) * (2 * a / M)
+    integral = np.zeros(5)
+    for xi in xs:
+        integral += _cons(_shifted(oracle_mod, WL, WR, xi))
+    integral *= 2 * a / M
+    expect = a * (_cons(WL) + _cons(WR)) - (_flux(WR) - _flux(WL))
+    scale = a * (np.abs(_cons(WL)) + np.abs(_cons(WR))) + 1e-300
+    err = np.abs(integral - expect) / scale
+    assert np.all(err < 4e-3), (err, WL, WR)
+
+
+def test_sonic_fan_invariants(oracle_mod):
+    """Transonic left rarefaction: at x/t = 0 the state is sonic (u = c) on the same
+    isentrope and Riemann invariant as the left state."""
+    rL, pL = 1.0, 1.0
+    cL = math.sqrt(G * pL / rL)
+    u0 = 0.75 * cL
+    W, F, star, it = oracle_mod.riemann_gas(G, [rL, u0, 0, 0, pL], [0.125, u0, 0, 0, 0.1])
+    rho, u, p = W[0], W[1], W[4]
+    c = math.sqrt(G * p / rho)
+    assert abs(u - c) < 1e-12
+    assert abs((u + 2 * c / (G - 1)) - (u0 + 2 * cL / (G - 1))) < 1e-12
+    assert abs(p / rho ** G - pL / rL ** G) < 1e-12
+
+
+def test_identical_states_bitwise(oracle_mod):
+    rng = np.random.default_rng(3)
+    for _ in range(50):
+        Wx = [rng.uniform(0.1, 3), rng.uniform(-3, 3), rng.uniform(-1, 1), rng.uniform(-1, 1),
+              rng.uniform(0.01, 5)]
+        W, F, star, it = oracle_mod.riemann_gas(G, Wx, Wx)
+        assert np.array_equal(W, np.array(Wx)), (W, Wx)
+        assert star[0] == Wx[4] and star[1] == Wx[1]
+
+
+def test_galilean_and_mirror_invariance(oracle_mod):
+    for WL, WR in _random_problems(10, 11):
+        _, _, s0, _ = oracle_mod.riemann_gas(G, WL, WR)
+        L = list(WL); R = list(WR)
+        L[1] += 0.37; R[1] += 0.37
+        _, _, s1, _ = oracle_mod.riemann_gas(G, L, R)
+        assert abs(s1[0] - s0[0]) < 1e-11 * s0[0] and abs(s1[1] - s0[1] - 0.37) < 1e-11
+        Lm = [WR[0], -WR[1], WR[2], WR[3], WR[4]]
+        Rm = [WL[0], -WL[1], WL[2], WL[3], WL[4]]
+        _, _, s2, _ = oracle_mod.riemann_gas(G, Lm, Rm)
+        assert abs(s2[0] - s0[0]) < 1e-11 * s0[0] and abs(s2[1] + s0[1]) < 1e-11
+
+
+def test_tangential_velocity_from_contact_side(oracle_mod):
+    W, F, star, it = oracle_mod.riemann_gas(G, [1, 0.2, 0.7, -0.3, 1], [1, 0.2, -0.5, 0.9, 1])
+    assert star[1] > 0 and W[2] == 0.7 and W[3] == -0.3
+    W, F, star, it = oracle_mod.riemann_gas(G, [1, -0.2, 0.7, -0.3, 1], [1, -0.2, -0.5, 0.9, 1])
+    assert star[1] < 0 and W[2] == -0.5 and W[3] == 0.9
+
+
+def test_vacuum_condition(oracle_mod):
+    """Vacuum is generated iff (2/(gamma-1))(c_L + c_R) <= u_R - u_L."""
+    c = math.sqrt(G * 0.4 / 1.0)
+    crit = 2.0 / (G - 1.0) * (2 * c)
+    _, F, _, it = oracle_mod.riemann_gas(G, [1, -0.5 * crit * 1.01, 0, 0, 0.4],
+                                         [1, 0.5 * crit * 1.01, 0, 0, 0.4])
+    assert it == -1 and np.all(F == 0.0)
+    _, F, _, it = oracle_mod.riemann_gas(G, [1, -0.5 * crit * 0.99, 0, 0, 0.4],
+                                         [1, 0.5 * crit * 0.99, 0, 0, 0.4])
+    assert it > 0
+
+
+def test_pressure_function_smooth_at_pK(oracle_mod):
+    """f, f' and f'' are continuous where the shock and rarefaction branches meet;
+    f'(p_K) = 1/(rho_K c_K)."""
+    pk = 1.0
+    h = 1e-5
+    fm, dm = oracle_mod.pressure_fn(G, pk - h, 1.0, pk)
+    fp, dp = oracle_mod.pressure_fn(G, pk + h, 1.0, pk)
+    f0, d0 = oracle_mod.pressure_fn(G, pk, 1.0, pk)
+    assert f0 == 0.0
+    assert abs(d0 - 1.0 / math.sqrt(G)) < 1e-15
+    assert abs(d0 - 0.845154) < 1e-6
+    assert abs(fp - fm - 2 * h * d0) < 1e-9
+    # second derivative from each side agrees (-0.724418 at rho = p = 1)
+    _, dm2 = oracle_mod.pressure_fn(G, pk - 2 * h, 1.0, pk)
+    _, dp2 = oracle_mod.pressure_fn(G, pk + 2 * h, 1.0, pk)
+    left = (d0 - dm2) / (2 * h)
+    right = (dp2 - d0) / (2 * h)
+    assert abs(left - (-0.724418)) < 1e-4 and abs(right - (-0.724418)) < 1e-4
+
+
+# ------------------------------- pressureless (dust) solver ----------------------------
+
+def test_dust_upwind_and_vacuum(oracle_mod):
+    F = oracle_mod.riemann_dust([2.0, 0.5, 0.1, -0.2], [1.0, 0.8, 0.3, 0.4])
+    assert np.allclose(F, [1.0, 0.5, 0.1, -0.2], rtol=0, atol=1e-15)
+    F = oracle_mod.riemann_dust([2.0, -0.8, 0.1, -0.2], [1.0, -0.5, 0.3, 0.4])
+    assert np.allclose(F, [-0.5, 0.25, -0.15, -0.2], rtol=0, atol=1e-15)
+    F = oracle_mod.riemann_dust([2.0, -0.1, 0.1, -0.2], [1.0, 0.5, 0.3, 0.4])
+    assert np.all(F == 0.0)
+
+
+def test_dust_delta_shock_jump_condition(oracle_mod):
+    """Converging streams form a delta shock whose speed s satisfies the jump condition
+    s^2 [rho] - 2 s [rho u] + [rho u^2] = 0.  The speed is located as the frame shift at
+    which the sampled flux switches from the left to the right state."""
+    rng = np.random.default_rng(5)
+    for _ in range(20):
+        rL, rR = rng.uniform(0.1, 3.0, 2)
+        uL = rng.uniform(0.0, 2.0)
+        uR = uL - rng.uniform(0.1, 2.0)
+        lo, hi = uR, uL
+        for _ in range(80):
+            mid = 0.5 * (lo + hi)
+            F = oracle_mod.riemann_dust([rL, uL - mid, 0, 0], [rR, uR - mid, 0, 0])
+            if F[0] > 0:   # left state chosen: shock moves right of x/t = mid
+                lo = mid
+            else:
+                hi = mid
+        s = 0.5 * (lo + hi)
+        jr = rR - rL
+        jm = rR * uR - rL * uL
+        je = rR * uR * uR - rL * uL * uL
+        assert abs(s * s * jr - 2 * s * jm + je) < 1e-10 * (abs(je) + abs(jm) + 1), s
+
+
+def test_dust_symmetric_collision_mean_flux(oracle_mod):
+    F = oracle_mod.riemann_dust([1.5, 0.4, 0.2, 0.0], [1.5, -0.4, -0.2, 0.0])
+    assert F[0] == 0.0 and abs(F[1] - 1.5 * 0.16) < 1e-15 and abs(F[2] - 0.12) < 1e-15
+
+
+def test_dust_empty_sides(oracle_mod):
+    assert np.all(oracle_mod.riemann_dust([0.0, 1.0, 0, 0], [0.0, -1.0, 0, 0]) == 0.0)
+    F = oracle_mod.riemann_dust([0.0, 0.0, 0, 0], [1.0, -0.5, 0, 0])
+    assert np.allclose(F, [-0.5, 0.25, 0, 0])
