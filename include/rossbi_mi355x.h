@@ -1,0 +1,174 @@
+/*
+ * rossbi_mi355x.h -- C ABI of the MI355X (gfx950) library for one time step of the
+ * RoSSBi3D bi-fluid finite-volume scheme (Rendon Restrepo & Barge, arXiv 2207.04252).
+ *
+ * The library advances a compressible inviscid ideal gas and up to four pressureless
+ * dust fluids on a cylindrical (r, theta, z) grid: parabolic reconstruction of the
+ * deviation from the stationary flow with a MinMod limiter (Sect. 2.7), an exact
+ * Riemann problem at every interface (Sect. 2.6; pressureless for the dust, Sect. 2.9),
+ * flux divergence with geometric, gravity and drag sources (Sect. 2.1, App. B), the
+ * empty-run residual of the balanced scheme (Sect. 2.8), the RK2 midpoint step and the
+ * CFL time step (Sect. 2.5).
+ *
+ * Conventions for every call:
+ *   - return value: rb_status, 0 on success, negative on error;
+ *   - device memory for the state, the stage buffer and the work area is allocated by
+ *     the caller (for instance as torch tensors) and passed as raw device pointers; the
+ *     library allocates no device memory;
+ *   - all work is issued on the caller's HIP stream; calls that return host data
+ *     synchronise that stream;
+ *   - a context is thread-compatible, not thread-safe: calls on one context must not
+ *     overlap;
+ *   - fields are stored field-major, then z, then r, then theta:
+ *     index = ((f * nz + k) * nr + i) * ntheta + j, theta contiguous.  Field order:
+ *     gas (rho u, rho v, rho w, E, rho) with u, v, w the r, theta, z velocities
+ *     (App. B), then for each dust species (rho_d u, rho_d v, rho_d w, rho_d).
+ */
+#ifndef ROSSBI_MI355X_H
+#define ROSSBI_MI355X_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  RB_OK = 0,
+  RB_EINVAL = -1,    /* bad argument or configuration                              */
+  RB_ENOMEM = -2,    /* a caller buffer is smaller than rb_query_sizes asked for   */
+  RB_EDEVICE = -3,   /* a HIP call failed                                          */
+  RB_ENEGATIVE = -4, /* a cell has rho <= 0 or p <= 0 (or NaN)                     */
+  RB_EVACUUM = -5,   /* a Riemann problem generated vacuum (run completed)         */
+  RB_ENOCONV = -6,   /* Newton on p* did not converge in 50 iterations             */
+  RB_ESTIFF = -7,    /* dt >= the smallest dust stopping time                      */
+  RB_ESTATE = -8     /* call made in the wrong state (e.g. after a hard error)    */
+} rb_status;
+
+typedef enum { RB_FP64 = 0, RB_FP32_PERT = 1 } rb_precision;
+
+typedef enum { RB_DT_CFL = 0, RB_DT_FIXED = 1, RB_DT_LIST = 2 } rb_dt_kind;
+
+enum { RB_INIT_SOD = 0, RB_INIT_DISC = 1 };
+
+/* Time-step policy.  CFL: dt = min over cells of cfl V / ((|v| + c_s) max|dA|), the
+ * dust adding its own speed (Sect. 2.5); FIXED: dt; LIST: dt_list[q] for step q of the
+ * call (host pointer, n entries). */
+typedef struct {
+  int32_t kind;
+  int32_t pad;
+  double dt;
+  const double* dt_list;
+} rb_dt_policy;
+
+/* Problem statement (Sect. 2.1-2.5, App. A).  Code units: GM and r = 1 set the unit of
+ * length and time; the disc has H/r = h0 at r = 1, temperature ~ r^beta_T and midplane
+ * density rho_mid0 r^beta_rho; z in [-z_half, z_half] (nz == 1: 2D, no z faces). */
+typedef struct {
+  int32_t nr, ntheta, nz;     /* interior cells                                     */
+  int32_t log_r;              /* 1: logarithmic radial faces (Sect. 2.3), 0: uniform  */
+  int32_t init_kind;          /* RB_INIT_SOD or RB_INIT_DISC                         */
+  int32_t balanced;           /* subtract the empty-run residual (Sect. 2.8)         */
+  int32_t n_dust;             /* 0..4 pressureless dust species                      */
+  int32_t precision;          /* rb_precision                                        */
+  double r_in, r_out, z_half;
+  double gamma, GM, cfl;
+  /* Sod annulus: (rho, p, u_r) for r < sod_r0 and r >= sod_r0                        */
+  double sod_r0, sod_left[3], sod_right[3];
+  /* disc                                                                              */
+  double h0, beta_T, rho_mid0, beta_rho;
+  /* column Gaussian vortex of the initial state (amplitude = -Rossby number), and the
+   * relative amplitude of the density noise                                           */
+  double vortex_amp, vortex_r0, vortex_th0, vortex_sig_r, vortex_sig_a, noise_amp;
+  /* dust: Stokes number (t_s = St / Omega_K), dust-to-gas column ratio, H_d / H       */
+  double stokes[4], eps_dust[4], hd_over_h[4];
+} rb_config;
+
+/* Caller-owned device buffers.  Sizes come from rb_query_sizes; pointers must be
+ * 256-byte aligned device addresses that stay valid until rb_destroy. */
+typedef struct {
+  void* state;   /* the deviation E' (gas) / the dust variables, FP64 or FP32         */
+  void* stage;   /* midpoint state of the RK2 step, same layout and type             */
+  void* work;    /* geometry, background, residual tables and reduction partials     */
+  size_t state_bytes, stage_bytes, work_bytes;
+} rb_buffers;
+
+typedef struct {
+  double t;               /* simulated time                                          */
+  int64_t step;           /* completed steps                                         */
+  int32_t flags;          /* bit 0 negative, 1 vacuum, 2 no convergence, 3 stiff    */
+  int32_t first_bad_step; /* step at which a hard error was first seen, or -1        */
+  int64_t first_bad_cell; /* lowest global cell index (k*nr + i)*ntheta + j, or -1   */
+  int64_t fallbacks;      /* face states replaced by the cell-centre state           */
+  int64_t vacuum_faces;   /* Riemann problems that generated vacuum                  */
+  int32_t max_newton;     /* largest Newton iteration count seen                     */
+  int32_t pad;
+  double mass[5];         /* total gas mass, then each dust species                  */
+  double outflow[5];      /* boundary mass outflow rate of the last second stage     */
+  double dt_last;         /* last time step                                          */
+} rb_diag;
+
+typedef struct rb_ctx rb_ctx;
+
+/* Fills the three *_bytes fields for cfg (pointers untouched).  EINVAL on a bad cfg. */
+rb_status rb_query_sizes(const rb_config* cfg, rb_buffers* sizes);
+
+/* Builds the geometry, the stationary flow at cell and face centres (App. A), the
+ * empty-run residual R0 = G(E0) (Sect. 2.8, computed by the step kernel itself) and
+ * the initial state, all on the device.  noise: host array of ncells doubles in
+ * [-1, 1) multiplying noise_amp (NULL: no noise); amp: host array of ncells vortex
+ * amplitudes (NULL: vortex_amp everywhere).  Both are read before the call returns.
+ * stream: hipStream_t (NULL: default stream).  *out receives the context. */
+rb_status rb_init_state(const rb_config* cfg, const rb_buffers* bufs, const double* noise,
+                        const double* amp, void* stream, rb_ctx** out);
+
+/* Advances n RK2 steps (Sect. 2.5) entirely on the device, with no host
+ * synchronisation between steps.  dt_out (host, n entries, may be NULL) receives the
+ * time steps.  Hard errors (ENEGATIVE, ENOCONV, ESTIFF) stop the evolution at the
+ * step where they occur and are sticky until rb_set_fields; EVACUUM is reported after
+ * the n steps complete. */
+rb_status rb_step(rb_ctx* ctx, int n, const rb_dt_policy* policy, double* dt_out);
+
+/* Copies the full conservative state E0 + E' (gas) and the dust variables to host
+ * memory, FP64, in the field layout above; n_doubles must be nfields * ncells. */
+rb_status rb_get_fields(rb_ctx* ctx, double* host_out, size_t n_doubles);
+
+/* Replaces the state from host memory (same layout as rb_get_fields) and clears the
+ * error flags. */
+rb_status rb_set_fields(rb_ctx* ctx, const double* host_in, size_t n_doubles);
+
+/* Writes the spatial operator of the current state to host memory: G(E) - R0 for the
+ * gas (R0 subtracted when balanced) and G for the dust, FP64, field layout above
+ * (Sect. 2.2: V dE/dt = G). */
+rb_status rb_eval_operator(rb_ctx* ctx, double* host_out, size_t n_doubles);
+
+/* Copies the empty-run residual R0 to host memory, [nz][nr][5]. */
+rb_status rb_get_residual(rb_ctx* ctx, double* host_out, size_t n_doubles);
+
+/* CFL time step of the current state (Sect. 2.5), computed on the device. */
+rb_status rb_cfl_dt(rb_ctx* ctx, double* dt);
+
+/* Counters, time, masses (fixed-tree FP64 sums) and the last boundary outflow. */
+rb_status rb_diagnostics(rb_ctx* ctx, rb_diag* out);
+
+/* Kernel timers.  With enable != 0, rb_step brackets every launch of the stage
+ * kernels (gas, dust) and of the reductions with HIP events recorded on the context's
+ * stream and accumulates their elapsed times.  rb_profile_read fills, per kernel kind
+ * (0 gas stage kernel, 1 dust stage kernel, 2 reductions and CFL), the total
+ * milliseconds and the number of launches since profiling was enabled (3 entries
+ * each).  Enabling resets the totals. */
+rb_status rb_profile(rb_ctx* ctx, int enable);
+rb_status rb_profile_read(rb_ctx* ctx, double* total_ms, int64_t* launches);
+
+/* Message describing the last error on ctx; valid until the next call on ctx. */
+const char* rb_last_error(const rb_ctx* ctx);
+
+/* Releases the host-side context (the caller frees its device buffers). */
+void rb_destroy(rb_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ROSSBI_MI355X_H */

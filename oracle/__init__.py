@@ -127,6 +127,8 @@ def lib() -> ctypes.CDLL:
         L.or_tangent.argtypes = [ctypes.POINTER(OrConfig), _D, _D, _D, _D, ctypes.c_int, _D,
                                  ctypes.c_double, ctypes.c_double, ctypes.c_double, _D, _D]
         L.or_threads.restype = ctypes.c_int
+        L.or_count_ops.restype = ctypes.c_double
+        L.or_count_ops.argtypes = [ctypes.POINTER(OrConfig), _D]
         _lib = L
     return _lib
 
@@ -271,3 +273,10 @@ def tangent(cfg: synth.Config, noise, amp, amp_dot, st_dot, dt_list):
                               len(dts), _ptr(dts), synth.CORE_R[0], synth.CORE_R[1], synth.CORE_DTH,
                               _ptr(J), _ptr(dJ))
     return status, J[0], dJ[0]
+
+
+def count_ops(cfg: synth.Config, noise=None) -> float:
+    """Algorithmic FP64 operations per cell of one stage (operator + update)."""
+    s = to_struct(cfg)
+    noise = _f64(noise)
+    return lib().or_count_ops(ctypes.byref(s), _ptr(noise))

@@ -109,6 +109,32 @@ inline Dual operator/(double a, const Dual& b) {
   return Dual(q, -q * b.d / b.v);
 }
 
+/* FP64 operation counter: a double that counts its own arithmetic (+ - * / sqrt pow),
+ * used to state the algorithmic work of the scheme per cell (comparisons are free). */
+struct OpCount { long long n = 0; };
+static OpCount g_ops;
+struct CountD {
+  double v;
+  CountD(double x = 0.0) : v(x) {}
+};
+inline CountD cnt(double x) { ++g_ops.n; return CountD(x); }
+inline CountD operator+(const CountD& a, const CountD& b) { return cnt(a.v + b.v); }
+inline CountD operator-(const CountD& a, const CountD& b) { return cnt(a.v - b.v); }
+inline CountD operator-(const CountD& a) { return CountD(-a.v); }
+inline CountD operator*(const CountD& a, const CountD& b) { return cnt(a.v * b.v); }
+inline CountD operator/(const CountD& a, const CountD& b) { return cnt(a.v / b.v); }
+inline CountD operator+(const CountD& a, double b) { return cnt(a.v + b); }
+inline CountD operator+(double a, const CountD& b) { return cnt(a + b.v); }
+inline CountD operator-(const CountD& a, double b) { return cnt(a.v - b); }
+inline CountD operator-(double a, const CountD& b) { return cnt(a - b.v); }
+inline CountD operator*(const CountD& a, double b) { return cnt(a.v * b); }
+inline CountD operator*(double a, const CountD& b) { return cnt(a * b.v); }
+inline CountD operator/(const CountD& a, double b) { return cnt(a.v / b); }
+inline CountD operator/(double a, const CountD& b) { return cnt(a / b.v); }
+inline double val(const CountD& x) { return x.v; }
+inline CountD sqrt_(const CountD& x) { return cnt(std::sqrt(x.v)); }
+inline CountD pow_(const CountD& x, double y) { return cnt(std::pow(x.v, y)); }
+
 inline double val(double x) { return x; }
 inline double val(const Dual& x) { return x.v; }
 inline double tan_(double) { return 0.0; }
@@ -1171,6 +1197,36 @@ void or_equilibrium(const OrConfig* cfg, double r, double z, double* out) {
   Sim<double> s;
   s.c = *cfg;
   s.equilibrium(r, z, out[0], out[1], out[2]);
+}
+
+/* Algorithmic FP64 operations of one evaluation of the spatial operator G and one
+ * stage update on the initial state, per cell (single thread; + - * / sqrt pow count
+ * one each). */
+double or_count_ops(const OrConfig* cfg, const double* noise) {
+#ifdef _OPENMP
+  int nt = omp_get_max_threads();
+  omp_set_num_threads(1);
+#endif
+  Sim<CountD> s;
+  if (!s.setup(*cfg)) return -1.0;
+  if (s.c.balanced) s.empty_run();
+  s.initial_state(noise, nullptr);
+  g_ops.n = 0;
+  s.evaluate(s.E, s.nd > 0, s.c.balanced != 0, s.Gb);
+  for (int f = 0; f < s.nf; ++f)
+    for (int k = 0; k < s.nz; ++k)
+      for (int i = 0; i < s.nr; ++i) {
+        double cfac = 0.5 * 1e-3 / s.V[i];
+        for (int j = 0; j < s.nth; ++j) {
+          size_t id = f * s.N + s.idx(k, i, j);
+          s.Es[id] = s.E[id] + cfac * s.Gb[id];
+        }
+      }
+  long long n = g_ops.n;
+#ifdef _OPENMP
+  omp_set_num_threads(nt);
+#endif
+  return (double)n / (double)s.N;
 }
 
 /* Tangent-linear run: the whole run with dual numbers.  The amplitude field carries the

@@ -1,0 +1,542 @@
+// Host runtime behind the C ABI of include/rossbi_mi355x.h: validation, work-area
+// layout, the initialisation sequence (tables, empty run, initial state) and the step
+// loop.  Every computation runs in the device kernels of rb_kernels.hip; this file
+// only sequences launches on the caller's stream and moves data at the boundary.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "rb_internal.h"
+
+using namespace rb;
+
+struct rb_ctx {
+  rb_config cfg;
+  Geo g;
+  Layout L;
+  hipStream_t stream;
+  double* state;
+  double* stage;
+  double* work;
+  double t;
+  int64_t step;
+  double dt_last;
+  int hard;       // sticky rb_status of a hard error, 0 if none
+  std::string err;
+  // kernel timers (rb_profile): events bracketing launches within one rb_step chunk
+  int prof = 0;
+  std::vector<hipEvent_t> ev;
+  std::vector<int> ev_kind;
+  size_t ev_used = 0;
+  double prof_ms[3] = {0, 0, 0};
+  int64_t prof_n[3] = {0, 0, 0};
+};
+
+namespace {
+
+size_t up32(size_t x) { return (x + 31) / 32 * 32; }
+
+bool validate(const rb_config* c, std::string* why) {
+  auto bad = [&](const char* m) { if (why) *why = m; return false; };
+  if (!c) return bad("null config");
+  if (c->nr < 3 || c->ntheta < 4 || c->nz < 1) return bad("grid too small (nr >= 3, ntheta >= 4)");
+  if (c->nz == 2 || c->nz == 3) return bad("nz must be 1 (2D) or >= 4");
+  if ((double)c->nr * c->ntheta * c->nz > 4.0e9) return bad("grid too large");
+  if (c->n_dust < 0 || c->n_dust > 4) return bad("n_dust must be 0..4");
+  if (!(c->gamma > 1.0)) return bad("gamma must exceed 1");
+  if (!(c->cfl > 0.0 && c->cfl <= 1.0)) return bad("cfl must be in (0, 1]");
+  if (!(c->r_in > 0.0 && c->r_out > c->r_in)) return bad("need 0 < r_in < r_out");
+  if (c->nz > 1 && !(c->z_half > 0.0)) return bad("z_half must be positive in 3D");
+  if (c->init_kind != RB_INIT_SOD && c->init_kind != RB_INIT_DISC) return bad("unknown init_kind");
+  if (c->init_kind == RB_INIT_DISC && !(c->GM > 0.0)) return bad("disc needs GM > 0");
+  if (c->init_kind == RB_INIT_SOD && c->n_dust > 0) return bad("Sod annulus carries no dust");
+  if (c->n_dust > 0 && !(c->GM > 0.0)) return bad("dust drag needs GM > 0 (t_s = St/Omega_K)");
+  for (int s = 0; s < c->n_dust; ++s)
+    if (!(c->stokes[s] > 0.0) || !(c->hd_over_h[s] > 0.0) || !(c->eps_dust[s] >= 0.0))
+      return bad("dust parameters must be positive");
+  if (c->precision != RB_FP64) return bad("precision not supported by this build");
+  return true;
+}
+
+Layout make_layout(const rb_config& c) {
+  Layout L;
+  const size_t nr = c.nr, nth = c.ntheta, nz = c.nz, nf = 5 + 4 * c.n_dust;
+  const size_t N = nr * nth * nz;
+  L.ntj = (int)((nth + TJ - 1) / TJ);
+  L.nti = (int)((nr + TI - 1) / TI);
+  if (nz == 1) {
+    L.tk = 1;
+  } else {
+    int tk = 2;
+    const char* env = std::getenv("RB_TK");
+    if (env && std::atoi(env) > 0) {
+      tk = std::atoi(env);
+    } else {
+      const int cand[4] = {16, 8, 4, 2};
+      for (int q = 0; q < 4; ++q) {
+        size_t blocks = (size_t)L.ntj * L.nti * ((nz + cand[q] - 1) / cand[q]);
+        if (blocks >= 512 || cand[q] == 2) { tk = cand[q]; break; }
+      }
+    }
+    L.tk = (int)std::min<size_t>(tk, nz);
+  }
+  L.nkc = (int)((nz + L.tk - 1) / L.tk);
+  L.nblocks = L.ntj * L.nti * L.nkc;
+  L.ncfl = (int)std::min<size_t>((N + 255) / 256, 2048);
+  size_t o = 0;
+  auto take = [&](size_t n) { size_t at = o; o += up32(n); return at; };
+  L.ctrl = take((sizeof(Ctrl) + 7) / 8);
+  L.rt = take(nr * RT_N);
+  L.ar = take(nr + 1);
+  L.rco = take((nr + 2) * RC_N);
+  L.rcell = take(nr + 4);
+  L.zc = take(nz);
+  L.bgc = take(nz * nr * 5);
+  L.bgr = take(nz * (nr + 1) * 5);
+  L.bgz = take((nz + 1) * nr * 5);
+  L.r0 = take(nz * nr * 5);
+  L.grav = take(nz * nr * 2);
+  L.ghr = take(4 * nz * nf);
+  L.ghrf = take(2 * nz * 5);
+  L.ghz = take(4 * nr * nf);
+  L.ghzf = take(2 * nr * 5);
+  L.dtlog = take(DTLOG + 2);
+  L.cflp = take(std::max((size_t)L.nblocks * 5, (size_t)L.ncfl));
+  L.outp = take((size_t)L.nblocks * 5);
+  L.red = take(2048 + 16);
+  L.total = o;
+  return L;
+}
+
+Geo make_geo(const rb_config& c) {
+  Geo g;
+  g.nr = c.nr; g.nth = c.ntheta; g.nz = c.nz;
+  g.twod = c.nz == 1;
+  g.nd = c.n_dust;
+  g.nf = 5 + 4 * c.n_dust;
+  g.N = (size_t)c.nr * c.ntheta * c.nz;
+  g.gamma = c.gamma; g.GM = c.GM; g.cfl = c.cfl;
+  for (int s = 0; s < 4; ++s) g.inv_st[s] = s < c.n_dust ? 1.0 / c.stokes[s] : 0.0;
+  return g;
+}
+
+StageArgs base_args(rb_ctx* x) {
+  StageArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.g = x->g;
+  const Layout& L = x->L;
+  double* w = x->work;
+  a.t.rt = w + L.rt; a.t.ar = w + L.ar; a.t.rco = w + L.rco; a.t.bgc = w + L.bgc;
+  a.t.bgr = w + L.bgr; a.t.bgz = w + L.bgz; a.t.r0 = w + L.r0; a.t.grav = w + L.grav;
+  a.t.ghr = w + L.ghr; a.t.ghrf = w + L.ghrf; a.t.ghz = w + L.ghz; a.t.ghzf = w + L.ghzf;
+  a.c.ctrl = reinterpret_cast<Ctrl*>(w + L.ctrl);
+  a.c.dtlog = w + L.dtlog; a.c.cflp = w + L.cflp; a.c.outp = w + L.outp; a.c.r0w = w + L.r0;
+  a.tk = L.tk; a.ntj = L.ntj; a.nti = L.nti; a.nkc = L.nkc;
+  a.dt_idx = -1;
+  return a;
+}
+
+rb_status fail(rb_ctx* x, rb_status s, const std::string& m) {
+  if (x) x->err = m;
+  return s;
+}
+
+rb_status hip_fail(rb_ctx* x, hipError_t e, const char* where) {
+  std::string m = std::string(where) + ": " + hipGetErrorString(e);
+  return fail(x, RB_EDEVICE, m);
+}
+
+#define HIPCHK(x, expr, where)                       \
+  do {                                              \
+    hipError_t e_ = (expr);                         \
+    if (e_ != hipSuccess) return hip_fail(x, e_, where); \
+  } while (0)
+
+rb_status reset_ctrl(rb_ctx* x) {
+  Ctrl c;
+  std::memset(&c, 0, sizeof(c));
+  c.bad_step = -1;
+  c.first_bad = ~0ull;
+  // keep the stopping time computed by the table kernel
+  Ctrl old;
+  HIPCHK(x, hipMemcpyAsync(&old, x->work + x->L.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, x->stream),
+         "read control block");
+  HIPCHK(x, hipStreamSynchronize(x->stream), "sync");
+  c.min_ts = old.min_ts;
+  HIPCHK(x, hipMemcpyAsync(x->work + x->L.ctrl, &c, sizeof(Ctrl), hipMemcpyHostToDevice, x->stream),
+         "write control block");
+  HIPCHK(x, hipStreamSynchronize(x->stream), "sync");
+  return RB_OK;
+}
+
+// event pair around one launch of kernel kind `kind` (no-op unless profiling)
+struct ProfScope {
+  rb_ctx* x;
+  int kind;
+  size_t slot;
+  ProfScope(rb_ctx* x_, int kind_) : x(x_), kind(kind_), slot(0) {
+    if (!x->prof) return;
+    if (x->ev_used + 2 > x->ev.size()) {
+      for (int q = 0; q < 64; ++q) {
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess) return;
+        x->ev.push_back(e);
+      }
+      x->ev_kind.resize(x->ev.size() / 2);
+    }
+    slot = x->ev_used;
+    x->ev_used += 2;
+    x->ev_kind[slot / 2] = kind;
+    hipEventRecord(x->ev[slot], x->stream);
+  }
+  ~ProfScope() {
+    if (x->prof && slot + 1 < x->ev.size()) hipEventRecord(x->ev[slot + 1], x->stream);
+  }
+};
+
+// accumulate the recorded event pairs (stream already synchronised)
+void prof_collect(rb_ctx* x) {
+  if (!x->prof) return;
+  for (size_t p = 0; p + 1 < x->ev_used; p += 2) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, x->ev[p], x->ev[p + 1]) == hipSuccess) {
+      int k = x->ev_kind[p / 2];
+      x->prof_ms[k] += ms;
+      x->prof_n[k] += 1;
+    }
+  }
+  x->ev_used = 0;
+}
+
+hipError_t run_stage(rb_ctx* x, const StageArgs& a) {
+  hipError_t e;
+  {
+    ProfScope ps(x, 0);
+    e = launch_stage_group(a, x->L.nblocks, 0, x->stream);
+  }
+  if (e != hipSuccess || a.gas_only) return e;
+  for (int s = 0; s < x->g.nd; ++s) {
+    ProfScope ps(x, 1);
+    e = launch_stage_group(a, x->L.nblocks, 1 + s, x->stream);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+rb_status status_of_flags(int flags) {
+  if (flags & FL_NEG) return RB_ENEGATIVE;
+  if (flags & FL_NOCONV) return RB_ENOCONV;
+  if (flags & FL_STIFF) return RB_ESTIFF;
+  if (flags & FL_VAC) return RB_EVACUUM;
+  return RB_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+rb_status rb_query_sizes(const rb_config* cfg, rb_buffers* sizes) {
+  if (!cfg || !sizes) return RB_EINVAL;
+  std::string why;
+  if (!validate(cfg, &why)) return RB_EINVAL;
+  const size_t N = (size_t)cfg->nr * cfg->ntheta * cfg->nz;
+  const size_t nf = 5 + 4 * cfg->n_dust;
+  const size_t elem = cfg->precision == RB_FP64 ? 8 : 4;
+  Layout L = make_layout(*cfg);
+  sizes->state_bytes = nf * N * elem;
+  sizes->stage_bytes = nf * N * elem;
+  sizes->work_bytes = L.total * sizeof(double);
+  return RB_OK;
+}
+
+rb_status rb_init_state(const rb_config* cfg, const rb_buffers* bufs, const double* noise,
+                        const double* amp, void* stream, rb_ctx** out) {
+  if (!out) return RB_EINVAL;
+  *out = nullptr;
+  if (!cfg || !bufs) return RB_EINVAL;
+  std::string why;
+  if (!validate(cfg, &why)) {
+    std::fprintf(stderr, "rb_init_state: %s\n", why.c_str());
+    return RB_EINVAL;
+  }
+  rb_buffers need;
+  rb_query_sizes(cfg, &need);
+  if (!bufs->state || !bufs->stage || !bufs->work) return RB_EINVAL;
+  if (bufs->state_bytes < need.state_bytes || bufs->stage_bytes < need.stage_bytes ||
+      bufs->work_bytes < need.work_bytes)
+    return RB_ENOMEM;
+  if (((uintptr_t)bufs->state | (uintptr_t)bufs->stage | (uintptr_t)bufs->work) & 255)
+    return RB_EINVAL;
+  rb_ctx* x = new rb_ctx();
+  x->cfg = *cfg;
+  x->g = make_geo(*cfg);
+  x->L = make_layout(*cfg);
+  x->stream = (hipStream_t)stream;
+  x->state = (double*)bufs->state;
+  x->stage = (double*)bufs->stage;
+  x->work = (double*)bufs->work;
+  x->t = 0.0;
+  x->step = 0;
+  x->dt_last = 0.0;
+  x->hard = 0;
+  auto bail = [&](rb_status s) { delete x; return s; };
+  if (launch_fill(x->work, x->L.total, 0.0, x->stream) != hipSuccess) return bail(RB_EDEVICE);
+  if (reset_ctrl(x) != RB_OK) return bail(RB_EDEVICE);
+
+  InitArgs ia;
+  std::memset(&ia, 0, sizeof(ia));
+  ia.g = x->g;
+  ia.cfg = *cfg;
+  ia.work = x->work;
+  ia.L = x->L;
+  ia.state = x->state;
+  if (launch_tables(ia, x->stream) != hipSuccess) return bail(RB_EDEVICE);
+
+  // empty run (Sect. 2.8): the spatial operator of the stationary flow, by the step
+  // kernel itself, written to the residual table
+  if (cfg->balanced) {
+    if (launch_fill(x->stage, x->g.N * x->g.nf, 0.0, x->stream) != hipSuccess) return bail(RB_EDEVICE);
+    StageArgs a = base_args(x);
+    a.in = x->stage;
+    a.base = x->stage;
+    a.out = nullptr;
+    a.mode = MODE_RESID;
+    a.gas_only = 1;
+    if (launch_stage(a, x->L.nblocks, x->stream) != hipSuccess) return bail(RB_EDEVICE);
+  }
+  // initial state: noise and amplitude fields staged through the stage buffer
+  const size_t N = x->g.N;
+  if (noise) {
+    if (hipMemcpyAsync(x->stage, noise, N * sizeof(double), hipMemcpyHostToDevice, x->stream) !=
+        hipSuccess)
+      return bail(RB_EDEVICE);
+    ia.noise = x->stage;
+  }
+  if (amp) {
+    if (hipMemcpyAsync(x->stage + N, amp, N * sizeof(double), hipMemcpyHostToDevice, x->stream) !=
+        hipSuccess)
+      return bail(RB_EDEVICE);
+    ia.amp = x->stage + N;
+  }
+  if (launch_init_state(ia, x->stream) != hipSuccess) return bail(RB_EDEVICE);
+  if (hipStreamSynchronize(x->stream) != hipSuccess) return bail(RB_EDEVICE);
+  if (hipGetLastError() != hipSuccess) return bail(RB_EDEVICE);
+  *out = x;
+  return RB_OK;
+}
+
+rb_status rb_step(rb_ctx* x, int n, const rb_dt_policy* policy, double* dt_out) {
+  if (!x || !policy || n < 0) return RB_EINVAL;
+  if (x->hard) return fail(x, (rb_status)x->hard, "a hard error is pending; call rb_set_fields");
+  if (policy->kind == RB_DT_FIXED && !(policy->dt > 0.0)) return fail(x, RB_EINVAL, "dt must be > 0");
+  if (policy->kind == RB_DT_LIST && !policy->dt_list) return fail(x, RB_EINVAL, "dt_list is null");
+  if (policy->kind < 0 || policy->kind > 2) return fail(x, RB_EINVAL, "unknown dt policy");
+  const bool cfl = policy->kind == RB_DT_CFL;
+  StageArgs a = base_args(x);
+  double* dtlog = x->work + x->L.dtlog;
+  std::vector<double> hd;
+  int done = 0;
+  while (done < n || (n == 0 && done == 0)) {
+    const int m = std::min(n - done, DTLOG);
+    if (!cfl) {
+      hd.assign(m + 1, policy->dt);
+      if (policy->kind == RB_DT_LIST) {
+        for (int q = 0; q < m; ++q) {
+          hd[q] = policy->dt_list[done + q];
+          if (!(hd[q] > 0.0)) return fail(x, RB_EINVAL, "dt_list entries must be > 0");
+        }
+        hd[m] = m > 0 ? hd[m - 1] : policy->dt;
+      }
+      HIPCHK(x, hipMemcpyAsync(dtlog, hd.data(), (m + 1) * sizeof(double), hipMemcpyHostToDevice,
+                               x->stream), "upload dt");
+    }
+    // start of the chunk: positivity check and CFL of the current state
+    a.step = (int)(x->step);
+    {
+      ProfScope ps(x, 2);
+      HIPCHK(x, launch_cfl(a, x->state, x->L.ncfl, 0, x->stream), "cfl");
+      HIPCHK(x, launch_reduce(a, x->L.ncfl, 0, cfl ? 1 : 0, 0, x->stream), "reduce");
+    }
+    for (int q = 0; q < m; ++q) {
+      a.step = (int)(x->step + q);
+      a.dt_idx = q;
+      a.mode = MODE_UPDATE;
+      a.gas_only = 0;
+      // first stage: E* = E^n + (dt/2V) (G(E^n) - R0)
+      a.in = x->state; a.base = x->state; a.out = x->stage; a.coef = 0.5; a.second = 0;
+      HIPCHK(x, run_stage(x, a), "stage 1");
+      // second stage: E^{n+1} = E^n + (dt/V) (G(E*) - R0), in place
+      a.in = x->stage; a.base = x->state; a.out = x->state; a.coef = 1.0; a.second = 1;
+      HIPCHK(x, run_stage(x, a), "stage 2");
+      {
+        ProfScope ps(x, 2);
+        HIPCHK(x, launch_reduce(a, x->L.nblocks, q + 1, cfl ? 1 : 0, 1, x->stream), "reduce");
+      }
+    }
+    std::vector<double> got(m + 1);
+    HIPCHK(x, hipMemcpyAsync(got.data(), dtlog, (m + 1) * sizeof(double), hipMemcpyDeviceToHost,
+                             x->stream), "read dt");
+    Ctrl c;
+    HIPCHK(x, hipMemcpyAsync(&c, x->work + x->L.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, x->stream),
+           "read control");
+    HIPCHK(x, hipStreamSynchronize(x->stream), "sync");
+    prof_collect(x);
+    int completed = m;
+    if (c.status & FL_HARD) {
+      completed = std::max(0, std::min(m, c.bad_step - (int)x->step));
+    }
+    for (int q = 0; q < completed; ++q) {
+      x->t += got[q];
+      if (dt_out) dt_out[done + q] = got[q];
+    }
+    if (completed > 0) x->dt_last = got[completed - 1];
+    x->step += completed;
+    done += m;
+    if (c.status & FL_HARD) {
+      x->hard = status_of_flags(c.status & FL_HARD);
+      char buf[160];
+      std::snprintf(buf, sizeof(buf), "hard error flags 0x%x at step %d, first bad cell %llu",
+                    c.status, c.bad_step, (unsigned long long)c.first_bad);
+      return fail(x, (rb_status)x->hard, buf);
+    }
+    if (n == 0) break;
+  }
+  Ctrl c;
+  HIPCHK(x, hipMemcpy(&c, x->work + x->L.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost), "read control");
+  if (c.status & FL_VAC) return fail(x, RB_EVACUUM, "vacuum generated in a Riemann problem");
+  return RB_OK;
+}
+
+rb_status rb_get_fields(rb_ctx* x, double* host_out, size_t n_doubles) {
+  if (!x || !host_out) return RB_EINVAL;
+  const size_t N = x->g.N;
+  if (n_doubles != N * x->g.nf) return fail(x, RB_EINVAL, "n_doubles must be nfields * ncells");
+  StageArgs a = base_args(x);
+  for (int f = 0; f < x->g.nf; ++f) {
+    HIPCHK(x, launch_to_full(a, x->state, x->stage, f, x->stream), "to_full");
+    HIPCHK(x, hipMemcpyAsync(host_out + (size_t)f * N, x->stage, N * sizeof(double),
+                             hipMemcpyDeviceToHost, x->stream), "copy out");
+  }
+  HIPCHK(x, hipStreamSynchronize(x->stream), "sync");
+  return RB_OK;
+}
+
+rb_status rb_set_fields(rb_ctx* x, const double* host_in, size_t n_doubles) {
+  if (!x || !host_in) return RB_EINVAL;
+  const size_t N = x->g.N;
+  if (n_doubles != N * x->g.nf) return fail(x, RB_EINVAL, "n_doubles must be nfields * ncells");
+  StageArgs a = base_args(x);
+  for (int f = 0; f < x->g.nf; ++f) {
+    HIPCHK(x, hipMemcpyAsync(x->stage, host_in + (size_t)f * N, N * sizeof(double),
+                             hipMemcpyHostToDevice, x->stream), "copy in");
+    HIPCHK(x, launch_from_full(a, x->stage, x->state, f, x->stream), "from_full");
+  }
+  HIPCHK(x, hipStreamSynchronize(x->stream), "sync");
+  x->hard = 0;
+  return reset_ctrl(x);
+}
+
+rb_status rb_eval_operator(rb_ctx* x, double* host_out, size_t n_doubles) {
+  if (!x || !host_out) return RB_EINVAL;
+  const size_t N = x->g.N;
+  if (n_doubles != N * x->g.nf) return fail(x, RB_EINVAL, "n_doubles must be nfields * ncells");
+  StageArgs a = base_args(x);
+  a.in = x->state; a.base = x->state; a.out = x->stage; a.mode = MODE_OPER; a.gas_only = 0;
+  HIPCHK(x, launch_stage(a, x->L.nblocks, x->stream), "operator");
+  HIPCHK(x, hipMemcpyAsync(host_out, x->stage, N * x->g.nf * sizeof(double), hipMemcpyDeviceToHost,
+                           x->stream), "copy out");
+  HIPCHK(x, hipStreamSynchronize(x->stream), "sync");
+  return RB_OK;
+}
+
+rb_status rb_get_residual(rb_ctx* x, double* host_out, size_t n_doubles) {
+  if (!x || !host_out) return RB_EINVAL;
+  const size_t n = (size_t)x->g.nz * x->g.nr * 5;
+  if (n_doubles != n) return fail(x, RB_EINVAL, "n_doubles must be nz * nr * 5");
+  HIPCHK(x, hipMemcpyAsync(host_out, x->work + x->L.r0, n * sizeof(double), hipMemcpyDeviceToHost,
+                           x->stream), "copy out");
+  HIPCHK(x, hipStreamSynchronize(x->stream), "sync");
+  return RB_OK;
+}
+
+rb_status rb_cfl_dt(rb_ctx* x, double* dt) {
+  if (!x || !dt) return RB_EINVAL;
+  if (x->hard) return fail(x, (rb_status)x->hard, "a hard error is pending");
+  StageArgs a = base_args(x);
+  a.step = (int)x->step;
+  HIPCHK(x, launch_cfl(a, x->state, x->L.ncfl, 0, x->stream), "cfl");
+  HIPCHK(x, launch_reduce(a, x->L.ncfl, DTLOG + 1, 1, 0, x->stream), "reduce");
+  HIPCHK(x, hipMemcpyAsync(dt, x->work + x->L.dtlog + DTLOG + 1, sizeof(double),
+                           hipMemcpyDeviceToHost, x->stream), "copy out");
+  Ctrl c;
+  HIPCHK(x, hipMemcpyAsync(&c, x->work + x->L.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, x->stream),
+         "read control");
+  HIPCHK(x, hipStreamSynchronize(x->stream), "sync");
+  if (c.status & FL_NEG) {
+    x->hard = RB_ENEGATIVE;
+    return fail(x, RB_ENEGATIVE, "negative density or pressure in the state");
+  }
+  return RB_OK;
+}
+
+rb_status rb_diagnostics(rb_ctx* x, rb_diag* out) {
+  if (!x || !out) return RB_EINVAL;
+  std::memset(out, 0, sizeof(*out));
+  StageArgs a = base_args(x);
+  double* red = x->work + x->L.red;
+  const int nb = 2048;
+  for (int s = 0; s <= x->g.nd; ++s) {
+    const int f = s == 0 ? 4 : 5 + 4 * (s - 1) + 3;
+    HIPCHK(x, launch_mass(a, x->state, red, f, nb, x->stream), "mass");
+    HIPCHK(x, launch_sum(red, nb, red + nb + s, x->stream), "sum");
+  }
+  double ms[5] = {0, 0, 0, 0, 0};
+  HIPCHK(x, hipMemcpyAsync(ms, red + nb, (x->g.nd + 1) * sizeof(double), hipMemcpyDeviceToHost,
+                           x->stream), "copy");
+  Ctrl c;
+  HIPCHK(x, hipMemcpyAsync(&c, x->work + x->L.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, x->stream),
+         "read control");
+  HIPCHK(x, hipStreamSynchronize(x->stream), "sync");
+  out->t = x->t;
+  out->step = x->step;
+  out->flags = c.status;
+  out->first_bad_step = c.bad_step;
+  out->first_bad_cell = c.first_bad == ~0ull ? -1 : (int64_t)c.first_bad;
+  out->fallbacks = (int64_t)c.nfall;
+  out->vacuum_faces = (int64_t)c.nvac;
+  out->max_newton = c.maxit;
+  for (int s = 0; s < 5; ++s) {
+    out->mass[s] = ms[s];
+    out->outflow[s] = c.outflow[s];
+  }
+  out->dt_last = x->dt_last;
+  return RB_OK;
+}
+
+rb_status rb_profile(rb_ctx* x, int enable) {
+  if (!x) return RB_EINVAL;
+  x->prof = enable ? 1 : 0;
+  x->ev_used = 0;
+  for (int k = 0; k < 3; ++k) { x->prof_ms[k] = 0.0; x->prof_n[k] = 0; }
+  return RB_OK;
+}
+
+rb_status rb_profile_read(rb_ctx* x, double* total_ms, int64_t* launches) {
+  if (!x || !total_ms || !launches) return RB_EINVAL;
+  for (int k = 0; k < 3; ++k) { total_ms[k] = x->prof_ms[k]; launches[k] = x->prof_n[k]; }
+  return RB_OK;
+}
+
+const char* rb_last_error(const rb_ctx* x) { return x ? x->err.c_str() : "null context"; }
+
+void rb_destroy(rb_ctx* x) {
+  if (!x) return;
+  for (hipEvent_t e : x->ev) hipEventDestroy(e);
+  delete x;
+}
+
+}  // extern "C"

@@ -1,0 +1,130 @@
+// Internal definitions shared by the device kernels and the host runtime of the
+// bi-fluid finite-volume library (work-area layout, kernel argument blocks, flags).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "rossbi_mi355x.h"
+
+namespace rb {
+
+// Stage kernel tile: 64 cells along theta (one wavefront per radial row) x 8 rows in r,
+// marching through a chunk of z planes.
+constexpr int TJ = 64;
+constexpr int TI = 8;
+constexpr int NT = TJ * TI;
+constexpr int MAXF = 21;
+constexpr int DTLOG = 4096;  // device dt log entries per rb_step chunk
+
+enum : int { FL_NEG = 1, FL_VAC = 2, FL_NOCONV = 4, FL_STIFF = 8 };
+constexpr int FL_HARD = FL_NEG | FL_NOCONV | FL_STIFF;
+
+// per-radial-row table entries (interior rows)
+enum { RT_V = 0, RT_INVV, RT_ATH, RT_AZ, RT_INVRC, RT_OMK, RT_MAXA, RT_RC, RT_N };
+// reconstruction coefficients of a cell along r: increment to the upper face is
+// minmod(wpm*dm + wpp*dp, lpm*dm, lpp*dp), to the lower face
+// minmod(wmm*dm + wmp*dp, lmm*dm, lmp*dp), dm/dp the backward/forward differences.
+enum { RC_WPM = 0, RC_WPP, RC_LPM, RC_LPP, RC_WMM, RC_WMP, RC_LMM, RC_LMP, RC_N };
+
+// Device control block at the start of the work area.
+struct Ctrl {
+  int status;
+  int bad_step;
+  int maxit;
+  int pad0;
+  unsigned long long first_bad;
+  unsigned long long nfall;
+  unsigned long long nvac;
+  double min_ts;          // smallest dust stopping time (init)
+  double outflow[5];      // boundary mass outflow of the last second stage
+  double scratch[8];
+};
+
+// Offsets (in doubles) of the tables inside the work area.
+struct Layout {
+  size_t ctrl, rt, ar, rco, rcell, zc, bgc, bgr, bgz, r0, grav, ghr, ghrf, ghz, ghzf;
+  size_t dtlog, cflp, outp, red, total;
+  int nblocks;   // stage-kernel blocks
+  int ntj, nti, nkc, tk;
+  int ncfl;      // blocks of the standalone CFL / conversion kernels
+};
+
+struct Geo {
+  int nr, nth, nz, twod, nd, nf;
+  size_t N;
+  double gamma, GM, cfl;
+  double inv_st[4];
+};
+
+struct Tables {
+  const double* rt;
+  const double* ar;
+  const double* rco;
+  const double* bgc;
+  const double* bgr;
+  const double* bgz;
+  const double* r0;
+  const double* grav;
+  const double* ghr;
+  const double* ghrf;
+  const double* ghz;
+  const double* ghzf;
+};
+
+struct Ctl {
+  Ctrl* ctrl;
+  double* dtlog;
+  double* cflp;
+  double* outp;
+  double* r0w;   // writable residual table (empty run)
+};
+
+enum : int { MODE_UPDATE = 0, MODE_RESID = 1, MODE_OPER = 2 };
+
+struct StageArgs {
+  Geo g;
+  Tables t;
+  Ctl c;
+  const double* in;     // state whose operator is evaluated (stencil source)
+  const double* base;   // E^n, base of the update
+  double* out;          // updated state (or operator output)
+  double coef;          // 1/2 for the first stage, 1 for the second
+  int dt_idx;           // dtlog entry holding this step's dt
+  int mode;
+  int gas_only;         // empty run: gas without drag
+  int second;           // second stage: CFL partials, ledger, checks
+  int step;             // global step index (error reporting)
+  int tk, ntj, nti, nkc;
+};
+
+struct InitArgs {
+  Geo g;
+  rb_config cfg;
+  double* work;
+  Layout L;
+  const double* noise;  // device, may be null
+  const double* amp;    // device, may be null
+  double* state;
+};
+
+// launchers (rb_kernels.hip)
+hipError_t launch_tables(const InitArgs& a, hipStream_t s);
+hipError_t launch_init_state(const InitArgs& a, hipStream_t s);
+hipError_t launch_stage(const StageArgs& a, int blocks, hipStream_t s);
+// one group of a stage: 0 the gas, 1 + s dust species s
+hipError_t launch_stage_group(const StageArgs& a, int blocks, int group, hipStream_t s);
+hipError_t launch_cfl(const StageArgs& a, const double* state, int blocks, int dt_idx, hipStream_t s);
+hipError_t launch_reduce(const StageArgs& a, int nparts, int dt_idx_next, int want_dt,
+                         int want_ledger, hipStream_t s);
+hipError_t launch_fill(double* p, size_t n, double v, hipStream_t s);
+hipError_t launch_to_full(const StageArgs& a, const double* state, double* out, int f,
+                          hipStream_t s);
+hipError_t launch_from_full(const StageArgs& a, const double* in, double* state, int f,
+                            hipStream_t s);
+hipError_t launch_mass(const StageArgs& a, const double* state, double* partials, int f,
+                       int blocks, hipStream_t s);
+hipError_t launch_sum(const double* partials, int n, double* out, hipStream_t s);
+
+}  // namespace rb

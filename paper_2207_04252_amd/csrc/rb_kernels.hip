@@ -1,0 +1,1309 @@
+// Device kernels of the bi-fluid finite-volume library for gfx950 (MI355X).
+//
+// One RK2 stage is one launch of k_stage: a workgroup owns a 64 (theta) x 8 (r) tile of
+// cells and marches through a chunk of z planes.  Each z plane of the tile, with a
+// two-cell halo, is staged in LDS; every thread solves the Riemann problems at the upper
+// theta and r faces of its own cell (the tile's lower-edge faces are solved by the first
+// 72 threads), exchanges the fluxes through LDS, and keeps the z direction in registers
+// (a three-plane ring of the cell's column and the flux of the face below).  Fluxes,
+// divergence, sources, drag and the update are fused: the state is read once per
+// stage (plus the L2-resident halo) and written once.
+#include <math.h>
+
+#include "rb_internal.h"
+
+namespace rb {
+
+// ------------------------------------------------------------------------------------
+// small helpers
+
+__device__ __forceinline__ double minmod3(double x, double y, double z) {
+  if (x > 0.0 && y > 0.0 && z > 0.0) return fmin(x, fmin(y, z));
+  if (x < 0.0 && y < 0.0 && z < 0.0) return fmax(x, fmax(y, z));
+  return 0.0;
+}
+
+// Uniform direction (index coordinates): the three-point parabola gives the upper-face
+// increment (dm + 3 dp)/8 and the lower-face increment -(3 dm + dp)/8, limited by the
+// one-sided differences (Sect. 2.7).  Written so that mirrored data give exactly
+// opposite increments.
+__device__ __forceinline__ double inc_up_u(double em, double e0, double ep) {
+  double dm = e0 - em, dp = ep - e0;
+  return minmod3(fma(3.0, dp, dm) * 0.125, dm, dp);
+}
+__device__ __forceinline__ double inc_lo_u(double em, double e0, double ep) {
+  double dm = e0 - em, dp = ep - e0;
+  return minmod3(-(fma(3.0, dm, dp) * 0.125), -dm, -dp);
+}
+// Non-uniform r: precomputed parabola weights and limiter bounds of the cell.
+__device__ __forceinline__ double inc_up_c(double em, double e0, double ep, const double* co) {
+  double dm = e0 - em, dp = ep - e0;
+  return minmod3(fma(co[RC_WPP], dp, co[RC_WPM] * dm), co[RC_LPM] * dm, co[RC_LPP] * dp);
+}
+__device__ __forceinline__ double inc_lo_c(double em, double e0, double ep, const double* co) {
+  double dm = e0 - em, dp = ep - e0;
+  return minmod3(fma(co[RC_WMP], dp, co[RC_WMM] * dm), co[RC_LMM] * dm, co[RC_LMP] * dp);
+}
+
+// x^(-1/7) for x > 0: FP32 hardware log2/exp2 seed, then Newton on z^-7 = x written as
+// z <- z + (z/7)(1 - x z^7) (quadratic convergence, three steps reach FP64 accuracy;
+// x = 1 is a fixed point).
+__device__ __forceinline__ double inv_root7(double x) {
+  if (x == 1.0) return 1.0;
+  float xf = fminf(fmaxf((float)x, 1e-30f), 1e30f);
+  double z = (double)__builtin_amdgcn_exp2f(-0.142857142857142857f * __builtin_amdgcn_logf(xf));
+  const double k7 = 1.0 / 7.0;
+#pragma unroll
+  for (int it = 0; it < 3; ++it) {
+    double z2 = z * z;
+    double z3 = z2 * z;
+    double z7 = z3 * z3 * z;
+    z = fma(z * k7, fma(-x, z7, 1.0), z);
+  }
+  return z;
+}
+
+struct GasC {
+  double g, gm1, inv_gm1, g2m1, gm1_2g, gp1_2g, kshock, a2, half_gm1;
+};
+
+__device__ __forceinline__ GasC gas_consts(double g) {
+  GasC c;
+  c.g = g;
+  c.gm1 = g - 1.0;
+  c.inv_gm1 = 1.0 / (g - 1.0);
+  c.g2m1 = 2.0 / (g - 1.0);
+  c.gm1_2g = (g - 1.0) / (2.0 * g);
+  c.gp1_2g = (g + 1.0) / (2.0 * g);
+  c.kshock = (g - 1.0) / (g + 1.0);
+  c.a2 = 2.0 / (g + 1.0);
+  c.half_gm1 = 0.5 * (g - 1.0);
+  return c;
+}
+
+// Powers of x = p/p_K needed by the exact solver: x^((g-1)/2g), x^(-(g+1)/2g), x^(1/g).
+// With g = 7/5 they are x^(1/7), x^(-6/7), x^(5/7), all from one x^(-1/7).
+template <bool G75> struct Pow3 {
+  double p17, pm67, p57;
+  __device__ __forceinline__ Pow3(double x, const GasC& c) {
+    if (G75) {
+      double z = inv_root7(x);
+      double z2 = z * z;
+      double z6 = z2 * z2 * z2;
+      p17 = x * z6;
+      pm67 = z6;
+      p57 = x * z2;
+    } else {
+      p17 = pow(x, c.gm1_2g);
+      pm67 = pow(x, -c.gp1_2g);
+      p57 = pow(x, 1.0 / c.g);
+    }
+  }
+};
+
+template <bool G75>
+__device__ __forceinline__ double ipow_fan_rho(double ratio, const GasC& c) {
+  if (G75) { double r2 = ratio * ratio; return r2 * r2 * ratio; }
+  return pow(ratio, c.g2m1);
+}
+template <bool G75>
+__device__ __forceinline__ double ipow_fan_p(double ratio, const GasC& c) {
+  if (G75) { double r2 = ratio * ratio; double r3 = r2 * ratio; return r3 * r3 * ratio; }
+  return pow(ratio, 2.0 * c.g / (c.g - 1.0));
+}
+
+// One side of the pressure function of the exact solver (Sect. 2.6) and its derivative.
+template <bool G75>
+__device__ __forceinline__ void pfun(double p, double rK, double pK, double cK, const GasC& c,
+                                     double& f, double& df) {
+  if (p > pK) {
+    double A = c.a2 / rK;
+    double B = c.kshock * pK;
+    double q = sqrt(A / (p + B));
+    f = (p - pK) * q;
+    df = q * (1.0 - 0.5 * (p - pK) / (B + p));
+  } else {
+    Pow3<G75> w(p / pK, c);
+    f = c.g2m1 * cK * (w.p17 - 1.0);
+    df = w.pm67 / (rK * cK);
+  }
+}
+
+struct TStat {
+  int fall, vac, maxit, noconv;
+};
+
+// Exact Riemann problem of the ideal gas sampled at x/t = 0 (Sect. 2.6): Newton on p*
+// from the primitive-variable guess (relative change <= 1e-12, at most 50 iterations),
+// star velocity, then the wave pattern at x/t = 0; tangential velocities come from the
+// side of the contact.  Output: mass, normal momentum, two tangential momenta, energy.
+template <bool G75>
+__device__ void gas_riemann(const GasC& c, double rL, double uL, double aL, double bL, double pL,
+                            double rR, double uR, double aR, double bR, double pR, double fl[5],
+                            TStat& st) {
+  double cL = sqrt(c.g * pL / rL);
+  double cR = sqrt(c.g * pR / rR);
+  double du = uR - uL;
+  double rho, un, t1, t2, p;
+  if (c.g2m1 * (cL + cR) <= du) {
+    // vacuum between two rarefactions
+    st.vac++;
+    double sHL = uL - cL, sSL = uL + c.g2m1 * cL, sSR = uR - c.g2m1 * cR, sHR = uR + cR;
+    if (0.0 <= sHL) { rho = rL; un = uL; t1 = aL; t2 = bL; p = pL; }
+    else if (0.0 < sSL) {
+      double cc = c.a2 * (cL + c.half_gm1 * uL);
+      double ratio = cc / cL;
+      rho = rL * ipow_fan_rho<G75>(ratio, c); un = cc; p = pL * ipow_fan_p<G75>(ratio, c);
+      t1 = aL; t2 = bL;
+    } else if (0.0 <= sSR) { rho = 0.0; un = 0.0; t1 = 0.0; t2 = 0.0; p = 0.0; }
+    else if (0.0 < sHR) {
+      double cc = c.a2 * (cR - c.half_gm1 * uR);
+      double ratio = cc / cR;
+      rho = rR * ipow_fan_rho<G75>(ratio, c); un = -cc; p = pR * ipow_fan_p<G75>(ratio, c);
+      t1 = aR; t2 = bR;
+    } else { rho = rR; un = uR; t1 = aR; t2 = bR; p = pR; }
+  } else {
+    double ppv = 0.5 * (pL + pR) - 0.125 * du * (rL + rR) * (cL + cR);
+    double ps = fmax(ppv, 1e-8 * fmin(pL, pR));
+    int it = 0;
+    bool conv = false;
+    while (it < 50) {
+      ++it;
+      double fL, dL, fR, dR;
+      pfun<G75>(ps, rL, pL, cL, c, fL, dL);
+      pfun<G75>(ps, rR, pR, cR, c, fR, dR);
+      double pn = ps - (fL + fR + du) / (dL + dR);
+      if (pn < 1e-8 * ps) pn = 1e-8 * ps;
+      double ch = 2.0 * fabs(pn - ps) / (pn + ps);
+      ps = pn;
+      if (ch <= 1e-12) { conv = true; break; }
+    }
+    st.maxit = max(st.maxit, it);
+    if (!conv) st.noconv = 1;
+    double fL, dL, fR, dR;
+    pfun<G75>(ps, rL, pL, cL, c, fL, dL);
+    pfun<G75>(ps, rR, pR, cR, c, fR, dR);
+    double us = 0.5 * (uL + uR) + 0.5 * (fR - fL);
+    p = ps;
+    if (0.0 <= us) {
+      t1 = aL; t2 = bL;
+      if (ps > pL) {
+        double q = ps / pL;
+        double sL = uL - cL * sqrt(c.gp1_2g * q + c.gm1_2g);
+        if (0.0 <= sL) { rho = rL; un = uL; p = pL; }
+        else { rho = rL * (q + c.kshock) / (c.kshock * q + 1.0); un = us; }
+      } else {
+        double sHL = uL - cL;
+        if (0.0 <= sHL) { rho = rL; un = uL; p = pL; }
+        else {
+          Pow3<G75> w(ps / pL, c);
+          double sTL = us - cL * w.p17;
+          if (0.0 > sTL) { rho = rL * w.p57; un = us; }
+          else {
+            double cc = c.a2 * (cL + c.half_gm1 * uL);
+            double ratio = cc / cL;
+            rho = rL * ipow_fan_rho<G75>(ratio, c); un = cc; p = pL * ipow_fan_p<G75>(ratio, c);
+          }
+        }
+      }
+    } else {
+      t1 = aR; t2 = bR;
+      if (ps > pR) {
+        double q = ps / pR;
+        double sR = uR + cR * sqrt(c.gp1_2g * q + c.gm1_2g);
+        if (0.0 >= sR) { rho = rR; un = uR; p = pR; }
+        else { rho = rR * (q + c.kshock) / (c.kshock * q + 1.0); un = us; }
+      } else {
+        double sHR = uR + cR;
+        if (0.0 >= sHR) { rho = rR; un = uR; p = pR; }
+        else {
+          Pow3<G75> w(ps / pR, c);
+          double sTR = us + cR * w.p17;
+          if (0.0 <= sTR) { rho = rR * w.p57; un = us; }
+          else {
+            double cc = c.a2 * (cR - c.half_gm1 * uR);
+            double ratio = cc / cR;
+            rho = rR * ipow_fan_rho<G75>(ratio, c); un = -cc; p = pR * ipow_fan_p<G75>(ratio, c);
+          }
+        }
+      }
+    }
+  }
+  double en = p * c.inv_gm1 + 0.5 * rho * (un * un + t1 * t1 + t2 * t2);
+  double m = rho * un;
+  fl[0] = m;
+  fl[1] = m * un + p;
+  fl[2] = m * t1;
+  fl[3] = m * t2;
+  fl[4] = (en + p) * un;
+}
+
+// Exact pressureless Riemann problem at x/t = 0 (Sect. 2.9): diverging or equal streams
+// leave vacuum between them (upwind state or zero flux); converging streams form a
+// delta shock of speed (sqrt(rho_L) u_L + sqrt(rho_R) u_R)/(sqrt(rho_L) + sqrt(rho_R)),
+// the flux being the upwind one and the mean of both at a standing shock.  The sign
+// of the shock speed is formed without contraction so that mirrored states give zero.
+__device__ void dust_riemann(double rL, double uL, double aL, double bL, double rR, double uR,
+                             double aR, double bR, double fl[4]) {
+#pragma clang fp contract(off)
+  fl[0] = 0.0; fl[1] = 0.0; fl[2] = 0.0; fl[3] = 0.0;
+  if (!(rL > 0.0)) { rL = 0.0; uL = 0.0; aL = 0.0; bL = 0.0; }
+  if (!(rR > 0.0)) { rR = 0.0; uR = 0.0; aR = 0.0; bR = 0.0; }
+  if (rL + rR == 0.0) return;
+  int side;  // -1 left, +1 right, 0 mean
+  if (uL <= uR) {
+    if (uL > 0.0) side = -1;
+    else if (uR < 0.0) side = 1;
+    else return;
+  } else {
+    double xa = sqrt(rL) * uL;
+    double xb = sqrt(rR) * uR;
+    double num = xa + xb;
+    side = num > 0.0 ? -1 : (num < 0.0 ? 1 : 0);
+  }
+  double mL = rL * uL, mR = rR * uR;
+  if (side < 0) { fl[0] = mL; fl[1] = mL * uL; fl[2] = mL * aL; fl[3] = mL * bL; }
+  else if (side > 0) { fl[0] = mR; fl[1] = mR * uR; fl[2] = mR * aR; fl[3] = mR * bR; }
+  else {
+    fl[0] = 0.5 * (mL + mR);
+    fl[1] = 0.5 * (mL * uL + mR * uR);
+    fl[2] = 0.5 * (mL * aL + mR * aR);
+    fl[3] = 0.5 * (mL * bL + mR * bR);
+  }
+}
+
+// normal / tangential velocity slots of direction DIR (0 r, 1 theta, 2 z)
+template <int DIR> struct Dirs {
+  static constexpr int n = DIR;
+  static constexpr int t1 = DIR == 0 ? 1 : 0;
+  static constexpr int t2 = DIR == 2 ? 1 : 2;
+};
+
+struct Prim5 {
+  double rho, un, t1, t2, p;
+};
+
+template <int DIR>
+__device__ __forceinline__ Prim5 gas_prim(const double q[5], double gm1) {
+  Prim5 w;
+  double inv = 1.0 / q[4];
+  double u = q[0] * inv, v = q[1] * inv, z = q[2] * inv;
+  w.rho = q[4];
+  w.p = gm1 * (q[3] - 0.5 * (q[0] * u + q[1] * v + q[2] * z));
+  double vel[3] = {u, v, z};
+  w.un = vel[Dirs<DIR>::n];
+  w.t1 = vel[Dirs<DIR>::t1];
+  w.t2 = vel[Dirs<DIR>::t2];
+  return w;
+}
+
+// Reconstructed gas face states (Sect. 2.7: E0 at the face + E' + limited parabola
+// increment), positivity fallback to the cell-centre state, exact Riemann problem,
+// F* = F(E*) in field order.  Cells A, B | C, D along DIR; the face lies between B and C.
+template <int DIR, bool G75>
+__device__ __forceinline__ void gas_face(const GasC& c, const double* eA, const double* eB,
+                                         const double* eC, const double* eD, const double* coB,
+                                         const double* coC, const double* bgf, const double* cenB,
+                                         double sB, const double* cenC, double sC, double F[5],
+                                         TStat& st) {
+  double qL[5], qR[5];
+#pragma unroll
+  for (int f = 0; f < 5; ++f) {
+    double iB, iC;
+    if (DIR == 0) {
+      iB = inc_up_c(eA[f], eB[f], eC[f], coB);
+      iC = inc_lo_c(eB[f], eC[f], eD[f], coC);
+    } else {
+      iB = inc_up_u(eA[f], eB[f], eC[f]);
+      iC = inc_lo_u(eB[f], eC[f], eD[f]);
+    }
+    qL[f] = bgf[f] + (eB[f] + iB);
+    qR[f] = bgf[f] + (eC[f] + iC);
+  }
+  Prim5 L = gas_prim<DIR>(qL, c.gm1);
+  Prim5 R = gas_prim<DIR>(qR, c.gm1);
+  if (!(L.rho > 0.0 && L.p > 0.0)) {
+#pragma unroll
+    for (int f = 0; f < 5; ++f) qL[f] = cenB[f] + sB * eB[f];
+    L = gas_prim<DIR>(qL, c.gm1);
+    st.fall++;
+  }
+  if (!(R.rho > 0.0 && R.p > 0.0)) {
+#pragma unroll
+    for (int f = 0; f < 5; ++f) qR[f] = cenC[f] + sC * eC[f];
+    R = gas_prim<DIR>(qR, c.gm1);
+    st.fall++;
+  }
+  double fl[5];
+  gas_riemann<G75>(c, L.rho, L.un, L.t1, L.t2, L.p, R.rho, R.un, R.t1, R.t2, R.p, fl, st);
+  F[4] = fl[0];
+  F[Dirs<DIR>::n] = fl[1];
+  F[Dirs<DIR>::t1] = fl[2];
+  F[Dirs<DIR>::t2] = fl[3];
+  F[3] = fl[4];
+}
+
+// Dust face: the dust variables are reconstructed whole (no stationary reference);
+// a face density below zero falls back to the cell-centre state.
+template <int DIR>
+__device__ __forceinline__ void dust_face(const double* eA, const double* eB, const double* eC,
+                                          const double* eD, const double* coB, const double* coC,
+                                          double F[4], TStat& st) {
+  double qL[4], qR[4];
+#pragma unroll
+  for (int f = 0; f < 4; ++f) {
+    double iB, iC;
+    if (DIR == 0) {
+      iB = inc_up_c(eA[f], eB[f], eC[f], coB);
+      iC = inc_lo_c(eB[f], eC[f], eD[f], coC);
+    } else {
+      iB = inc_up_u(eA[f], eB[f], eC[f]);
+      iC = inc_lo_u(eB[f], eC[f], eD[f]);
+    }
+    qL[f] = eB[f] + iB;
+    qR[f] = eC[f] + iC;
+  }
+  if (qL[3] < 0.0) {
+#pragma unroll
+    for (int f = 0; f < 4; ++f) qL[f] = eB[f];
+    st.fall++;
+  }
+  if (qR[3] < 0.0) {
+#pragma unroll
+    for (int f = 0; f < 4; ++f) qR[f] = eC[f];
+    st.fall++;
+  }
+  double vL[3] = {0.0, 0.0, 0.0}, vR[3] = {0.0, 0.0, 0.0};
+  if (qL[3] > 0.0) {
+    double inv = 1.0 / qL[3];
+    vL[0] = qL[0] * inv; vL[1] = qL[1] * inv; vL[2] = qL[2] * inv;
+  }
+  if (qR[3] > 0.0) {
+    double inv = 1.0 / qR[3];
+    vR[0] = qR[0] * inv; vR[1] = qR[1] * inv; vR[2] = qR[2] * inv;
+  }
+  double fl[4];
+  dust_riemann(qL[3], vL[Dirs<DIR>::n], vL[Dirs<DIR>::t1], vL[Dirs<DIR>::t2], qR[3],
+               vR[Dirs<DIR>::n], vR[Dirs<DIR>::t1], vR[Dirs<DIR>::t2], fl);
+  F[3] = fl[0];
+  F[Dirs<DIR>::n] = fl[1];
+  F[Dirs<DIR>::t1] = fl[2];
+  F[Dirs<DIR>::t2] = fl[3];
+}
+
+// ------------------------------------------------------------------------------------
+// state access with ghost cells (Sect. 2.4): r and z ghosts come from tables, theta wraps
+
+__device__ __forceinline__ double fetch(const StageArgs& a, const double* st, int f, int k, int i,
+                                        int j) {
+  const Geo& g = a.g;
+  if (k < 0 || k >= g.nz) {
+    int side = k < 0 ? 0 : 1;
+    int layer = min(k < 0 ? -1 - k : k - g.nz, 1);
+    int ii = min(max(i, 0), g.nr - 1);
+    return a.t.ghz[((size_t)(side * 2 + layer) * g.nr + ii) * g.nf + f];
+  }
+  if (i < 0 || i >= g.nr) {
+    int side = i < 0 ? 0 : 1;
+    int layer = min(i < 0 ? -1 - i : i - g.nr, 1);
+    return a.t.ghr[((size_t)(side * 2 + layer) * g.nz + k) * g.nf + f];
+  }
+  return st[(size_t)f * g.N + ((size_t)k * g.nr + i) * g.nth + j];
+}
+
+// centre state used by the gas fallback: E0(centre) + E' for interior cells (scale 1),
+// the ghost's full state (scale 0) otherwise
+__device__ __forceinline__ const double* centre_ptr(const StageArgs& a, int k, int i, double& s) {
+  const Geo& g = a.g;
+  if (k < 0 || k >= g.nz) {
+    s = 0.0;
+    int ii = min(max(i, 0), g.nr - 1);
+    return a.t.ghzf + ((size_t)(k < 0 ? 0 : 1) * g.nr + ii) * 5;
+  }
+  if (i < 0 || i >= g.nr) {
+    s = 0.0;
+    return a.t.ghrf + ((size_t)(i < 0 ? 0 : 1) * g.nz + k) * 5;
+  }
+  s = 1.0;
+  return a.t.bgc + ((size_t)k * g.nr + i) * 5;
+}
+
+__device__ __forceinline__ const double* rco_ptr(const StageArgs& a, int i) {
+  int c = min(max(i, -1), a.g.nr);
+  return a.t.rco + (size_t)(c + 1) * RC_N;
+}
+
+__device__ __forceinline__ double wave_min(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o, 64));
+  return v;
+}
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+__device__ __forceinline__ int wave_isum(int v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+__device__ __forceinline__ int wave_imax(int v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
+// XCD-aware tile order: workgroup b is dispatched to XCD b % 8; give every XCD a
+// contiguous range of tiles so that halo re-reads hit its own L2.
+__device__ __forceinline__ int xcd_tile(int b, int nblk) {
+  int q = nblk >> 3, rem = nblk & 7, x = b & 7;
+  return x * q + min(x, rem) + (b >> 3);
+}
+
+// ------------------------------------------------------------------------------------
+// the stage kernels: one launch per group of fields (the gas; each dust species).  The
+// groups interact only through the cell-local drag, which each kernel evaluates from
+// the other group's centre state of the same stage input.
+
+template <bool GAS, int ND, bool G75>
+__global__ void __launch_bounds__(NT) k_march(StageArgs a, int species) {
+  constexpr int NG = GAS ? 5 : 4;
+  // a hard error stops the evolution; the flag is read once and broadcast so that the
+  // whole workgroup takes the same branch (other workgroups may set it meanwhile)
+  __shared__ int s_stop;
+  if (threadIdx.x == 0) s_stop = __atomic_load_n(&a.c.ctrl->status, __ATOMIC_RELAXED);
+  __syncthreads();
+  if (s_stop & FL_HARD) return;
+  __shared__ double s_pl[NG][TI + 4][TJ + 4];
+  __shared__ double s_ft[NG][TI][TJ + 1];
+  __shared__ double s_fr[NG][TI + 1][TJ];
+  __shared__ double s_red[NT / 64][2];
+
+  const Geo& g = a.g;
+  const GasC gc = gas_consts(g.gamma);
+  const int F0 = GAS ? 0 : 5 + 4 * species;
+  const int slot = GAS ? 0 : 1 + species;
+  const int tile = xcd_tile(blockIdx.x, gridDim.x);
+  const int tjb = tile % a.ntj;
+  const int tib = (tile / a.ntj) % a.nti;
+  const int kcb = tile / (a.ntj * a.nti);
+  const int tid = threadIdx.x, tj = tid & (TJ - 1), ti = tid / TJ;
+  const int j0 = tjb * TJ, i0 = tib * TI;
+  const int k0 = kcb * a.tk, k1 = min(g.nz, k0 + a.tk);
+  const int jg = j0 + tj;
+  const int jw = jg % g.nth;
+  const int ig = i0 + ti;
+  const bool act = jg < g.nth && ig < g.nr;
+  const int igc = min(ig, g.nr - 1);
+  const bool drag = !a.gas_only && ND > 0;
+  const double* in = a.in;
+  const double dt = a.dt_idx >= 0 ? a.c.dtlog[a.dt_idx] : 0.0;
+
+  TStat st = {0, 0, 0, 0};
+  double dtmin = 1e300;
+  double ledger = 0.0;
+
+  const double* rt = a.t.rt + (size_t)igc * RT_N;
+  const double Vc = rt[RT_V], invV = rt[RT_INVV], Ath = rt[RT_ATH], Az = rt[RT_AZ];
+  const double invrc = rt[RT_INVRC], omk = rt[RT_OMK], maxA = rt[RT_MAXA];
+  const double Arlo = a.t.ar[igc], Arhi = a.t.ar[igc + 1];
+
+  // z ring of the thread's column: e_{k-1}, e_k, e_{k+1}, e_{k+2}; fluxes below/above k
+  double rm[NG], r0[NG], rp[NG], rn[NG], fzlo[NG], fzhi[NG];
+  const bool twod = g.twod != 0;
+  if (!twod) {
+    double e2[NG];
+#pragma unroll
+    for (int f = 0; f < NG; ++f) {
+      e2[f] = fetch(a, in, F0 + f, k0 - 2, ig, jw);
+      rm[f] = fetch(a, in, F0 + f, k0 - 1, ig, jw);
+      r0[f] = fetch(a, in, F0 + f, k0, ig, jw);
+      rp[f] = fetch(a, in, F0 + f, k0 + 1, ig, jw);
+    }
+    if (GAS) {
+      double sB, sC;
+      const double* cB = centre_ptr(a, k0 - 1, igc, sB);
+      const double* cC = centre_ptr(a, k0, igc, sC);
+      const double* bgf = a.t.bgz + ((size_t)k0 * g.nr + igc) * 5;
+      gas_face<2, G75>(gc, e2, rm, r0, rp, nullptr, nullptr, bgf, cB, sB, cC, sC, fzlo, st);
+    } else {
+      dust_face<2>(e2, rm, r0, rp, nullptr, nullptr, fzlo, st);
+    }
+    if (a.second && k0 == 0 && act) ledger -= Az * fzlo[NG - 1];
+  } else {
+#pragma unroll
+    for (int f = 0; f < NG; ++f) {
+      r0[f] = fetch(a, in, F0 + f, 0, ig, jw);
+      rm[f] = 0.0; rp[f] = 0.0; rn[f] = 0.0; fzlo[f] = 0.0; fzhi[f] = 0.0;
+    }
+  }
+
+  for (int k = k0; k < k1; ++k) {
+    if (!twod) {
+#pragma unroll
+      for (int f = 0; f < NG; ++f) rn[f] = fetch(a, in, F0 + f, k + 2, ig, jw);
+    }
+    // ---- stage the plane (with halo) in LDS
+#pragma unroll
+    for (int f = 0; f < NG; ++f) s_pl[f][ti + 2][tj + 2] = r0[f];
+    for (int h = tid; h < (TI + 4) * (TJ + 4); h += NT) {
+      int rr = h / (TJ + 4), cc = h % (TJ + 4);
+      if (rr >= 2 && rr < TI + 2 && cc >= 2 && cc < TJ + 2) continue;
+      int ii = i0 + rr - 2;
+      int jj = (j0 + cc - 2 + g.nth) % g.nth;
+#pragma unroll
+      for (int f = 0; f < NG; ++f) s_pl[f][rr][cc] = fetch(a, in, F0 + f, k, ii, jj);
+    }
+    __syncthreads();
+    // ---- theta face j+1/2 and r face i+1/2 of this cell
+    {
+      double eA[NG], eB[NG], eC[NG], eD[NG], F[NG];
+#pragma unroll
+      for (int f = 0; f < NG; ++f) {
+        eA[f] = s_pl[f][ti + 2][tj + 1]; eB[f] = s_pl[f][ti + 2][tj + 2];
+        eC[f] = s_pl[f][ti + 2][tj + 3]; eD[f] = s_pl[f][ti + 2][tj + 4];
+      }
+      if (GAS) {
+        const double* bgf = a.t.bgc + ((size_t)k * g.nr + igc) * 5;
+        gas_face<1, G75>(gc, eA, eB, eC, eD, nullptr, nullptr, bgf, bgf, 1.0, bgf, 1.0, F, st);
+      } else {
+        dust_face<1>(eA, eB, eC, eD, nullptr, nullptr, F, st);
+      }
+#pragma unroll
+      for (int f = 0; f < NG; ++f) s_ft[f][ti][tj + 1] = F[f];
+#pragma unroll
+      for (int f = 0; f < NG; ++f) {
+        eA[f] = s_pl[f][ti + 1][tj + 2]; eB[f] = s_pl[f][ti + 2][tj + 2];
+        eC[f] = s_pl[f][ti + 3][tj + 2]; eD[f] = s_pl[f][ti + 4][tj + 2];
+      }
+      if (GAS) {
+        const int ifc = min(ig + 1, g.nr);
+        const double* bgf = a.t.bgr + ((size_t)k * (g.nr + 1) + ifc) * 5;
+        double sB, sC;
+        const double* cB = centre_ptr(a, k, min(ig, g.nr), sB);
+        const double* cC = centre_ptr(a, k, min(ig + 1, g.nr), sC);
+        gas_face<0, G75>(gc, eA, eB, eC, eD, rco_ptr(a, ig), rco_ptr(a, ig + 1), bgf, cB, sB, cC,
+                         sC, F, st);
+      } else {
+        dust_face<0>(eA, eB, eC, eD, rco_ptr(a, ig), rco_ptr(a, ig + 1), F, st);
+      }
+#pragma unroll
+      for (int f = 0; f < NG; ++f) s_fr[f][ti + 1][tj] = F[f];
+      if (a.second && act && ig == g.nr - 1) ledger += Arhi * F[NG - 1];
+    }
+    // ---- lower-edge faces of the tile: r face i0-1/2 (threads 0..63) and theta face
+    //      j0-1/2 of each row (threads 64..71)
+    if (tid < TJ) {
+      double eA[NG], eB[NG], eC[NG], eD[NG], F[NG];
+      const int col = tid;
+#pragma unroll
+      for (int f = 0; f < NG; ++f) {
+        eA[f] = s_pl[f][0][col + 2]; eB[f] = s_pl[f][1][col + 2];
+        eC[f] = s_pl[f][2][col + 2]; eD[f] = s_pl[f][3][col + 2];
+      }
+      if (GAS) {
+        const double* bgf = a.t.bgr + ((size_t)k * (g.nr + 1) + i0) * 5;
+        double sB, sC;
+        const double* cB = centre_ptr(a, k, i0 - 1, sB);
+        const double* cC = centre_ptr(a, k, i0, sC);
+        gas_face<0, G75>(gc, eA, eB, eC, eD, rco_ptr(a, i0 - 1), rco_ptr(a, i0), bgf, cB, sB, cC,
+                         sC, F, st);
+      } else {
+        dust_face<0>(eA, eB, eC, eD, rco_ptr(a, i0 - 1), rco_ptr(a, i0), F, st);
+      }
+#pragma unroll
+      for (int f = 0; f < NG; ++f) s_fr[f][0][col] = F[f];
+      if (a.second && i0 == 0 && j0 + col < g.nth) ledger -= a.t.ar[0] * F[NG - 1];
+    } else if (tid < TJ + TI) {
+      double eA[NG], eB[NG], eC[NG], eD[NG], F[NG];
+      const int row = tid - TJ;
+      const int irow = min(i0 + row, g.nr - 1);
+#pragma unroll
+      for (int f = 0; f < NG; ++f) {
+        eA[f] = s_pl[f][row + 2][0]; eB[f] = s_pl[f][row + 2][1];
+        eC[f] = s_pl[f][row + 2][2]; eD[f] = s_pl[f][row + 2][3];
+      }
+      if (GAS) {
+        const double* bgf = a.t.bgc + ((size_t)k * g.nr + irow) * 5;
+        gas_face<1, G75>(gc, eA, eB, eC, eD, nullptr, nullptr, bgf, bgf, 1.0, bgf, 1.0, F, st);
+      } else {
+        dust_face<1>(eA, eB, eC, eD, nullptr, nullptr, F, st);
+      }
+#pragma unroll
+      for (int f = 0; f < NG; ++f) s_ft[f][row][0] = F[f];
+    }
+    // ---- z face k+1/2 from the register ring
+    if (!twod) {
+      if (GAS) {
+        double sB, sC;
+        const double* cB = centre_ptr(a, k, igc, sB);
+        const double* cC = centre_ptr(a, k + 1, igc, sC);
+        const double* bgf = a.t.bgz + ((size_t)(k + 1) * g.nr + igc) * 5;
+        gas_face<2, G75>(gc, rm, r0, rp, rn, nullptr, nullptr, bgf, cB, sB, cC, sC, fzhi, st);
+      } else {
+        dust_face<2>(rm, r0, rp, rn, nullptr, nullptr, fzhi, st);
+      }
+      if (a.second && act && k == g.nz - 1) ledger += Az * fzhi[NG - 1];
+    }
+    __syncthreads();
+    // ---- divergence -sum_s A_s F.n_s (Sect. 2.2), sources (App. B), drag (Sect. 2.9)
+    double Gd[NG];
+#pragma unroll
+    for (int f = 0; f < NG; ++f) {
+      double dr = Arhi * s_fr[f][ti + 1][tj] - Arlo * s_fr[f][ti][tj];
+      double dth = Ath * (s_ft[f][ti][tj + 1] - s_ft[f][ti][tj]);
+      double dz = twod ? 0.0 : Az * (fzhi[f] - fzlo[f]);
+      Gd[f] = -((dr + dth) + dz);
+    }
+    const size_t cell = ((size_t)k * g.nr + ig) * g.nth + jg;
+    const size_t cellw = ((size_t)k * g.nr + igc) * g.nth + jw;
+    const double gr = a.t.grav[((size_t)k * g.nr + igc) * 2 + 0];
+    const double gz = a.t.grav[((size_t)k * g.nr + igc) * 2 + 1];
+    const double* bgc = a.t.bgc + ((size_t)k * g.nr + igc) * 5;
+    double S[NG];
+    if (GAS) {
+      double q[5];
+#pragma unroll
+      for (int f = 0; f < 5; ++f) q[f] = bgc[f] + r0[f];
+      const double inv = 1.0 / q[4];
+      const double u = q[0] * inv, v = q[1] * inv, w = q[2] * inv;
+      const double p = gc.gm1 * (q[3] - 0.5 * (q[0] * u + q[1] * v + q[2] * w));
+      S[0] = (q[1] * v + p) * invrc + q[4] * gr;
+      S[1] = -(q[0] * v) * invrc;
+      S[2] = q[4] * gz;
+      S[3] = q[0] * gr + q[2] * gz;
+      S[4] = 0.0;
+      if (drag) {
+        double dx = 0.0, dy = 0.0, dzz = 0.0;
+#pragma unroll
+        for (int s = 0; s < ND; ++s) {
+          const int o = 5 + 4 * s;
+          const double rd = in[(size_t)(o + 3) * g.N + cellw];
+          double ud = 0.0, vd = 0.0, wd = 0.0;
+          if (rd > 0.0) {
+            double id = 1.0 / rd;
+            ud = in[(size_t)o * g.N + cellw] * id;
+            vd = in[(size_t)(o + 1) * g.N + cellw] * id;
+            wd = in[(size_t)(o + 2) * g.N + cellw] * id;
+          }
+          const double its = omk * g.inv_st[s];
+          dx += rd * (ud - u) * its;
+          dy += rd * (vd - v) * its;
+          dzz += rd * (wd - w) * its;
+        }
+        S[0] += dx;
+        S[1] += dy;
+        S[2] += dzz;
+        S[3] += u * dx + v * dy + w * dzz;
+      }
+    } else {
+      const double rd = r0[3];
+      double ud = 0.0, vd = 0.0, wd = 0.0;
+      if (rd > 0.0) {
+        double id = 1.0 / rd;
+        ud = r0[0] * id; vd = r0[1] * id; wd = r0[2] * id;
+      }
+      double fx = 0.0, fy = 0.0, fz = 0.0;
+      if (drag) {
+        double q[5];
+#pragma unroll
+        for (int f = 0; f < 5; ++f) q[f] = bgc[f] + in[(size_t)f * g.N + cellw];
+        const double inv = 1.0 / q[4];
+        const double u = q[0] * inv, v = q[1] * inv, w = q[2] * inv;
+        const double its = omk * g.inv_st[species];
+        fx = rd * (ud - u) * its;
+        fy = rd * (vd - v) * its;
+        fz = rd * (wd - w) * its;
+      }
+      S[0] = (r0[1] * vd) * invrc + rd * gr - fx;
+      S[1] = -(r0[0] * vd) * invrc - fy;
+      S[2] = rd * gz - fz;
+      S[3] = 0.0;
+    }
+    double Gt[NG];
+#pragma unroll
+    for (int f = 0; f < NG; ++f) Gt[f] = fma(S[f], Vc, Gd[f]);
+    if (GAS && a.mode != MODE_RESID) {
+      const double* R0 = a.t.r0 + ((size_t)k * g.nr + igc) * 5;
+#pragma unroll
+      for (int f = 0; f < NG; ++f) Gt[f] -= R0[f];
+    }
+    if (a.mode == MODE_RESID) {
+      if (GAS && act && jg == 0) {
+#pragma unroll
+        for (int f = 0; f < NG; ++f) a.c.r0w[((size_t)k * g.nr + ig) * 5 + f] = Gt[f];
+      }
+    } else if (a.mode == MODE_OPER) {
+      if (act) {
+#pragma unroll
+        for (int f = 0; f < NG; ++f) a.out[(size_t)(F0 + f) * g.N + cell] = Gt[f];
+      }
+    } else if (act) {
+      const double cdt = a.coef * dt * invV;
+      double nv[NG];
+#pragma unroll
+      for (int f = 0; f < NG; ++f) {
+        nv[f] = fma(cdt, Gt[f], a.base[(size_t)(F0 + f) * g.N + cell]);
+        a.out[(size_t)(F0 + f) * g.N + cell] = nv[f];
+      }
+      if (GAS) {
+        // positivity of the new gas state; CFL of the new state (second stage)
+        double qn[5];
+#pragma unroll
+        for (int f = 0; f < 5; ++f) qn[f] = bgc[f] + nv[f];
+        const double in2 = 1.0 / qn[4];
+        const double un = qn[0] * in2, vn = qn[1] * in2, wn = qn[2] * in2;
+        const double pn = gc.gm1 * (qn[3] - 0.5 * (qn[0] * un + qn[1] * vn + qn[2] * wn));
+        if (!(qn[4] > 0.0 && pn > 0.0)) {
+          atomicOr(&a.c.ctrl->status, FL_NEG);
+          atomicMin(&a.c.ctrl->first_bad, (unsigned long long)cell);
+          atomicCAS(&a.c.ctrl->bad_step, -1, a.step);
+        } else if (a.second) {
+          double spd = sqrt(un * un + vn * vn + wn * wn) + sqrt(gc.g * pn * in2);
+          dtmin = fmin(dtmin, g.cfl * Vc / (spd * maxA));
+        }
+      } else if (a.second && nv[3] > 0.0) {
+        double id = 1.0 / nv[3];
+        double a1 = nv[0] * id, a2 = nv[1] * id, a3 = nv[2] * id;
+        double spd = sqrt(a1 * a1 + a2 * a2 + a3 * a3);
+        dtmin = fmin(dtmin, g.cfl * Vc / (spd * maxA));
+      }
+    }
+    // ---- shift the ring
+#pragma unroll
+    for (int f = 0; f < NG; ++f) {
+      rm[f] = r0[f]; r0[f] = rp[f]; rp[f] = rn[f]; fzlo[f] = fzhi[f];
+    }
+  }
+
+  // ---- block reductions: counters, CFL partial, boundary outflow partial
+  const int wv = tid / 64, ln = tid & 63;
+  int nf_ = wave_isum(st.fall), nv_ = wave_isum(st.vac), mi_ = wave_imax(st.maxit);
+  int nc_ = wave_imax(st.noconv);
+  if (ln == 0) {
+    if (nf_) atomicAdd(&a.c.ctrl->nfall, (unsigned long long)nf_);
+    if (nv_) { atomicAdd(&a.c.ctrl->nvac, (unsigned long long)nv_); atomicOr(&a.c.ctrl->status, FL_VAC); }
+    if (mi_) atomicMax(&a.c.ctrl->maxit, mi_);
+    if (nc_) { atomicOr(&a.c.ctrl->status, FL_NOCONV); atomicCAS(&a.c.ctrl->bad_step, -1, a.step); }
+  }
+  if (a.second && a.mode == MODE_UPDATE) {
+    double m = wave_min(dtmin);
+    double ls = wave_sum(ledger);
+    if (ln == 0) { s_red[wv][0] = m; s_red[wv][1] = ls; }
+    __syncthreads();
+    if (tid == 0) {
+      double mm = s_red[0][0], lsum = s_red[0][1];
+      for (int w2 = 1; w2 < NT / 64; ++w2) {
+        mm = fmin(mm, s_red[w2][0]);
+        lsum += s_red[w2][1];
+      }
+      a.c.cflp[(size_t)blockIdx.x * 5 + slot] = mm;
+      a.c.outp[(size_t)blockIdx.x * 5 + slot] = lsum;
+    }
+  }
+}
+
+// ------------------------------------------------------------------------------------
+// standalone CFL of a state (start of a call) with the positivity check
+
+template <int ND>
+__global__ void __launch_bounds__(256) k_cfl(StageArgs a, const double* state) {
+  __shared__ double s_m[4];
+  const Geo& g = a.g;
+  double dtmin = 1e300;
+  const double gm1 = g.gamma - 1.0;
+  for (size_t c = (size_t)blockIdx.x * blockDim.x + threadIdx.x; c < g.N;
+       c += (size_t)gridDim.x * blockDim.x) {
+    const size_t ki = c / g.nth;
+    const int i = (int)(ki % g.nr);
+    const double* bgc = a.t.bgc + ki * 5;
+    double q[5];
+#pragma unroll
+    for (int f = 0; f < 5; ++f) q[f] = bgc[f] + state[(size_t)f * g.N + c];
+    const double in2 = 1.0 / q[4];
+    const double u = q[0] * in2, v = q[1] * in2, w = q[2] * in2;
+    const double p = gm1 * (q[3] - 0.5 * (q[0] * u + q[1] * v + q[2] * w));
+    if (!(q[4] > 0.0 && p > 0.0)) {
+      atomicOr(&a.c.ctrl->status, FL_NEG);
+      atomicMin(&a.c.ctrl->first_bad, (unsigned long long)c);
+      atomicCAS(&a.c.ctrl->bad_step, -1, a.step);
+      continue;
+    }
+    double spd = sqrt(u * u + v * v + w * w) + sqrt(g.gamma * p * in2);
+#pragma unroll
+    for (int s = 0; s < ND; ++s) {
+      const int o = 5 + 4 * s;
+      double rd = state[(size_t)(o + 3) * g.N + c];
+      if (rd > 0.0) {
+        double id = 1.0 / rd;
+        double a1 = state[(size_t)o * g.N + c] * id, a2 = state[(size_t)(o + 1) * g.N + c] * id;
+        double a3 = state[(size_t)(o + 2) * g.N + c] * id;
+        spd = fmax(spd, sqrt(a1 * a1 + a2 * a2 + a3 * a3));
+      }
+    }
+    const double* rt = a.t.rt + (size_t)i * RT_N;
+    dtmin = fmin(dtmin, g.cfl * rt[RT_V] / (spd * rt[RT_MAXA]));
+  }
+  double m = wave_min(dtmin);
+  if ((threadIdx.x & 63) == 0) s_m[threadIdx.x / 64] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double mm = fmin(fmin(s_m[0], s_m[1]), fmin(s_m[2], s_m[3]));
+    a.c.cflp[blockIdx.x] = mm;
+  }
+}
+
+// final reduction after a step: next dt (CFL), stiffness check, boundary outflow ledger
+__global__ void __launch_bounds__(256) k_reduce(StageArgs a, int nparts, int dt_next, int want_dt,
+                                                int want_ledger) {
+  __shared__ double s_m[4];
+  __shared__ double s_l[4][5];
+  __shared__ int s_stop;
+  if (threadIdx.x == 0) s_stop = __atomic_load_n(&a.c.ctrl->status, __ATOMIC_RELAXED);
+  __syncthreads();
+  if (s_stop & FL_HARD) return;
+  double m = 1e300;
+  double l[5] = {0, 0, 0, 0, 0};
+  // fixed partition and order: deterministic sums
+  // stage partials: [nparts][5] (gas, dust species); standalone CFL: [nparts]
+  const int per = want_ledger ? 1 + a.g.nd : 1;
+  for (int b = threadIdx.x; b < nparts; b += blockDim.x) {
+    if (want_dt)
+      for (int s = 0; s < per; ++s) m = fmin(m, a.c.cflp[want_ledger ? (size_t)b * 5 + s : b]);
+    if (want_ledger)
+#pragma unroll
+      for (int s = 0; s < 5; ++s) l[s] += a.c.outp[(size_t)b * 5 + s];
+  }
+  m = wave_min(m);
+#pragma unroll
+  for (int s = 0; s < 5; ++s) l[s] = wave_sum(l[s]);
+  if ((threadIdx.x & 63) == 0) {
+    s_m[threadIdx.x / 64] = m;
+#pragma unroll
+    for (int s = 0; s < 5; ++s) s_l[threadIdx.x / 64][s] = l[s];
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    if (want_dt) {
+      double mm = fmin(fmin(s_m[0], s_m[1]), fmin(s_m[2], s_m[3]));
+      a.c.dtlog[dt_next] = mm;
+    }
+    if (want_ledger)
+#pragma unroll
+      for (int s = 0; s < 5; ++s)
+        a.c.ctrl->outflow[s] = ((s_l[0][s] + s_l[1][s]) + (s_l[2][s] + s_l[3][s]));
+    double dtn = a.c.dtlog[dt_next];
+    if (a.g.nd > 0 && dtn >= a.c.ctrl->min_ts) {
+      atomicOr(&a.c.ctrl->status, FL_STIFF);
+      atomicCAS(&a.c.ctrl->bad_step, -1, a.step + 1);
+    }
+  }
+}
+
+// ------------------------------------------------------------------------------------
+// tables and initial state (device side of the initialisation)
+
+struct EqPoint {
+  double rho, P, v;
+};
+
+// Stationary flow (App. A): rho0 = rho_mid(r) exp[(GM/c^2)(1/s - 1/r)], P0 = c^2 rho0 with
+// the isothermal c^2 = h0^2 GM r^beta_T, and the azimuthal velocity from the radial
+// balance, v^2 = GM/r + c^2 (beta_T + beta_rho) + beta_T GM (1/r - 1/s) (the analytic
+// pressure gradient folded in).
+__device__ EqPoint eq_point(const rb_config& c, double r, double z) {
+  EqPoint e;
+  const double c2 = c.h0 * c.h0 * c.GM * pow(r, c.beta_T);
+  const double s = sqrt(r * r + z * z);
+  const double invs = 1.0 / s, invr = 1.0 / r;
+  e.rho = c.rho_mid0 * pow(r, c.beta_rho) * exp(c.GM / c2 * (invs - invr));
+  e.P = c2 * e.rho;
+  e.v = sqrt(c.GM * invr + c2 * (c.beta_T + c.beta_rho) + c.beta_T * c.GM * (invr - invs));
+  return e;
+}
+
+__device__ void gas_cons(double g, double rho, double u, double v, double P, double* q) {
+  q[0] = rho * u;
+  q[1] = rho * v;
+  q[2] = 0.0;
+  q[3] = P / (g - 1.0) + 0.5 * rho * (u * u + v * v);
+  q[4] = rho;
+}
+
+// initial dust layer of species s: eps (H/H_d) rho_mid(r) exp(-z^2 / 2 H_d^2)
+__device__ double dust_layer(const rb_config& c, int s, double r, double z) {
+  const double c2 = c.h0 * c.h0 * c.GM * pow(r, c.beta_T);
+  const double H = sqrt(c2) / sqrt(c.GM / (r * r * r));
+  const double Hd = c.hd_over_h[s] * H;
+  return c.eps_dust[s] / c.hd_over_h[s] * c.rho_mid0 * pow(r, c.beta_rho) *
+         exp(-(z * z) / (2.0 * Hd * Hd));
+}
+
+// full stationary state (gas + dust layer moving with the gas) at (r, z); Sod: the
+// initial state at radius r
+__device__ void background_full(const InitArgs& a, double r, double z, double* q) {
+  const rb_config& c = a.cfg;
+  if (c.init_kind == RB_INIT_SOD) {
+    const double* s = r < c.sod_r0 ? c.sod_left : c.sod_right;
+    gas_cons(c.gamma, s[0], s[2], 0.0, s[1], q);
+    return;
+  }
+  EqPoint e = eq_point(c, r, z);
+  gas_cons(c.gamma, e.rho, 0.0, e.v, e.P, q);
+  for (int s = 0; s < c.n_dust; ++s) {
+    double rd = dust_layer(c, s, r, z);
+    q[5 + 4 * s + 0] = 0.0;
+    q[5 + 4 * s + 1] = rd * e.v;
+    q[5 + 4 * s + 2] = 0.0;
+    q[5 + 4 * s + 3] = rd;
+  }
+}
+
+__device__ __forceinline__ double face_r(const rb_config& c, int i) {
+  if (c.log_r) return c.r_in * pow(c.r_out / c.r_in, (double)i / c.nr);
+  return c.r_in + i * ((c.r_out - c.r_in) / c.nr);
+}
+__device__ __forceinline__ double cell_r(const rb_config& c, int i) {
+  return 0.5 * (face_r(c, i) + face_r(c, i + 1));
+}
+
+// radial tables: one block
+__global__ void __launch_bounds__(256) k_tables_r(InitArgs a) {
+  const rb_config& c = a.cfg;
+  const Layout& L = a.L;
+  double* w = a.work;
+  const int nr = c.nr;
+  const bool twod = c.nz == 1;
+  const double dth = 2.0 * M_PI / c.ntheta;
+  const double dz = twod ? 1.0 : 2.0 * c.z_half / c.nz;
+  for (int i = threadIdx.x; i < nr + 4; i += blockDim.x) w[L.rcell + i] = cell_r(c, i - 2);
+  for (int i = threadIdx.x; i <= nr; i += blockDim.x) w[L.ar + i] = face_r(c, i) * dth * dz;
+  for (int i = threadIdx.x; i < nr; i += blockDim.x) {
+    double rm = face_r(c, i), rp = face_r(c, i + 1);
+    double* rt = w + L.rt + (size_t)i * RT_N;
+    double area = 0.5 * (rp * rp - rm * rm);
+    rt[RT_V] = area * dth * dz;
+    rt[RT_INVV] = 1.0 / rt[RT_V];
+    rt[RT_ATH] = (rp - rm) * dz;
+    rt[RT_AZ] = area * dth;
+    double rc = 0.5 * (rm + rp);
+    rt[RT_RC] = rc;
+    rt[RT_INVRC] = 1.0 / rc;
+    rt[RT_OMK] = sqrt(c.GM / (rc * rc * rc));
+    double amax = fmax(fmax(rm * dth * dz, rp * dth * dz), rt[RT_ATH]);
+    if (!twod) amax = fmax(amax, rt[RT_AZ]);
+    rt[RT_MAXA] = amax;
+  }
+  // parabola weights and limiter bounds along r for cells -1..nr (Sect. 2.7)
+  for (int cI = threadIdx.x; cI < nr + 2; cI += blockDim.x) {
+    int cc = cI - 1;
+    double xm = cell_r(c, cc - 1), x0 = cell_r(c, cc), xp = cell_r(c, cc + 1);
+    double hm = x0 - xm, hp = xp - x0, sum = hm + hp;
+    double* co = w + L.rco + (size_t)cI * RC_N;
+    double d = face_r(c, cc + 1) - x0;
+    co[RC_WPP] = (d * d + hm * d) / (hp * sum);
+    co[RC_WPM] = (hp * d - d * d) / (hm * sum);
+    co[RC_LPM] = 2.0 * d / hm;
+    co[RC_LPP] = 2.0 * d / hp;
+    d = face_r(c, cc) - x0;
+    co[RC_WMP] = (d * d + hm * d) / (hp * sum);
+    co[RC_WMM] = (hp * d - d * d) / (hm * sum);
+    co[RC_LMM] = 2.0 * d / hm;
+    co[RC_LMP] = 2.0 * d / hp;
+  }
+  if (threadIdx.x == 0) {
+    Ctrl* ct = reinterpret_cast<Ctrl*>(w + L.ctrl);
+    double mts = 1e300;
+    for (int s = 0; s < c.n_dust; ++s)
+      for (int i = 0; i < nr; ++i) {
+        double rc = cell_r(c, i);
+        mts = fmin(mts, c.stokes[s] / sqrt(c.GM / (rc * rc * rc)));
+      }
+    ct->min_ts = mts;
+  }
+}
+
+// 2D tables over (k, i) including two ghost layers in each direction
+__global__ void __launch_bounds__(256) k_tables_2d(InitArgs a) {
+  const rb_config& c = a.cfg;
+  const Layout& L = a.L;
+  double* w = a.work;
+  const int nr = c.nr, nz = c.nz, nf = a.g.nf;
+  const bool twod = nz == 1;
+  const double dz = twod ? 1.0 : 2.0 * c.z_half / nz;
+  const int W = nr + 4, H = nz + 4;
+  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < W * H; t += gridDim.x * blockDim.x) {
+    const int ii = t % W - 2, kk = t / W - 2;
+    const double zc = twod ? 0.0 : (kk + 0.5 - 0.5 * nz) * dz;
+    double q[MAXF];
+    const bool kin = kk >= 0 && kk < nz, iin = ii >= 0 && ii < nr;
+    if (kin && iin) {
+      const double r = cell_r(c, ii);
+      background_full(a, r, zc, q);
+      for (int f = 0; f < 5; ++f) w[L.bgc + ((size_t)kk * nr + ii) * 5 + f] =
+          c.init_kind == RB_INIT_DISC ? q[f] : 0.0;
+      double s3 = pow(r * r + zc * zc, 1.5);
+      w[L.grav + ((size_t)kk * nr + ii) * 2 + 0] = -c.GM * r / s3;
+      w[L.grav + ((size_t)kk * nr + ii) * 2 + 1] = -c.GM * zc / s3;
+    }
+    if (kin && ii >= 0 && ii <= nr) {
+      background_full(a, face_r(c, ii), zc, q);
+      for (int f = 0; f < 5; ++f) w[L.bgr + ((size_t)kk * (nr + 1) + ii) * 5 + f] =
+          c.init_kind == RB_INIT_DISC ? q[f] : 0.0;
+    }
+    if (!twod && iin && kk >= 0 && kk <= nz) {
+      background_full(a, cell_r(c, ii), (kk - 0.5 * nz) * dz, q);
+      for (int f = 0; f < 5; ++f) w[L.bgz + ((size_t)kk * nr + ii) * 5 + f] =
+          c.init_kind == RB_INIT_DISC ? q[f] : 0.0;
+    }
+    // ghost cells: reconstructed variables (gas E', dust whole) and full gas state
+    if (kin && !iin && ii >= -2 && ii <= nr + 1) {
+      const int side = ii < 0 ? 0 : 1, layer = ii < 0 ? -1 - ii : ii - nr;
+      background_full(a, cell_r(c, ii), zc, q);
+      double* ge = w + L.ghr + ((size_t)(side * 2 + layer) * nz + kk) * nf;
+      for (int f = 0; f < nf; ++f)
+        ge[f] = (f < 5 && c.init_kind == RB_INIT_DISC) ? 0.0 : q[f];
+      if (layer == 0)
+        for (int f = 0; f < 5; ++f) w[L.ghrf + ((size_t)side * nz + kk) * 5 + f] = q[f];
+    }
+    if (!twod && iin && !kin && kk >= -2 && kk <= nz + 1) {
+      const int side = kk < 0 ? 0 : 1, layer = kk < 0 ? -1 - kk : kk - nz;
+      background_full(a, cell_r(c, ii), zc, q);
+      double* ge = w + L.ghz + ((size_t)(side * 2 + layer) * nr + ii) * nf;
+      for (int f = 0; f < nf; ++f)
+        ge[f] = (f < 5 && c.init_kind == RB_INIT_DISC) ? 0.0 : q[f];
+      if (layer == 0)
+        for (int f = 0; f < 5; ++f) w[L.ghzf + ((size_t)side * nr + ii) * 5 + f] = q[f];
+    }
+  }
+}
+
+// Initial state: Sod annulus, or the disc with the column Gaussian vortex (streamfunction
+// psi = psi0 exp(-X^2/2 sr^2 - Y^2/2 sa^2), X = r - r_v, Y = r_v wrap(theta - theta_v),
+// centre vorticity 2 Ro Omega_K(r_v) with Ro = -amplitude), density noise
+// rho0 (1 + a xi), unchanged pressure, dust moving with the gas.  Stored as E' (gas) and
+// whole variables (dust).
+__global__ void __launch_bounds__(256) k_init_state(InitArgs a) {
+  const rb_config& c = a.cfg;
+  const Geo& g = a.g;
+  const int nr = c.nr, nth = c.ntheta, nz = c.nz;
+  const bool twod = nz == 1;
+  const double dz = twod ? 1.0 : 2.0 * c.z_half / nz;
+  const double dth = 2.0 * M_PI / nth;
+  for (size_t cl = (size_t)blockIdx.x * blockDim.x + threadIdx.x; cl < g.N;
+       cl += (size_t)gridDim.x * blockDim.x) {
+    const int j = (int)(cl % nth);
+    const int i = (int)((cl / nth) % nr);
+    const int k = (int)(cl / ((size_t)nth * nr));
+    const double r = cell_r(c, i);
+    const double z = twod ? 0.0 : (k + 0.5 - 0.5 * nz) * dz;
+    double q[MAXF];
+    if (c.init_kind == RB_INIT_SOD) {
+      background_full(a, r, z, q);
+      for (int f = 0; f < 5; ++f) a.state[(size_t)f * g.N + cl] = q[f];
+      continue;
+    }
+    EqPoint e = eq_point(c, r, z);
+    double q0[5];
+    gas_cons(c.gamma, e.rho, 0.0, e.v, e.P, q0);
+    const double A = a.amp ? a.amp[cl] : c.vortex_amp;
+    const double rv = c.vortex_r0, sr = c.vortex_sig_r, sa = c.vortex_sig_a;
+    const double X = r - rv;
+    double d = (j + 0.5) * dth - c.vortex_th0;
+    d -= 2.0 * M_PI * floor((d + M_PI) / (2.0 * M_PI));
+    const double Y = rv * d;
+    const double Om = sqrt(c.GM / (rv * rv * rv));
+    const double psi = -2.0 * Om / (1.0 / (sr * sr) + 1.0 / (sa * sa)) *
+                       exp(-X * X / (2.0 * sr * sr) - Y * Y / (2.0 * sa * sa));
+    const double u = A * (-psi * rv * Y / (r * sa * sa));
+    const double v = e.v + A * (psi * X / (sr * sr));
+    const double xi = a.noise ? a.noise[cl] : 0.0;
+    const double rho = e.rho * (1.0 + c.noise_amp * xi);
+    gas_cons(c.gamma, rho, u, v, e.P, q);
+    for (int f = 0; f < 5; ++f) a.state[(size_t)f * g.N + cl] = q[f] - q0[f];
+    for (int s = 0; s < c.n_dust; ++s) {
+      const double rd = dust_layer(c, s, r, z);
+      const int o = 5 + 4 * s;
+      a.state[(size_t)(o + 0) * g.N + cl] = rd * u;
+      a.state[(size_t)(o + 1) * g.N + cl] = rd * v;
+      a.state[(size_t)(o + 2) * g.N + cl] = 0.0;
+      a.state[(size_t)(o + 3) * g.N + cl] = rd;
+    }
+  }
+}
+
+// ------------------------------------------------------------------------------------
+// conversions and reductions
+
+__global__ void k_fill(double* p, size_t n, double v) {
+  for (size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x; q < n;
+       q += (size_t)gridDim.x * blockDim.x)
+    p[q] = v;
+}
+
+// field f of the state -> full FP64 values (gas: E0 + E'; dust: as stored)
+__global__ void k_to_full(StageArgs a, const double* state, double* out, int f) {
+  const Geo& g = a.g;
+  for (size_t c = (size_t)blockIdx.x * blockDim.x + threadIdx.x; c < g.N;
+       c += (size_t)gridDim.x * blockDim.x) {
+    double v = state[(size_t)f * g.N + c];
+    if (f < 5) v += a.t.bgc[(c / g.nth) * 5 + f];
+    out[c] = v;
+  }
+}
+__global__ void k_from_full(StageArgs a, const double* in, double* state, int f) {
+  const Geo& g = a.g;
+  for (size_t c = (size_t)blockIdx.x * blockDim.x + threadIdx.x; c < g.N;
+       c += (size_t)gridDim.x * blockDim.x) {
+    double v = in[c];
+    if (f < 5) v -= a.t.bgc[(c / g.nth) * 5 + f];
+    state[(size_t)f * g.N + c] = v;
+  }
+}
+
+// mass of field f (density slot): per-block partial sums of rho V over fixed chunks,
+// each summed by a fixed tree (deterministic, FP64)
+__global__ void __launch_bounds__(256) k_mass(StageArgs a, const double* state, double* part, int f) {
+  __shared__ double s_s[4];
+  const Geo& g = a.g;
+  const size_t chunk = (g.N + gridDim.x - 1) / gridDim.x;
+  const size_t c0 = (size_t)blockIdx.x * chunk, c1 = min(g.N, c0 + chunk);
+  double acc = 0.0;
+  for (size_t c = c0 + threadIdx.x; c < c1; c += blockDim.x) {
+    const size_t ki = c / g.nth;
+    const int i = (int)(ki % g.nr);
+    double v = state[(size_t)f * g.N + c];
+    if (f < 5) v += a.t.bgc[ki * 5 + f];
+    acc += v * a.t.rt[(size_t)i * RT_N + RT_V];
+  }
+  acc = wave_sum(acc);
+  if ((threadIdx.x & 63) == 0) s_s[threadIdx.x / 64] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) part[blockIdx.x] = (s_s[0] + s_s[1]) + (s_s[2] + s_s[3]);
+}
+
+__global__ void __launch_bounds__(256) k_sum(const double* part, int n, double* out) {
+  __shared__ double s_s[4];
+  double acc = 0.0;
+  for (int b = threadIdx.x; b < n; b += blockDim.x) acc += part[b];
+  acc = wave_sum(acc);
+  if ((threadIdx.x & 63) == 0) s_s[threadIdx.x / 64] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) *out = (s_s[0] + s_s[1]) + (s_s[2] + s_s[3]);
+}
+
+// ------------------------------------------------------------------------------------
+// launchers
+
+hipError_t launch_tables(const InitArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL(k_tables_r, dim3(1), dim3(256), 0, s, a);
+  const int cells = (a.cfg.nr + 4) * (a.cfg.nz + 4);
+  const int blocks = (cells + 255) / 256;
+  hipLaunchKernelGGL(k_tables_2d, dim3(blocks), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_init_state(const InitArgs& a, hipStream_t s) {
+  const int blocks = (int)std::min<size_t>((a.g.N + 255) / 256, 65536);
+  hipLaunchKernelGGL(k_init_state, dim3(blocks), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+template <int ND>
+static void stage_nd(const StageArgs& a, int blocks, hipStream_t s) {
+  const bool g75 = a.g.gamma == 1.4;
+  if (g75) hipLaunchKernelGGL((k_march<true, ND, true>), dim3(blocks), dim3(NT), 0, s, a, 0);
+  else hipLaunchKernelGGL((k_march<true, ND, false>), dim3(blocks), dim3(NT), 0, s, a, 0);
+  if (a.gas_only) return;
+  for (int sp = 0; sp < ND; ++sp)
+    hipLaunchKernelGGL((k_march<false, ND, true>), dim3(blocks), dim3(NT), 0, s, a, sp);
+}
+
+template <int ND>
+static void group_nd(const StageArgs& a, int blocks, int group, hipStream_t s) {
+  if (group == 0) {
+    if (a.g.gamma == 1.4) hipLaunchKernelGGL((k_march<true, ND, true>), dim3(blocks), dim3(NT), 0, s, a, 0);
+    else hipLaunchKernelGGL((k_march<true, ND, false>), dim3(blocks), dim3(NT), 0, s, a, 0);
+  } else {
+    hipLaunchKernelGGL((k_march<false, ND, true>), dim3(blocks), dim3(NT), 0, s, a, group - 1);
+  }
+}
+
+hipError_t launch_stage_group(const StageArgs& a, int blocks, int group, hipStream_t s) {
+  switch (a.g.nd) {
+    case 0: group_nd<0>(a, blocks, group, s); break;
+    case 1: group_nd<1>(a, blocks, group, s); break;
+    case 2: group_nd<2>(a, blocks, group, s); break;
+    case 3: group_nd<3>(a, blocks, group, s); break;
+    case 4: group_nd<4>(a, blocks, group, s); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_stage(const StageArgs& a, int blocks, hipStream_t s) {
+  switch (a.g.nd) {
+    case 0: stage_nd<0>(a, blocks, s); break;
+    case 1: stage_nd<1>(a, blocks, s); break;
+    case 2: stage_nd<2>(a, blocks, s); break;
+    case 3: stage_nd<3>(a, blocks, s); break;
+    case 4: stage_nd<4>(a, blocks, s); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_cfl(const StageArgs& a, const double* state, int blocks, int dt_idx,
+                      hipStream_t s) {
+  (void)dt_idx;
+  switch (a.g.nd) {
+    case 0: hipLaunchKernelGGL(k_cfl<0>, dim3(blocks), dim3(256), 0, s, a, state); break;
+    case 1: hipLaunchKernelGGL(k_cfl<1>, dim3(blocks), dim3(256), 0, s, a, state); break;
+    case 2: hipLaunchKernelGGL(k_cfl<2>, dim3(blocks), dim3(256), 0, s, a, state); break;
+    case 3: hipLaunchKernelGGL(k_cfl<3>, dim3(blocks), dim3(256), 0, s, a, state); break;
+    case 4: hipLaunchKernelGGL(k_cfl<4>, dim3(blocks), dim3(256), 0, s, a, state); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_reduce(const StageArgs& a, int nparts, int dt_idx_next, int want_dt,
+                         int want_ledger, hipStream_t s) {
+  hipLaunchKernelGGL(k_reduce, dim3(1), dim3(256), 0, s, a, nparts, dt_idx_next, want_dt,
+                     want_ledger);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill(double* p, size_t n, double v, hipStream_t s) {
+  const int blocks = (int)std::min<size_t>((n + 255) / 256, 65536);
+  hipLaunchKernelGGL(k_fill, dim3(std::max(blocks, 1)), dim3(256), 0, s, p, n, v);
+  return hipGetLastError();
+}
+
+hipError_t launch_to_full(const StageArgs& a, const double* state, double* out, int f,
+                          hipStream_t s) {
+  const int blocks = (int)std::min<size_t>((a.g.N + 255) / 256, 65536);
+  hipLaunchKernelGGL(k_to_full, dim3(blocks), dim3(256), 0, s, a, state, out, f);
+  return hipGetLastError();
+}
+
+hipError_t launch_from_full(const StageArgs& a, const double* in, double* state, int f,
+                            hipStream_t s) {
+  const int blocks = (int)std::min<size_t>((a.g.N + 255) / 256, 65536);
+  hipLaunchKernelGGL(k_from_full, dim3(blocks), dim3(256), 0, s, a, in, state, f);
+  return hipGetLastError();
+}
+
+hipError_t launch_mass(const StageArgs& a, const double* state, double* partials, int f,
+                       int blocks, hipStream_t s) {
+  hipLaunchKernelGGL(k_mass, dim3(blocks), dim3(256), 0, s, a, state, partials, f);
+  return hipGetLastError();
+}
+
+hipError_t launch_sum(const double* partials, int n, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_sum, dim3(1), dim3(256), 0, s, partials, n, out);
+  return hipGetLastError();
+}
+
+}  // namespace rb

@@ -1,0 +1,75 @@
+"""The C-ABI library loads and exports every entry point the header declares; host-side
+validation and sizing (no GPU needed)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2207_04252_amd import rossbi, synth
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "rossbi_mi355x.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return re.findall(r"^\s*(?:rb_status|const char\s*\*|void)\s+\*?\s*(rb_\w+)\s*\(", text, flags=re.M)
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(rossbi.LIB_PATH):
+        pytest.fail("HIP library not built (run __graft_entry__.build())")
+    return rossbi.load()
+
+
+def test_header_declares_entry_points():
+    names = declared_functions()
+    assert set(names) == set(rossbi.EXPORTS), names
+
+
+def test_library_exports_every_declared_symbol(lib):
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+
+
+def test_struct_sizes_match_header_layout():
+    # rb_config: 8 int32 + 6 + 1 + 3 + 3 + 4 + 6 + 12 doubles
+    assert ctypes.sizeof(rossbi.rb_config) == 8 * 4 + (6 + 1 + 3 + 3 + 4 + 6 + 12) * 8
+    assert ctypes.sizeof(rossbi.rb_diag) == 8 + 8 + 4 + 4 + 8 + 8 + 8 + 4 + 4 + 5 * 8 + 5 * 8 + 8
+
+
+@pytest.mark.parametrize("name", list(synth.CONFIGS))
+def test_query_sizes(lib, name):
+    cfg = synth.CONFIGS[name]
+    c = rossbi.to_config(cfg)
+    b = rossbi.rb_buffers()
+    assert lib.rb_query_sizes(ctypes.byref(c), ctypes.byref(b)) == rossbi.RB_OK
+    assert b.state_bytes == cfg.n_fields * cfg.n_cells * 8
+    assert b.stage_bytes == b.state_bytes
+    # tables are two-dimensional (axisymmetric): small next to the state
+    assert 0 < b.work_bytes < max(64 << 20, b.state_bytes // 4)
+
+
+@pytest.mark.parametrize("mut", [
+    dict(nr=2), dict(nth=2), dict(nz=2), dict(gamma=1.0), dict(cfl=0.0), dict(r_in=-1.0),
+    dict(stokes=(0.1,) * 5, eps_dust=(0.01,) * 5, hd_over_h=(0.3,) * 5),
+    dict(stokes=(-0.1,), eps_dust=(0.01,), hd_over_h=(0.3,)),
+])
+def test_query_sizes_rejects_bad_config(lib, mut):
+    cfg = synth.C2_DISC.with_(**mut)
+    c = rossbi.to_config(cfg) if cfg.n_dust <= 4 else None
+    if c is None:
+        c = rossbi.to_config(cfg.with_(stokes=(), eps_dust=(), hd_over_h=()))
+        c.n_dust = 5
+    b = rossbi.rb_buffers()
+    assert lib.rb_query_sizes(ctypes.byref(c), ctypes.byref(b)) == rossbi.RB_EINVAL
+
+
+def test_null_arguments_rejected(lib):
+    assert lib.rb_query_sizes(None, None) == rossbi.RB_EINVAL
+    assert lib.rb_step(None, 1, None, None) == rossbi.RB_EINVAL
+    assert lib.rb_get_fields(None, None, 0) == rossbi.RB_EINVAL
+    assert lib.rb_last_error(None) == b"null context"
