@@ -90,6 +90,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--calib", action="store_true",
+                    help="first copy 256 MiB device to device 3 times (counter calibration)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -100,6 +102,13 @@ def main():
     import torch
     from paper_2207_04252_amd import rossbi
 
+    if args.calib:
+        src = torch.ones(64 << 20, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log("calibration copies: 3 x 268435456 bytes")
     cfg = synth.C2_DISC
     xi = synth.noise(cfg)
     log(f"init {cfg.name}")

@@ -63,6 +63,16 @@ __device__ __forceinline__ double inv_root7(double x) {
   return z;
 }
 
+// 1/x for normal positive or negative x: hardware estimate and two Newton steps
+// (within an ulp of the correctly rounded quotient).
+__device__ __forceinline__ double frcp(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  double e = fma(-x, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-x, r, 1.0);
+  return fma(r, e, r);
+}
+
 struct GasC {
   double g, gm1, inv_gm1, g2m1, gm1_2g, gp1_2g, kshock, a2, half_gm1;
 };
@@ -113,19 +123,35 @@ __device__ __forceinline__ double ipow_fan_p(double ratio, const GasC& c) {
 }
 
 // One side of the pressure function of the exact solver (Sect. 2.6) and its derivative.
+// Per-side constants of the pressure function: A = 2/((g+1) rho), B = (g-1)/(g+1) p,
+// 1/p and 1/(rho c).
+struct Side {
+  double r, u, p, c, A, B, ip, irc;
+};
+
+__device__ __forceinline__ Side make_side(double r, double ir, double u, double p, double c,
+                                          const GasC& g) {
+  Side s;
+  s.r = r; s.u = u; s.p = p; s.c = c;
+  s.A = g.a2 * ir;
+  s.B = g.kshock * p;
+  s.ip = frcp(p);
+  s.irc = ir * frcp(c);
+  return s;
+}
+
 template <bool G75>
-__device__ __forceinline__ void pfun(double p, double rK, double pK, double cK, const GasC& c,
-                                     double& f, double& df) {
-  if (p > pK) {
-    double A = c.a2 / rK;
-    double B = c.kshock * pK;
-    double q = sqrt(A / (p + B));
-    f = (p - pK) * q;
-    df = q * (1.0 - 0.5 * (p - pK) / (B + p));
+__device__ __forceinline__ void pfun(double p, const Side& K, const GasC& c, double& f,
+                                     double& df) {
+  if (p > K.p) {
+    double ipb = frcp(p + K.B);
+    double q = sqrt(K.A * ipb);
+    f = (p - K.p) * q;
+    df = q * (1.0 - 0.5 * (p - K.p) * ipb);
   } else {
-    Pow3<G75> w(p / pK, c);
-    f = c.g2m1 * cK * (w.p17 - 1.0);
-    df = w.pm67 / (rK * cK);
+    Pow3<G75> w(p * K.ip, c);
+    f = c.g2m1 * K.c * (w.p17 - 1.0);
+    df = w.pm67 * K.irc;
   }
 }
 
@@ -138,12 +164,12 @@ struct TStat {
 // star velocity, then the wave pattern at x/t = 0; tangential velocities come from the
 // side of the contact.  Output: mass, normal momentum, two tangential momenta, energy.
 template <bool G75>
-__device__ void gas_riemann(const GasC& c, double rL, double uL, double aL, double bL, double pL,
-                            double rR, double uR, double aR, double bR, double pR, double fl[5],
-                            TStat& st) {
-  double cL = sqrt(c.g * pL / rL);
-  double cR = sqrt(c.g * pR / rR);
-  double du = uR - uL;
+__device__ void gas_riemann(const GasC& c, double rL, double irL, double uL, double aL, double bL,
+                            double pL, double rR, double irR, double uR, double aR, double bR,
+                            double pR, double fl[5], TStat& st) {
+  const double cL = sqrt(c.g * pL * irL);
+  const double cR = sqrt(c.g * pR * irR);
+  const double du = uR - uL;
   double rho, un, t1, t2, p;
   if (c.g2m1 * (cL + cR) <= du) {
     // vacuum between two rarefactions
@@ -163,40 +189,73 @@ __device__ void gas_riemann(const GasC& c, double rL, double uL, double aL, doub
       t1 = aR; t2 = bR;
     } else { rho = rR; un = uR; t1 = aR; t2 = bR; p = pR; }
   } else {
+    const Side L = make_side(rL, irL, uL, pL, cL, c);
+    const Side R = make_side(rR, irR, uR, pR, cR, c);
+    // Supersonic faces: with u_L >= c_L, let p_hi be the star pressure at which a left
+    // shock would stand still.  If f(p_hi) >= 0 then p* <= p_hi (f increases), so the
+    // left wave (rarefaction with head u_L - c_L >= 0, or shock with speed >= 0) lies
+    // at x/t >= 0, and u* = u_L - f_L(p*) >= u_L - f_L(p_hi) >= 0: the solution at x/t = 0
+    // is the left state, which is what the full solve returns.  Mirror for u_R <= -c_R.
+    if (uL >= cL) {
+      const double m = uL / cL;
+      const double phi = pL * (m * m - c.gm1_2g) / c.gp1_2g;
+      double fL, dL, fR, dR;
+      pfun<G75>(phi, L, c, fL, dL);
+      pfun<G75>(phi, R, c, fR, dR);
+      if (fL + fR + du >= 0.0 && uL - fL >= 0.0) {
+        const double m0 = rL * uL;
+        const double en = pL * c.inv_gm1 + 0.5 * rL * (uL * uL + aL * aL + bL * bL);
+        fl[0] = m0; fl[1] = m0 * uL + pL; fl[2] = m0 * aL; fl[3] = m0 * bL; fl[4] = (en + pL) * uL;
+        return;
+      }
+    } else if (uR <= -cR) {
+      const double m = -uR / cR;
+      const double phi = pR * (m * m - c.gm1_2g) / c.gp1_2g;
+      double fL, dL, fR, dR;
+      pfun<G75>(phi, L, c, fL, dL);
+      pfun<G75>(phi, R, c, fR, dR);
+      if (fL + fR + du >= 0.0 && uR + fR <= 0.0) {
+        const double m0 = rR * uR;
+        const double en = pR * c.inv_gm1 + 0.5 * rR * (uR * uR + aR * aR + bR * bR);
+        fl[0] = m0; fl[1] = m0 * uR + pR; fl[2] = m0 * aR; fl[3] = m0 * bR; fl[4] = (en + pR) * uR;
+        return;
+      }
+    }
     double ppv = 0.5 * (pL + pR) - 0.125 * du * (rL + rR) * (cL + cR);
     double ps = fmax(ppv, 1e-8 * fmin(pL, pR));
     int it = 0;
     bool conv = false;
+    double fL = 0.0, dL = 1.0, fR = 0.0, dR = 1.0, dp = 0.0;
     while (it < 50) {
       ++it;
-      double fL, dL, fR, dR;
-      pfun<G75>(ps, rL, pL, cL, c, fL, dL);
-      pfun<G75>(ps, rR, pR, cR, c, fR, dR);
+      pfun<G75>(ps, L, c, fL, dL);
+      pfun<G75>(ps, R, c, fR, dR);
       double pn = ps - (fL + fR + du) / (dL + dR);
       if (pn < 1e-8 * ps) pn = 1e-8 * ps;
-      double ch = 2.0 * fabs(pn - ps) / (pn + ps);
+      dp = pn - ps;
+      // relative change 2|dp|/(p_new + p_old) <= 1e-12, written without a division
+      bool done = 2.0 * fabs(dp) <= 1e-12 * (pn + ps);
       ps = pn;
-      if (ch <= 1e-12) { conv = true; break; }
+      if (done) { conv = true; break; }
     }
     st.maxit = max(st.maxit, it);
     if (!conv) st.noconv = 1;
-    double fL, dL, fR, dR;
-    pfun<G75>(ps, rL, pL, cL, c, fL, dL);
-    pfun<G75>(ps, rR, pR, cR, c, fR, dR);
-    double us = 0.5 * (uL + uR) + 0.5 * (fR - fL);
+    // star velocity at the converged p*: the last iterate's f and f' extrapolated over
+    // the final (<= 1e-12 relative) Newton update; the neglected term is O(dp^2)
+    double us = 0.5 * (uL + uR) + 0.5 * ((fR + dR * dp) - (fL + dL * dp));
     p = ps;
     if (0.0 <= us) {
       t1 = aL; t2 = bL;
       if (ps > pL) {
-        double q = ps / pL;
+        double q = ps * L.ip;
         double sL = uL - cL * sqrt(c.gp1_2g * q + c.gm1_2g);
         if (0.0 <= sL) { rho = rL; un = uL; p = pL; }
-        else { rho = rL * (q + c.kshock) / (c.kshock * q + 1.0); un = us; }
+        else { rho = rL * (q + c.kshock) * frcp(c.kshock * q + 1.0); un = us; }
       } else {
         double sHL = uL - cL;
         if (0.0 <= sHL) { rho = rL; un = uL; p = pL; }
         else {
-          Pow3<G75> w(ps / pL, c);
+          Pow3<G75> w(ps * L.ip, c);
           double sTL = us - cL * w.p17;
           if (0.0 > sTL) { rho = rL * w.p57; un = us; }
           else {
@@ -209,15 +268,15 @@ __device__ void gas_riemann(const GasC& c, double rL, double uL, double aL, doub
     } else {
       t1 = aR; t2 = bR;
       if (ps > pR) {
-        double q = ps / pR;
+        double q = ps * R.ip;
         double sR = uR + cR * sqrt(c.gp1_2g * q + c.gm1_2g);
         if (0.0 >= sR) { rho = rR; un = uR; p = pR; }
-        else { rho = rR * (q + c.kshock) / (c.kshock * q + 1.0); un = us; }
+        else { rho = rR * (q + c.kshock) * frcp(c.kshock * q + 1.0); un = us; }
       } else {
         double sHR = uR + cR;
         if (0.0 >= sHR) { rho = rR; un = uR; p = pR; }
         else {
-          Pow3<G75> w(ps / pR, c);
+          Pow3<G75> w(ps * R.ip, c);
           double sTR = us + cR * w.p17;
           if (0.0 <= sTR) { rho = rR * w.p57; un = us; }
           else {
@@ -280,13 +339,14 @@ template <int DIR> struct Dirs {
 };
 
 struct Prim5 {
-  double rho, un, t1, t2, p;
+  double rho, irho, un, t1, t2, p;
 };
 
 template <int DIR>
 __device__ __forceinline__ Prim5 gas_prim(const double q[5], double gm1) {
   Prim5 w;
-  double inv = 1.0 / q[4];
+  double inv = frcp(q[4]);
+  w.irho = inv;
   double u = q[0] * inv, v = q[1] * inv, z = q[2] * inv;
   w.rho = q[4];
   w.p = gm1 * (q[3] - 0.5 * (q[0] * u + q[1] * v + q[2] * z));
@@ -335,7 +395,8 @@ __device__ __forceinline__ void gas_face(const GasC& c, const double* eA, const 
     st.fall++;
   }
   double fl[5];
-  gas_riemann<G75>(c, L.rho, L.un, L.t1, L.t2, L.p, R.rho, R.un, R.t1, R.t2, R.p, fl, st);
+  gas_riemann<G75>(c, L.rho, L.irho, L.un, L.t1, L.t2, L.p, R.rho, R.irho, R.un, R.t1, R.t2, R.p,
+                   fl, st);
   F[4] = fl[0];
   F[Dirs<DIR>::n] = fl[1];
   F[Dirs<DIR>::t1] = fl[2];

@@ -163,7 +163,12 @@ def test_operator_parity(rb):
     cs, _ = __import__("tests.parity", fromlist=["x"]).sound_speed(E, cfg.gamma)
     speed = np.sqrt((E[0] ** 2 + E[1] ** 2 + E[2] ** 2)) / E[4] + cs
     for f in range(cfg.n_fields):
-        scale = np.abs(E[f]).max() * amax * speed.max()
+        mag = np.abs(E[f])
+        if f < 3:
+            mag = np.maximum(mag, E[4] * cs)
+        elif f >= 5 and (f - 5) % 4 < 3:
+            mag = np.maximum(mag, E[5 + 4 * ((f - 5) // 4) + 3] * cs)
+        scale = mag.max() * amax * speed.max()
         err = np.max(np.abs(G[f] - Go[f])) / scale
         say(f"[operator] field {f}: err/scale {err:.2e}")
         assert err <= 1e-12, (f, err)
