@@ -158,11 +158,17 @@ class Oracle:
         self.nf = cfg.n_fields
         self.shape = (self.nf, cfg.nz, cfg.nr, cfg.nth)
 
-    def __del__(self):
+    def close(self):
         h = getattr(self, "h", None)
         if h:
             lib().or_destroy(h)
             self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:  # interpreter shutdown: module globals already cleared
+            pass
 
     def step(self, n: int, dt: float | None = None, dt_list=None):
         """Advance n steps: CFL (default), fixed dt, or a list of dt. Returns (status, dts)."""

@@ -19,8 +19,8 @@ struct rb_ctx {
   Geo g;
   Layout L;
   hipStream_t stream;
-  double* state;
-  double* stage;
+  void* state;
+  void* stage;
   double* work;
   double t;
   int64_t step;
@@ -58,7 +58,11 @@ bool validate(const rb_config* c, std::string* why) {
   for (int s = 0; s < c->n_dust; ++s)
     if (!(c->stokes[s] > 0.0) || !(c->hd_over_h[s] > 0.0) || !(c->eps_dust[s] >= 0.0))
       return bad("dust parameters must be positive");
-  if (c->precision != RB_FP64) return bad("precision not supported by this build");
+  if (c->precision != RB_FP64 && c->precision != RB_FP32_PERT) return bad("unknown precision");
+  if (c->precision == RB_FP32_PERT && c->init_kind != RB_INIT_DISC)
+    return bad("the FP32-perturbation form needs a disc background");
+  if (c->precision == RB_FP32_PERT && c->gamma != 1.4)
+    return bad("the FP32-perturbation form is specialised to gamma = 7/5");
   return true;
 }
 
@@ -104,6 +108,7 @@ Layout make_layout(const rb_config& c) {
   L.ghrf = take(2 * nz * 5);
   L.ghz = take(4 * nr * nf);
   L.ghzf = take(2 * nr * 5);
+  L.dsc = take(std::max<size_t>(1, (size_t)c.n_dust * nz * nr));
   L.dtlog = take(DTLOG + 2);
   L.cflp = take(std::max((size_t)L.nblocks * 5, (size_t)L.ncfl));
   L.outp = take((size_t)L.nblocks * 5);
@@ -120,6 +125,7 @@ Geo make_geo(const rb_config& c) {
   g.nf = 5 + 4 * c.n_dust;
   g.N = (size_t)c.nr * c.ntheta * c.nz;
   g.gamma = c.gamma; g.GM = c.GM; g.cfl = c.cfl;
+  g.p32 = c.precision == RB_FP32_PERT;
   for (int s = 0; s < 4; ++s) g.inv_st[s] = s < c.n_dust ? 1.0 / c.stokes[s] : 0.0;
   return g;
 }
@@ -133,6 +139,7 @@ StageArgs base_args(rb_ctx* x) {
   a.t.rt = w + L.rt; a.t.ar = w + L.ar; a.t.rco = w + L.rco; a.t.bgc = w + L.bgc;
   a.t.bgr = w + L.bgr; a.t.bgz = w + L.bgz; a.t.r0 = w + L.r0; a.t.grav = w + L.grav;
   a.t.ghr = w + L.ghr; a.t.ghrf = w + L.ghrf; a.t.ghz = w + L.ghz; a.t.ghzf = w + L.ghzf;
+  a.t.dsc = w + L.dsc;
   a.c.ctrl = reinterpret_cast<Ctrl*>(w + L.ctrl);
   a.c.dtlog = w + L.dtlog; a.c.cflp = w + L.cflp; a.c.outp = w + L.outp; a.c.r0w = w + L.r0;
   a.tk = L.tk; a.ntj = L.ntj; a.nti = L.nti; a.nkc = L.nkc;
@@ -245,10 +252,15 @@ rb_status rb_query_sizes(const rb_config* cfg, rb_buffers* sizes) {
   if (!validate(cfg, &why)) return RB_EINVAL;
   const size_t N = (size_t)cfg->nr * cfg->ntheta * cfg->nz;
   const size_t nf = 5 + 4 * cfg->n_dust;
-  const size_t elem = cfg->precision == RB_FP64 ? 8 : 4;
   Layout L = make_layout(*cfg);
-  sizes->state_bytes = nf * N * elem;
-  sizes->stage_bytes = nf * N * elem;
+  size_t bytes = nf * N * 8;
+  if (cfg->precision == RB_FP32_PERT) {
+    // gas deviation + dust momenta in FP32 (padded to 256 B), dust densities in FP64
+    const size_t nf32 = 5 + 3 * (size_t)cfg->n_dust;
+    bytes = (nf32 * N + 63) / 64 * 64 * 4 + (size_t)cfg->n_dust * N * 8;
+  }
+  sizes->state_bytes = bytes;
+  sizes->stage_bytes = bytes;
   sizes->work_bytes = L.total * sizeof(double);
   return RB_OK;
 }
@@ -276,8 +288,8 @@ rb_status rb_init_state(const rb_config* cfg, const rb_buffers* bufs, const doub
   x->g = make_geo(*cfg);
   x->L = make_layout(*cfg);
   x->stream = (hipStream_t)stream;
-  x->state = (double*)bufs->state;
-  x->stage = (double*)bufs->stage;
+  x->state = bufs->state;
+  x->stage = bufs->stage;
   x->work = (double*)bufs->work;
   x->t = 0.0;
   x->step = 0;
@@ -297,9 +309,11 @@ rb_status rb_init_state(const rb_config* cfg, const rb_buffers* bufs, const doub
   if (launch_tables(ia, x->stream) != hipSuccess) return bail(RB_EDEVICE);
 
   // empty run (Sect. 2.8): the spatial operator of the stationary flow, by the step
-  // kernel itself, written to the residual table
-  if (cfg->balanced) {
-    if (launch_fill(x->stage, x->g.N * x->g.nf, 0.0, x->stream) != hipSuccess) return bail(RB_EDEVICE);
+  // kernel itself, written to the residual table.  The FP32-perturbation form forms
+  // G(E) - G(E0) directly and needs no residual.
+  if (cfg->balanced && !x->g.p32) {
+    if (launch_fill((double*)x->stage, x->g.N * x->g.nf, 0.0, x->stream) != hipSuccess)
+      return bail(RB_EDEVICE);
     StageArgs a = base_args(x);
     a.in = x->stage;
     a.base = x->stage;
@@ -314,13 +328,13 @@ rb_status rb_init_state(const rb_config* cfg, const rb_buffers* bufs, const doub
     if (hipMemcpyAsync(x->stage, noise, N * sizeof(double), hipMemcpyHostToDevice, x->stream) !=
         hipSuccess)
       return bail(RB_EDEVICE);
-    ia.noise = x->stage;
+    ia.noise = (const double*)x->stage;
   }
   if (amp) {
-    if (hipMemcpyAsync(x->stage + N, amp, N * sizeof(double), hipMemcpyHostToDevice, x->stream) !=
-        hipSuccess)
+    if (hipMemcpyAsync((double*)x->stage + N, amp, N * sizeof(double), hipMemcpyHostToDevice,
+                       x->stream) != hipSuccess)
       return bail(RB_EDEVICE);
-    ia.amp = x->stage + N;
+    ia.amp = (const double*)x->stage + N;
   }
   if (launch_init_state(ia, x->stream) != hipSuccess) return bail(RB_EDEVICE);
   if (hipStreamSynchronize(x->stream) != hipSuccess) return bail(RB_EDEVICE);
@@ -417,7 +431,7 @@ rb_status rb_get_fields(rb_ctx* x, double* host_out, size_t n_doubles) {
   if (n_doubles != N * x->g.nf) return fail(x, RB_EINVAL, "n_doubles must be nfields * ncells");
   StageArgs a = base_args(x);
   for (int f = 0; f < x->g.nf; ++f) {
-    HIPCHK(x, launch_to_full(a, x->state, x->stage, f, x->stream), "to_full");
+    HIPCHK(x, launch_to_full(a, x->state, (double*)x->stage, f, x->stream), "to_full");
     HIPCHK(x, hipMemcpyAsync(host_out + (size_t)f * N, x->stage, N * sizeof(double),
                              hipMemcpyDeviceToHost, x->stream), "copy out");
   }
@@ -433,7 +447,7 @@ rb_status rb_set_fields(rb_ctx* x, const double* host_in, size_t n_doubles) {
   for (int f = 0; f < x->g.nf; ++f) {
     HIPCHK(x, hipMemcpyAsync(x->stage, host_in + (size_t)f * N, N * sizeof(double),
                              hipMemcpyHostToDevice, x->stream), "copy in");
-    HIPCHK(x, launch_from_full(a, x->stage, x->state, f, x->stream), "from_full");
+    HIPCHK(x, launch_from_full(a, (const double*)x->stage, x->state, f, x->stream), "from_full");
   }
   HIPCHK(x, hipStreamSynchronize(x->stream), "sync");
   x->hard = 0;
@@ -447,6 +461,15 @@ rb_status rb_eval_operator(rb_ctx* x, double* host_out, size_t n_doubles) {
   StageArgs a = base_args(x);
   a.in = x->state; a.base = x->state; a.out = x->stage; a.mode = MODE_OPER; a.gas_only = 0;
   HIPCHK(x, launch_stage(a, x->L.nblocks, x->stream), "operator");
+  if (x->g.p32) {
+    // FP32 form: the kernels write FP32; widened at the boundary
+    std::vector<float> tmp(N * x->g.nf);
+    HIPCHK(x, hipMemcpyAsync(tmp.data(), x->stage, tmp.size() * sizeof(float),
+                             hipMemcpyDeviceToHost, x->stream), "copy out");
+    HIPCHK(x, hipStreamSynchronize(x->stream), "sync");
+    for (size_t q = 0; q < tmp.size(); ++q) host_out[q] = tmp[q];
+    return RB_OK;
+  }
   HIPCHK(x, hipMemcpyAsync(host_out, x->stage, N * x->g.nf * sizeof(double), hipMemcpyDeviceToHost,
                            x->stream), "copy out");
   HIPCHK(x, hipStreamSynchronize(x->stream), "sync");
@@ -457,6 +480,7 @@ rb_status rb_get_residual(rb_ctx* x, double* host_out, size_t n_doubles) {
   if (!x || !host_out) return RB_EINVAL;
   const size_t n = (size_t)x->g.nz * x->g.nr * 5;
   if (n_doubles != n) return fail(x, RB_EINVAL, "n_doubles must be nz * nr * 5");
+  if (x->g.p32) return fail(x, RB_EINVAL, "the FP32-perturbation form has no residual table");
   HIPCHK(x, hipMemcpyAsync(host_out, x->work + x->L.r0, n * sizeof(double), hipMemcpyDeviceToHost,
                            x->stream), "copy out");
   HIPCHK(x, hipStreamSynchronize(x->stream), "sync");

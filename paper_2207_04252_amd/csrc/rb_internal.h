@@ -37,15 +37,16 @@ struct Ctrl {
   unsigned long long first_bad;
   unsigned long long nfall;
   unsigned long long nvac;
+  unsigned long long nresolve;  // FP32-perturbation faces re-solved in FP64
   double min_ts;          // smallest dust stopping time (init)
   double outflow[5];      // boundary mass outflow of the last second stage
-  double scratch[8];
+  double scratch[7];
 };
 
 // Offsets (in doubles) of the tables inside the work area.
 struct Layout {
   size_t ctrl, rt, ar, rco, rcell, zc, bgc, bgr, bgz, r0, grav, ghr, ghrf, ghz, ghzf;
-  size_t dtlog, cflp, outp, red, total;
+  size_t dsc, dtlog, cflp, outp, red, total;
   int nblocks;   // stage-kernel blocks
   int ntj, nti, nkc, tk;
   int ncfl;      // blocks of the standalone CFL / conversion kernels
@@ -53,6 +54,7 @@ struct Layout {
 
 struct Geo {
   int nr, nth, nz, twod, nd, nf;
+  int p32;       // state stored as FP32 perturbation (gas) / scaled dust
   size_t N;
   double gamma, GM, cfl;
   double inv_st[4];
@@ -71,6 +73,7 @@ struct Tables {
   const double* ghrf;
   const double* ghz;
   const double* ghzf;
+  const double* dsc;   // dust storage scale [species][k][i] (FP32 storage)
 };
 
 struct Ctl {
@@ -87,9 +90,9 @@ struct StageArgs {
   Geo g;
   Tables t;
   Ctl c;
-  const double* in;     // state whose operator is evaluated (stencil source)
-  const double* base;   // E^n, base of the update
-  double* out;          // updated state (or operator output)
+  const void* in;       // state whose operator is evaluated (stencil source)
+  const void* base;     // E^n, base of the update
+  void* out;            // updated state (or operator output, FP64)
   double coef;          // 1/2 for the first stage, 1 for the second
   int dt_idx;           // dtlog entry holding this step's dt
   int mode;
@@ -106,7 +109,7 @@ struct InitArgs {
   Layout L;
   const double* noise;  // device, may be null
   const double* amp;    // device, may be null
-  double* state;
+  void* state;
 };
 
 // launchers (rb_kernels.hip)
@@ -115,15 +118,15 @@ hipError_t launch_init_state(const InitArgs& a, hipStream_t s);
 hipError_t launch_stage(const StageArgs& a, int blocks, hipStream_t s);
 // one group of a stage: 0 the gas, 1 + s dust species s
 hipError_t launch_stage_group(const StageArgs& a, int blocks, int group, hipStream_t s);
-hipError_t launch_cfl(const StageArgs& a, const double* state, int blocks, int dt_idx, hipStream_t s);
+hipError_t launch_cfl(const StageArgs& a, const void* state, int blocks, int dt_idx, hipStream_t s);
 hipError_t launch_reduce(const StageArgs& a, int nparts, int dt_idx_next, int want_dt,
                          int want_ledger, hipStream_t s);
 hipError_t launch_fill(double* p, size_t n, double v, hipStream_t s);
-hipError_t launch_to_full(const StageArgs& a, const double* state, double* out, int f,
+hipError_t launch_to_full(const StageArgs& a, const void* state, double* out, int f,
                           hipStream_t s);
-hipError_t launch_from_full(const StageArgs& a, const double* in, double* state, int f,
+hipError_t launch_from_full(const StageArgs& a, const double* in, void* state, int f,
                             hipStream_t s);
-hipError_t launch_mass(const StageArgs& a, const double* state, double* partials, int f,
+hipError_t launch_mass(const StageArgs& a, const void* state, double* partials, int f,
                        int blocks, hipStream_t s);
 hipError_t launch_sum(const double* partials, int n, double* out, hipStream_t s);
 

@@ -10,6 +10,8 @@
 // stage (plus the L2-resident halo) and written once.
 #include <math.h>
 
+#include <type_traits>
+
 #include "rb_internal.h"
 
 namespace rb {
@@ -17,32 +19,39 @@ namespace rb {
 // ------------------------------------------------------------------------------------
 // small helpers
 
-__device__ __forceinline__ double minmod3(double x, double y, double z) {
-  if (x > 0.0 && y > 0.0 && z > 0.0) return fmin(x, fmin(y, z));
-  if (x < 0.0 && y < 0.0 && z < 0.0) return fmax(x, fmax(y, z));
-  return 0.0;
+template <class T>
+__device__ __forceinline__ T minmod3(T x, T y, T z) {
+  if (x > T(0) && y > T(0) && z > T(0)) return fmin(x, fmin(y, z));
+  if (x < T(0) && y < T(0) && z < T(0)) return fmax(x, fmax(y, z));
+  return T(0);
 }
 
 // Uniform direction (index coordinates): the three-point parabola gives the upper-face
 // increment (dm + 3 dp)/8 and the lower-face increment -(3 dm + dp)/8, limited by the
 // one-sided differences (Sect. 2.7).  Written so that mirrored data give exactly
 // opposite increments.
-__device__ __forceinline__ double inc_up_u(double em, double e0, double ep) {
-  double dm = e0 - em, dp = ep - e0;
-  return minmod3(fma(3.0, dp, dm) * 0.125, dm, dp);
+template <class T>
+__device__ __forceinline__ T inc_up_u(T em, T e0, T ep) {
+  T dm = e0 - em, dp = ep - e0;
+  return minmod3<T>(fma(T(3), dp, dm) * T(0.125), dm, dp);
 }
-__device__ __forceinline__ double inc_lo_u(double em, double e0, double ep) {
-  double dm = e0 - em, dp = ep - e0;
-  return minmod3(-(fma(3.0, dm, dp) * 0.125), -dm, -dp);
+template <class T>
+__device__ __forceinline__ T inc_lo_u(T em, T e0, T ep) {
+  T dm = e0 - em, dp = ep - e0;
+  return minmod3<T>(-(fma(T(3), dm, dp) * T(0.125)), -dm, -dp);
 }
 // Non-uniform r: precomputed parabola weights and limiter bounds of the cell.
-__device__ __forceinline__ double inc_up_c(double em, double e0, double ep, const double* co) {
-  double dm = e0 - em, dp = ep - e0;
-  return minmod3(fma(co[RC_WPP], dp, co[RC_WPM] * dm), co[RC_LPM] * dm, co[RC_LPP] * dp);
+template <class T>
+__device__ __forceinline__ T inc_up_c(T em, T e0, T ep, const double* co) {
+  T dm = e0 - em, dp = ep - e0;
+  return minmod3<T>(fma(T(co[RC_WPP]), dp, T(co[RC_WPM]) * dm), T(co[RC_LPM]) * dm,
+                    T(co[RC_LPP]) * dp);
 }
-__device__ __forceinline__ double inc_lo_c(double em, double e0, double ep, const double* co) {
-  double dm = e0 - em, dp = ep - e0;
-  return minmod3(fma(co[RC_WMP], dp, co[RC_WMM] * dm), co[RC_LMM] * dm, co[RC_LMP] * dp);
+template <class T>
+__device__ __forceinline__ T inc_lo_c(T em, T e0, T ep, const double* co) {
+  T dm = e0 - em, dp = ep - e0;
+  return minmod3<T>(fma(T(co[RC_WMP]), dp, T(co[RC_WMM]) * dm), T(co[RC_LMM]) * dm,
+                    T(co[RC_LMP]) * dp);
 }
 
 // x^(-1/7) for x > 0: FP32 hardware log2/exp2 seed, then Newton on z^-7 = x written as
@@ -156,7 +165,7 @@ __device__ __forceinline__ void pfun(double p, const Side& K, const GasC& c, dou
 }
 
 struct TStat {
-  int fall, vac, maxit, noconv;
+  int fall, vac, maxit, noconv, resolve;
 };
 
 // Exact Riemann problem of the ideal gas sampled at x/t = 0 (Sect. 2.6): Newton on p*
@@ -452,10 +461,117 @@ __device__ __forceinline__ void dust_face(const double* eA, const double* eB, co
   F[Dirs<DIR>::t2] = fl[3];
 }
 
+}  // namespace rb
+
+#include "rb_pert32.h"
+
+namespace rb {
+
+// FP32-perturbation gas face: reconstructed perturbations about the face background,
+// the perturbation Riemann problem and the flux change dF = F* - F(W0); faces the FP32
+// form cannot take (strong perturbation, transonic fan, no convergence, non-positive
+// face state) are re-solved in FP64 on the full states.
+template <int DIR>
+__device__ __forceinline__ void gas_face_p32(const GasC& c, const float* eA, const float* eB,
+                                             const float* eC, const float* eD, const double* coB,
+                                             const double* coC, const double* bgf,
+                                             const double* cenB, double sB, const double* cenC,
+                                             double sC, float F[5], TStat& st) {
+  float qL[5], qR[5];
+#pragma unroll
+  for (int f = 0; f < 5; ++f) {
+    float iB, iC;
+    if (DIR == 0) {
+      iB = inc_up_c<float>(eA[f], eB[f], eC[f], coB);
+      iC = inc_lo_c<float>(eB[f], eC[f], eD[f], coC);
+    } else {
+      iB = inc_up_u<float>(eA[f], eB[f], eC[f]);
+      iC = inc_lo_u<float>(eB[f], eC[f], eD[f]);
+    }
+    qL[f] = eB[f] + iB;
+    qR[f] = eC[f] + iC;
+  }
+  const BgW b = bg_prims<DIR>(bgf, c.g);
+  const float gm1 = (float)c.gm1;
+  const PW L = pert_prims<DIR>(b, qL, gm1);
+  const PW R = pert_prims<DIR>(b, qR, gm1);
+  const bool okL = (b.rho + (double)L.rho > 0.0) && (b.p + (double)L.p > 0.0);
+  const bool okR = (b.rho + (double)R.rho > 0.0) && (b.p + (double)R.p > 0.0);
+  PW W;
+  float fl[5];
+  if (okL && okR && riemann_pert(b, L, R, c, W, st)) {
+    flux_pert(b, W, (float)c.inv_gm1, fl);
+  } else {
+    st.resolve++;
+    double qL64[5], qR64[5];
+#pragma unroll
+    for (int f = 0; f < 5; ++f) {
+      qL64[f] = okL ? bgf[f] + (double)qL[f] : cenB[f] + sB * (double)eB[f];
+      qR64[f] = okR ? bgf[f] + (double)qR[f] : cenC[f] + sC * (double)eC[f];
+    }
+    if (!okL) st.fall++;
+    if (!okR) st.fall++;
+    const Prim5 PL = gas_prim<DIR>(qL64, c.gm1);
+    const Prim5 PR = gas_prim<DIR>(qR64, c.gm1);
+    double f64[5];
+    gas_riemann<true>(c, PL.rho, PL.irho, PL.un, PL.t1, PL.t2, PL.p, PR.rho, PR.irho, PR.un, PR.t1,
+                      PR.t2, PR.p, f64, st);
+    const double m0 = b.rho * b.un;
+    fl[0] = (float)(f64[0] - m0);
+    fl[1] = (float)(f64[1] - (m0 * b.un + b.p));
+    fl[2] = (float)(f64[2] - m0 * b.t1);
+    fl[3] = (float)(f64[3] - m0 * b.t2);
+    fl[4] = (float)(f64[4] - b.h * b.un);
+  }
+  F[4] = fl[0];
+  F[Dirs<DIR>::n] = fl[1];
+  F[Dirs<DIR>::t1] = fl[2];
+  F[Dirs<DIR>::t2] = fl[3];
+  F[3] = fl[4];
+}
+
 // ------------------------------------------------------------------------------------
 // state access with ghost cells (Sect. 2.4): r and z ghosts come from tables, theta wraps
 
-__device__ __forceinline__ double fetch(const StageArgs& a, const double* st, int f, int k, int i,
+// FP32-perturbation storage layout: the gas deviation (5 fields) and the dust momenta
+// (3 per species, divided by the species' initial-layer density) in FP32, then the dust
+// densities in FP64 (mass is accumulated in FP64).  f64_base: first double of that part.
+__device__ __forceinline__ size_t p32_f64_base(const Geo& g) {
+  return (((size_t)(5 + 3 * g.nd) * g.N + 63) / 64 * 64) / 2;
+}
+
+// interior value of field f (FP64 storage, or the FP32-perturbation layout above)
+template <bool P32>
+__device__ __forceinline__ double ld_cell(const StageArgs& a, const void* st, int f, int k, int i,
+                                          size_t cell) {
+  const Geo& g = a.g;
+  if (P32) {
+    if (f < 5) return (double)((const float*)st)[(size_t)f * g.N + cell];
+    const int sp = (f - 5) >> 2, c = (f - 5) & 3;
+    if (c == 3) return ((const double*)st)[p32_f64_base(g) + (size_t)sp * g.N + cell];
+    const double v = (double)((const float*)st)[(size_t)(5 + 3 * sp + c) * g.N + cell];
+    return v * a.t.dsc[((size_t)sp * g.nz + k) * g.nr + i];
+  }
+  return ((const double*)st)[(size_t)f * g.N + cell];
+}
+
+template <bool P32>
+__device__ __forceinline__ void st_cell(const StageArgs& a, void* st, int f, int k, int i,
+                                        size_t cell, double v) {
+  const Geo& g = a.g;
+  if (P32) {
+    if (f < 5) { ((float*)st)[(size_t)f * g.N + cell] = (float)v; return; }
+    const int sp = (f - 5) >> 2, c = (f - 5) & 3;
+    if (c == 3) { ((double*)st)[p32_f64_base(g) + (size_t)sp * g.N + cell] = v; return; }
+    v /= a.t.dsc[((size_t)sp * g.nz + k) * g.nr + i];
+    ((float*)st)[(size_t)(5 + 3 * sp + c) * g.N + cell] = (float)v;
+  } else {
+    ((double*)st)[(size_t)f * g.N + cell] = v;
+  }
+}
+
+template <bool P32>
+__device__ __forceinline__ double fetch(const StageArgs& a, const void* st, int f, int k, int i,
                                         int j) {
   const Geo& g = a.g;
   if (k < 0 || k >= g.nz) {
@@ -469,7 +585,7 @@ __device__ __forceinline__ double fetch(const StageArgs& a, const double* st, in
     int layer = min(i < 0 ? -1 - i : i - g.nr, 1);
     return a.t.ghr[((size_t)(side * 2 + layer) * g.nz + k) * g.nf + f];
   }
-  return st[(size_t)f * g.N + ((size_t)k * g.nr + i) * g.nth + j];
+  return ld_cell<P32>(a, st, f, k, i, ((size_t)k * g.nr + i) * g.nth + j);
 }
 
 // centre state used by the gas fallback: E0(centre) + E' for interior cells (scale 1),
@@ -527,18 +643,20 @@ __device__ __forceinline__ int xcd_tile(int b, int nblk) {
 // groups interact only through the cell-local drag, which each kernel evaluates from
 // the other group's centre state of the same stage input.
 
-template <bool GAS, int ND, bool G75>
+template <bool GAS, int ND, bool G75, bool P32>
 __global__ void __launch_bounds__(NT) k_march(StageArgs a, int species) {
   constexpr int NG = GAS ? 5 : 4;
+  constexpr bool PG = GAS && P32;  // gas in the FP32 perturbation form
+  using T = typename std::conditional<PG, float, double>::type;
   // a hard error stops the evolution; the flag is read once and broadcast so that the
   // whole workgroup takes the same branch (other workgroups may set it meanwhile)
   __shared__ int s_stop;
   if (threadIdx.x == 0) s_stop = __atomic_load_n(&a.c.ctrl->status, __ATOMIC_RELAXED);
   __syncthreads();
   if (s_stop & FL_HARD) return;
-  __shared__ double s_pl[NG][TI + 4][TJ + 4];
-  __shared__ double s_ft[NG][TI][TJ + 1];
-  __shared__ double s_fr[NG][TI + 1][TJ];
+  __shared__ T s_pl[NG][TI + 4][TJ + 4];
+  __shared__ T s_ft[NG][TI][TJ + 1];
+  __shared__ T s_fr[NG][TI + 1][TJ];
   __shared__ double s_red[NT / 64][2];
 
   const Geo& g = a.g;
@@ -558,10 +676,10 @@ __global__ void __launch_bounds__(NT) k_march(StageArgs a, int species) {
   const bool act = jg < g.nth && ig < g.nr;
   const int igc = min(ig, g.nr - 1);
   const bool drag = !a.gas_only && ND > 0;
-  const double* in = a.in;
+  const void* in = a.in;
   const double dt = a.dt_idx >= 0 ? a.c.dtlog[a.dt_idx] : 0.0;
 
-  TStat st = {0, 0, 0, 0};
+  TStat st = {0, 0, 0, 0, 0};
   double dtmin = 1e300;
   double ledger = 0.0;
 
@@ -570,40 +688,53 @@ __global__ void __launch_bounds__(NT) k_march(StageArgs a, int species) {
   const double invrc = rt[RT_INVRC], omk = rt[RT_OMK], maxA = rt[RT_MAXA];
   const double Arlo = a.t.ar[igc], Arhi = a.t.ar[igc + 1];
 
+  // gas face: FP64 full states, or FP32 perturbations about the face background
+  auto face = [&](auto dirc, const T* eA, const T* eB, const T* eC, const T* eD, const double* coB,
+                  const double* coC, const double* bgf, const double* cB, double sB,
+                  const double* cC, double sC, T* F) {
+    constexpr int D = decltype(dirc)::value;
+    if constexpr (PG) gas_face_p32<D>(gc, eA, eB, eC, eD, coB, coC, bgf, cB, sB, cC, sC, F, st);
+    else if constexpr (GAS) gas_face<D, G75>(gc, eA, eB, eC, eD, coB, coC, bgf, cB, sB, cC, sC, F, st);
+    else dust_face<D>(eA, eB, eC, eD, coB, coC, F, st);
+  };
+  using DR = std::integral_constant<int, 0>;
+  using DT = std::integral_constant<int, 1>;
+  using DZ = std::integral_constant<int, 2>;
+
   // z ring of the thread's column: e_{k-1}, e_k, e_{k+1}, e_{k+2}; fluxes below/above k
-  double rm[NG], r0[NG], rp[NG], rn[NG], fzlo[NG], fzhi[NG];
+  T rm[NG], r0[NG], rp[NG], rn[NG], fzlo[NG], fzhi[NG];
   const bool twod = g.twod != 0;
   if (!twod) {
-    double e2[NG];
+    T e2[NG];
 #pragma unroll
     for (int f = 0; f < NG; ++f) {
-      e2[f] = fetch(a, in, F0 + f, k0 - 2, ig, jw);
-      rm[f] = fetch(a, in, F0 + f, k0 - 1, ig, jw);
-      r0[f] = fetch(a, in, F0 + f, k0, ig, jw);
-      rp[f] = fetch(a, in, F0 + f, k0 + 1, ig, jw);
+      e2[f] = (T)fetch<P32>(a, in, F0 + f, k0 - 2, ig, jw);
+      rm[f] = (T)fetch<P32>(a, in, F0 + f, k0 - 1, ig, jw);
+      r0[f] = (T)fetch<P32>(a, in, F0 + f, k0, ig, jw);
+      rp[f] = (T)fetch<P32>(a, in, F0 + f, k0 + 1, ig, jw);
     }
-    if (GAS) {
-      double sB, sC;
-      const double* cB = centre_ptr(a, k0 - 1, igc, sB);
-      const double* cC = centre_ptr(a, k0, igc, sC);
-      const double* bgf = a.t.bgz + ((size_t)k0 * g.nr + igc) * 5;
-      gas_face<2, G75>(gc, e2, rm, r0, rp, nullptr, nullptr, bgf, cB, sB, cC, sC, fzlo, st);
-    } else {
-      dust_face<2>(e2, rm, r0, rp, nullptr, nullptr, fzlo, st);
+    double sB = 1.0, sC = 1.0;
+    const double* cB = GAS ? centre_ptr(a, k0 - 1, igc, sB) : nullptr;
+    const double* cC = GAS ? centre_ptr(a, k0, igc, sC) : nullptr;
+    const double* bgf = a.t.bgz + ((size_t)k0 * g.nr + igc) * 5;
+    face(DZ(), e2, rm, r0, rp, nullptr, nullptr, bgf, cB, sB, cC, sC, fzlo);
+    if (a.second && k0 == 0 && act) {
+      double fm = (double)fzlo[NG - 1];
+      if (PG) fm += bgf[2];  // background normal mass flux rho0 w0
+      ledger -= Az * fm;
     }
-    if (a.second && k0 == 0 && act) ledger -= Az * fzlo[NG - 1];
   } else {
 #pragma unroll
     for (int f = 0; f < NG; ++f) {
-      r0[f] = fetch(a, in, F0 + f, 0, ig, jw);
-      rm[f] = 0.0; rp[f] = 0.0; rn[f] = 0.0; fzlo[f] = 0.0; fzhi[f] = 0.0;
+      r0[f] = (T)fetch<P32>(a, in, F0 + f, 0, ig, jw);
+      rm[f] = T(0); rp[f] = T(0); rn[f] = T(0); fzlo[f] = T(0); fzhi[f] = T(0);
     }
   }
 
   for (int k = k0; k < k1; ++k) {
     if (!twod) {
 #pragma unroll
-      for (int f = 0; f < NG; ++f) rn[f] = fetch(a, in, F0 + f, k + 2, ig, jw);
+      for (int f = 0; f < NG; ++f) rn[f] = (T)fetch<P32>(a, in, F0 + f, k + 2, ig, jw);
     }
     // ---- stage the plane (with halo) in LDS
 #pragma unroll
@@ -614,22 +745,20 @@ __global__ void __launch_bounds__(NT) k_march(StageArgs a, int species) {
       int ii = i0 + rr - 2;
       int jj = (j0 + cc - 2 + g.nth) % g.nth;
 #pragma unroll
-      for (int f = 0; f < NG; ++f) s_pl[f][rr][cc] = fetch(a, in, F0 + f, k, ii, jj);
+      for (int f = 0; f < NG; ++f) s_pl[f][rr][cc] = (T)fetch<P32>(a, in, F0 + f, k, ii, jj);
     }
     __syncthreads();
     // ---- theta face j+1/2 and r face i+1/2 of this cell
     {
-      double eA[NG], eB[NG], eC[NG], eD[NG], F[NG];
+      T eA[NG], eB[NG], eC[NG], eD[NG], F[NG];
 #pragma unroll
       for (int f = 0; f < NG; ++f) {
         eA[f] = s_pl[f][ti + 2][tj + 1]; eB[f] = s_pl[f][ti + 2][tj + 2];
         eC[f] = s_pl[f][ti + 2][tj + 3]; eD[f] = s_pl[f][ti + 2][tj + 4];
       }
-      if (GAS) {
+      {
         const double* bgf = a.t.bgc + ((size_t)k * g.nr + igc) * 5;
-        gas_face<1, G75>(gc, eA, eB, eC, eD, nullptr, nullptr, bgf, bgf, 1.0, bgf, 1.0, F, st);
-      } else {
-        dust_face<1>(eA, eB, eC, eD, nullptr, nullptr, F, st);
+        face(DT(), eA, eB, eC, eD, nullptr, nullptr, bgf, bgf, 1.0, bgf, 1.0, F);
       }
 #pragma unroll
       for (int f = 0; f < NG; ++f) s_ft[f][ti][tj + 1] = F[f];
@@ -638,46 +767,46 @@ __global__ void __launch_bounds__(NT) k_march(StageArgs a, int species) {
         eA[f] = s_pl[f][ti + 1][tj + 2]; eB[f] = s_pl[f][ti + 2][tj + 2];
         eC[f] = s_pl[f][ti + 3][tj + 2]; eD[f] = s_pl[f][ti + 4][tj + 2];
       }
-      if (GAS) {
+      {
         const int ifc = min(ig + 1, g.nr);
         const double* bgf = a.t.bgr + ((size_t)k * (g.nr + 1) + ifc) * 5;
-        double sB, sC;
-        const double* cB = centre_ptr(a, k, min(ig, g.nr), sB);
-        const double* cC = centre_ptr(a, k, min(ig + 1, g.nr), sC);
-        gas_face<0, G75>(gc, eA, eB, eC, eD, rco_ptr(a, ig), rco_ptr(a, ig + 1), bgf, cB, sB, cC,
-                         sC, F, st);
-      } else {
-        dust_face<0>(eA, eB, eC, eD, rco_ptr(a, ig), rco_ptr(a, ig + 1), F, st);
+        double sB = 1.0, sC = 1.0;
+        const double* cB = GAS ? centre_ptr(a, k, min(ig, g.nr), sB) : nullptr;
+        const double* cC = GAS ? centre_ptr(a, k, min(ig + 1, g.nr), sC) : nullptr;
+        face(DR(), eA, eB, eC, eD, rco_ptr(a, ig), rco_ptr(a, ig + 1), bgf, cB, sB, cC, sC, F);
+        if (a.second && act && ig == g.nr - 1) {
+          double fm = (double)F[NG - 1];
+          if (PG) fm += bgf[0];  // background normal mass flux rho0 u0
+          ledger += Arhi * fm;
+        }
       }
 #pragma unroll
       for (int f = 0; f < NG; ++f) s_fr[f][ti + 1][tj] = F[f];
-      if (a.second && act && ig == g.nr - 1) ledger += Arhi * F[NG - 1];
     }
     // ---- lower-edge faces of the tile: r face i0-1/2 (threads 0..63) and theta face
     //      j0-1/2 of each row (threads 64..71)
     if (tid < TJ) {
-      double eA[NG], eB[NG], eC[NG], eD[NG], F[NG];
+      T eA[NG], eB[NG], eC[NG], eD[NG], F[NG];
       const int col = tid;
 #pragma unroll
       for (int f = 0; f < NG; ++f) {
         eA[f] = s_pl[f][0][col + 2]; eB[f] = s_pl[f][1][col + 2];
         eC[f] = s_pl[f][2][col + 2]; eD[f] = s_pl[f][3][col + 2];
       }
-      if (GAS) {
-        const double* bgf = a.t.bgr + ((size_t)k * (g.nr + 1) + i0) * 5;
-        double sB, sC;
-        const double* cB = centre_ptr(a, k, i0 - 1, sB);
-        const double* cC = centre_ptr(a, k, i0, sC);
-        gas_face<0, G75>(gc, eA, eB, eC, eD, rco_ptr(a, i0 - 1), rco_ptr(a, i0), bgf, cB, sB, cC,
-                         sC, F, st);
-      } else {
-        dust_face<0>(eA, eB, eC, eD, rco_ptr(a, i0 - 1), rco_ptr(a, i0), F, st);
-      }
+      const double* bgf = a.t.bgr + ((size_t)k * (g.nr + 1) + i0) * 5;
+      double sB = 1.0, sC = 1.0;
+      const double* cB = GAS ? centre_ptr(a, k, i0 - 1, sB) : nullptr;
+      const double* cC = GAS ? centre_ptr(a, k, i0, sC) : nullptr;
+      face(DR(), eA, eB, eC, eD, rco_ptr(a, i0 - 1), rco_ptr(a, i0), bgf, cB, sB, cC, sC, F);
 #pragma unroll
       for (int f = 0; f < NG; ++f) s_fr[f][0][col] = F[f];
-      if (a.second && i0 == 0 && j0 + col < g.nth) ledger -= a.t.ar[0] * F[NG - 1];
+      if (a.second && i0 == 0 && j0 + col < g.nth) {
+        double fm = (double)F[NG - 1];
+        if (PG) fm += bgf[0];
+        ledger -= a.t.ar[0] * fm;
+      }
     } else if (tid < TJ + TI) {
-      double eA[NG], eB[NG], eC[NG], eD[NG], F[NG];
+      T eA[NG], eB[NG], eC[NG], eD[NG], F[NG];
       const int row = tid - TJ;
       const int irow = min(i0 + row, g.nr - 1);
 #pragma unroll
@@ -685,36 +814,32 @@ __global__ void __launch_bounds__(NT) k_march(StageArgs a, int species) {
         eA[f] = s_pl[f][row + 2][0]; eB[f] = s_pl[f][row + 2][1];
         eC[f] = s_pl[f][row + 2][2]; eD[f] = s_pl[f][row + 2][3];
       }
-      if (GAS) {
-        const double* bgf = a.t.bgc + ((size_t)k * g.nr + irow) * 5;
-        gas_face<1, G75>(gc, eA, eB, eC, eD, nullptr, nullptr, bgf, bgf, 1.0, bgf, 1.0, F, st);
-      } else {
-        dust_face<1>(eA, eB, eC, eD, nullptr, nullptr, F, st);
-      }
+      const double* bgf = a.t.bgc + ((size_t)k * g.nr + irow) * 5;
+      face(DT(), eA, eB, eC, eD, nullptr, nullptr, bgf, bgf, 1.0, bgf, 1.0, F);
 #pragma unroll
       for (int f = 0; f < NG; ++f) s_ft[f][row][0] = F[f];
     }
     // ---- z face k+1/2 from the register ring
     if (!twod) {
-      if (GAS) {
-        double sB, sC;
-        const double* cB = centre_ptr(a, k, igc, sB);
-        const double* cC = centre_ptr(a, k + 1, igc, sC);
-        const double* bgf = a.t.bgz + ((size_t)(k + 1) * g.nr + igc) * 5;
-        gas_face<2, G75>(gc, rm, r0, rp, rn, nullptr, nullptr, bgf, cB, sB, cC, sC, fzhi, st);
-      } else {
-        dust_face<2>(rm, r0, rp, rn, nullptr, nullptr, fzhi, st);
+      double sB = 1.0, sC = 1.0;
+      const double* cB = GAS ? centre_ptr(a, k, igc, sB) : nullptr;
+      const double* cC = GAS ? centre_ptr(a, k + 1, igc, sC) : nullptr;
+      const double* bgf = a.t.bgz + ((size_t)(k + 1) * g.nr + igc) * 5;
+      face(DZ(), rm, r0, rp, rn, nullptr, nullptr, bgf, cB, sB, cC, sC, fzhi);
+      if (a.second && act && k == g.nz - 1) {
+        double fm = (double)fzhi[NG - 1];
+        if (PG) fm += bgf[2];
+        ledger += Az * fm;
       }
-      if (a.second && act && k == g.nz - 1) ledger += Az * fzhi[NG - 1];
     }
     __syncthreads();
     // ---- divergence -sum_s A_s F.n_s (Sect. 2.2), sources (App. B), drag (Sect. 2.9)
-    double Gd[NG];
+    T Gd[NG];
 #pragma unroll
     for (int f = 0; f < NG; ++f) {
-      double dr = Arhi * s_fr[f][ti + 1][tj] - Arlo * s_fr[f][ti][tj];
-      double dth = Ath * (s_ft[f][ti][tj + 1] - s_ft[f][ti][tj]);
-      double dz = twod ? 0.0 : Az * (fzhi[f] - fzlo[f]);
+      T dr = T(Arhi) * s_fr[f][ti + 1][tj] - T(Arlo) * s_fr[f][ti][tj];
+      T dth = T(Ath) * (s_ft[f][ti][tj + 1] - s_ft[f][ti][tj]);
+      T dz = twod ? T(0) : T(Az) * (fzhi[f] - fzlo[f]);
       Gd[f] = -((dr + dth) + dz);
     }
     const size_t cell = ((size_t)k * g.nr + ig) * g.nth + jg;
@@ -722,8 +847,49 @@ __global__ void __launch_bounds__(NT) k_march(StageArgs a, int species) {
     const double gr = a.t.grav[((size_t)k * g.nr + igc) * 2 + 0];
     const double gz = a.t.grav[((size_t)k * g.nr + igc) * 2 + 1];
     const double* bgc = a.t.bgc + ((size_t)k * g.nr + igc) * 5;
-    double S[NG];
-    if (GAS) {
+    T S[NG];
+    if constexpr (PG) {
+      // source change S(E) - S(E0): every term formed from the perturbations
+      const BgW bc = bg_prims<0>(bgc, gc.g);
+      const PW w = pert_prims<0>(bc, r0, (float)gc.gm1);
+      const float v0 = (float)bc.t1;
+      const float mth = (float)bgc[1] + r0[1];
+      const float mr = (float)bgc[0] + r0[0];
+      const float ir = (float)invrc, fgr = (float)gr, fgz = (float)gz;
+      S[0] = (r0[1] * v0 + mth * w.t1 + w.p) * ir + r0[4] * fgr;
+      S[1] = -(r0[0] * v0 + mr * w.t1) * ir;
+      S[2] = r0[4] * fgz;
+      S[3] = r0[0] * fgr + r0[2] * fgz;
+      S[4] = 0.0f;
+      if (drag) {
+        double q[5];
+#pragma unroll
+        for (int f = 0; f < 5; ++f) q[f] = bgc[f] + (double)r0[f];
+        const double inv = 1.0 / q[4];
+        const double u = q[0] * inv, v = q[1] * inv, w2 = q[2] * inv;
+        double dx = 0.0, dy = 0.0, dzz = 0.0;
+#pragma unroll
+        for (int s2 = 0; s2 < ND; ++s2) {
+          const int o = 5 + 4 * s2;
+          const double rd = ld_cell<P32>(a, in, o + 3, k, igc, cellw);
+          double ud = 0.0, vd = 0.0, wd = 0.0;
+          if (rd > 0.0) {
+            double id = 1.0 / rd;
+            ud = ld_cell<P32>(a, in, o, k, igc, cellw) * id;
+            vd = ld_cell<P32>(a, in, o + 1, k, igc, cellw) * id;
+            wd = ld_cell<P32>(a, in, o + 2, k, igc, cellw) * id;
+          }
+          const double its = omk * g.inv_st[s2];
+          dx += rd * (ud - u) * its;
+          dy += rd * (vd - v) * its;
+          dzz += rd * (wd - w2) * its;
+        }
+        S[0] += (float)dx;
+        S[1] += (float)dy;
+        S[2] += (float)dzz;
+        S[3] += (float)(u * dx + v * dy + w2 * dzz);
+      }
+    } else if constexpr (GAS) {
       double q[5];
 #pragma unroll
       for (int f = 0; f < 5; ++f) q[f] = bgc[f] + r0[f];
@@ -738,17 +904,17 @@ __global__ void __launch_bounds__(NT) k_march(StageArgs a, int species) {
       if (drag) {
         double dx = 0.0, dy = 0.0, dzz = 0.0;
 #pragma unroll
-        for (int s = 0; s < ND; ++s) {
-          const int o = 5 + 4 * s;
-          const double rd = in[(size_t)(o + 3) * g.N + cellw];
+        for (int s2 = 0; s2 < ND; ++s2) {
+          const int o = 5 + 4 * s2;
+          const double rd = ld_cell<P32>(a, in, o + 3, k, igc, cellw);
           double ud = 0.0, vd = 0.0, wd = 0.0;
           if (rd > 0.0) {
             double id = 1.0 / rd;
-            ud = in[(size_t)o * g.N + cellw] * id;
-            vd = in[(size_t)(o + 1) * g.N + cellw] * id;
-            wd = in[(size_t)(o + 2) * g.N + cellw] * id;
+            ud = ld_cell<P32>(a, in, o, k, igc, cellw) * id;
+            vd = ld_cell<P32>(a, in, o + 1, k, igc, cellw) * id;
+            wd = ld_cell<P32>(a, in, o + 2, k, igc, cellw) * id;
           }
-          const double its = omk * g.inv_st[s];
+          const double its = omk * g.inv_st[s2];
           dx += rd * (ud - u) * its;
           dy += rd * (vd - v) * its;
           dzz += rd * (wd - w) * its;
@@ -769,7 +935,7 @@ __global__ void __launch_bounds__(NT) k_march(StageArgs a, int species) {
       if (drag) {
         double q[5];
 #pragma unroll
-        for (int f = 0; f < 5; ++f) q[f] = bgc[f] + in[(size_t)f * g.N + cellw];
+        for (int f = 0; f < 5; ++f) q[f] = bgc[f] + ld_cell<P32>(a, in, f, k, igc, cellw);
         const double inv = 1.0 / q[4];
         const double u = q[0] * inv, v = q[1] * inv, w = q[2] * inv;
         const double its = omk * g.inv_st[species];
@@ -782,37 +948,50 @@ __global__ void __launch_bounds__(NT) k_march(StageArgs a, int species) {
       S[2] = rd * gz - fz;
       S[3] = 0.0;
     }
-    double Gt[NG];
+    T Gt[NG];
 #pragma unroll
-    for (int f = 0; f < NG; ++f) Gt[f] = fma(S[f], Vc, Gd[f]);
-    if (GAS && a.mode != MODE_RESID) {
+    for (int f = 0; f < NG; ++f) Gt[f] = fma(S[f], T(Vc), Gd[f]);
+    if (GAS && !P32 && a.mode != MODE_RESID) {
       const double* R0 = a.t.r0 + ((size_t)k * g.nr + igc) * 5;
 #pragma unroll
-      for (int f = 0; f < NG; ++f) Gt[f] -= R0[f];
+      for (int f = 0; f < NG; ++f) Gt[f] -= (T)R0[f];
     }
     if (a.mode == MODE_RESID) {
       if (GAS && act && jg == 0) {
 #pragma unroll
-        for (int f = 0; f < NG; ++f) a.c.r0w[((size_t)k * g.nr + ig) * 5 + f] = Gt[f];
+        for (int f = 0; f < NG; ++f) a.c.r0w[((size_t)k * g.nr + ig) * 5 + f] = (double)Gt[f];
       }
     } else if (a.mode == MODE_OPER) {
       if (act) {
 #pragma unroll
-        for (int f = 0; f < NG; ++f) a.out[(size_t)(F0 + f) * g.N + cell] = Gt[f];
+        for (int f = 0; f < NG; ++f) {
+          if (P32) ((float*)a.out)[(size_t)(F0 + f) * g.N + cell] = (float)Gt[f];
+          else ((double*)a.out)[(size_t)(F0 + f) * g.N + cell] = (double)Gt[f];
+        }
       }
     } else if (act) {
-      const double cdt = a.coef * dt * invV;
-      double nv[NG];
+      double nvd[NG];
+      if constexpr (PG) {
+        const float cdt = (float)(a.coef * dt * invV);
 #pragma unroll
-      for (int f = 0; f < NG; ++f) {
-        nv[f] = fma(cdt, Gt[f], a.base[(size_t)(F0 + f) * g.N + cell]);
-        a.out[(size_t)(F0 + f) * g.N + cell] = nv[f];
+        for (int f = 0; f < NG; ++f) {
+          float nv = fma(cdt, Gt[f], ((const float*)a.base)[(size_t)f * g.N + cell]);
+          ((float*)a.out)[(size_t)f * g.N + cell] = nv;
+          nvd[f] = (double)nv;
+        }
+      } else {
+        const double cdt = a.coef * dt * invV;
+#pragma unroll
+        for (int f = 0; f < NG; ++f) {
+          nvd[f] = fma(cdt, (double)Gt[f], ld_cell<P32>(a, a.base, F0 + f, k, ig, cell));
+          st_cell<P32>(a, a.out, F0 + f, k, ig, cell, nvd[f]);
+        }
       }
       if (GAS) {
         // positivity of the new gas state; CFL of the new state (second stage)
         double qn[5];
 #pragma unroll
-        for (int f = 0; f < 5; ++f) qn[f] = bgc[f] + nv[f];
+        for (int f = 0; f < 5; ++f) qn[f] = bgc[f] + nvd[f];
         const double in2 = 1.0 / qn[4];
         const double un = qn[0] * in2, vn = qn[1] * in2, wn = qn[2] * in2;
         const double pn = gc.gm1 * (qn[3] - 0.5 * (qn[0] * un + qn[1] * vn + qn[2] * wn));
@@ -824,9 +1003,9 @@ __global__ void __launch_bounds__(NT) k_march(StageArgs a, int species) {
           double spd = sqrt(un * un + vn * vn + wn * wn) + sqrt(gc.g * pn * in2);
           dtmin = fmin(dtmin, g.cfl * Vc / (spd * maxA));
         }
-      } else if (a.second && nv[3] > 0.0) {
-        double id = 1.0 / nv[3];
-        double a1 = nv[0] * id, a2 = nv[1] * id, a3 = nv[2] * id;
+      } else if (a.second && nvd[3] > 0.0) {
+        double id = 1.0 / nvd[3];
+        double a1 = nvd[0] * id, a2 = nvd[1] * id, a3 = nvd[2] * id;
         double spd = sqrt(a1 * a1 + a2 * a2 + a3 * a3);
         dtmin = fmin(dtmin, g.cfl * Vc / (spd * maxA));
       }
@@ -841,11 +1020,12 @@ __global__ void __launch_bounds__(NT) k_march(StageArgs a, int species) {
   // ---- block reductions: counters, CFL partial, boundary outflow partial
   const int wv = tid / 64, ln = tid & 63;
   int nf_ = wave_isum(st.fall), nv_ = wave_isum(st.vac), mi_ = wave_imax(st.maxit);
-  int nc_ = wave_imax(st.noconv);
+  int nc_ = wave_imax(st.noconv), nr_ = wave_isum(st.resolve);
   if (ln == 0) {
     if (nf_) atomicAdd(&a.c.ctrl->nfall, (unsigned long long)nf_);
     if (nv_) { atomicAdd(&a.c.ctrl->nvac, (unsigned long long)nv_); atomicOr(&a.c.ctrl->status, FL_VAC); }
     if (mi_) atomicMax(&a.c.ctrl->maxit, mi_);
+    if (nr_) atomicAdd(&a.c.ctrl->nresolve, (unsigned long long)nr_);
     if (nc_) { atomicOr(&a.c.ctrl->status, FL_NOCONV); atomicCAS(&a.c.ctrl->bad_step, -1, a.step); }
   }
   if (a.second && a.mode == MODE_UPDATE) {
@@ -868,8 +1048,8 @@ __global__ void __launch_bounds__(NT) k_march(StageArgs a, int species) {
 // ------------------------------------------------------------------------------------
 // standalone CFL of a state (start of a call) with the positivity check
 
-template <int ND>
-__global__ void __launch_bounds__(256) k_cfl(StageArgs a, const double* state) {
+template <int ND, bool P32>
+__global__ void __launch_bounds__(256) k_cfl(StageArgs a, const void* state) {
   __shared__ double s_m[4];
   const Geo& g = a.g;
   double dtmin = 1e300;
@@ -879,9 +1059,10 @@ __global__ void __launch_bounds__(256) k_cfl(StageArgs a, const double* state) {
     const size_t ki = c / g.nth;
     const int i = (int)(ki % g.nr);
     const double* bgc = a.t.bgc + ki * 5;
+    const int k = (int)(ki / g.nr);
     double q[5];
 #pragma unroll
-    for (int f = 0; f < 5; ++f) q[f] = bgc[f] + state[(size_t)f * g.N + c];
+    for (int f = 0; f < 5; ++f) q[f] = bgc[f] + ld_cell<P32>(a, state, f, k, i, c);
     const double in2 = 1.0 / q[4];
     const double u = q[0] * in2, v = q[1] * in2, w = q[2] * in2;
     const double p = gm1 * (q[3] - 0.5 * (q[0] * u + q[1] * v + q[2] * w));
@@ -895,11 +1076,12 @@ __global__ void __launch_bounds__(256) k_cfl(StageArgs a, const double* state) {
 #pragma unroll
     for (int s = 0; s < ND; ++s) {
       const int o = 5 + 4 * s;
-      double rd = state[(size_t)(o + 3) * g.N + c];
+      double rd = ld_cell<P32>(a, state, o + 3, k, i, c);
       if (rd > 0.0) {
         double id = 1.0 / rd;
-        double a1 = state[(size_t)o * g.N + c] * id, a2 = state[(size_t)(o + 1) * g.N + c] * id;
-        double a3 = state[(size_t)(o + 2) * g.N + c] * id;
+        double a1 = ld_cell<P32>(a, state, o, k, i, c) * id;
+        double a2 = ld_cell<P32>(a, state, o + 1, k, i, c) * id;
+        double a3 = ld_cell<P32>(a, state, o + 2, k, i, c) * id;
         spd = fmax(spd, sqrt(a1 * a1 + a2 * a2 + a3 * a3));
       }
     }
@@ -1107,6 +1289,11 @@ __global__ void __launch_bounds__(256) k_tables_2d(InitArgs a) {
       double s3 = pow(r * r + zc * zc, 1.5);
       w[L.grav + ((size_t)kk * nr + ii) * 2 + 0] = -c.GM * r / s3;
       w[L.grav + ((size_t)kk * nr + ii) * 2 + 1] = -c.GM * zc / s3;
+      // storage scale of each dust species (FP32 form): its initial layer density
+      for (int sp = 0; sp < c.n_dust; ++sp) {
+        double rd = q[5 + 4 * sp + 3];
+        w[L.dsc + ((size_t)sp * nz + kk) * nr + ii] = rd > 1e-300 ? rd : 1.0;
+      }
     }
     if (kin && ii >= 0 && ii <= nr) {
       background_full(a, face_r(c, ii), zc, q);
@@ -1140,6 +1327,21 @@ __global__ void __launch_bounds__(256) k_tables_2d(InitArgs a) {
   }
 }
 
+// store of the initial state: FP64, or FP32 with the dust scaled by its initial layer
+__device__ __forceinline__ void store_init(const InitArgs& a, int f, int k, int i, size_t cl,
+                                           double v) {
+  const Geo& g = a.g;
+  if (g.p32) {
+    if (f < 5) { ((float*)a.state)[(size_t)f * g.N + cl] = (float)v; return; }
+    const int sp = (f - 5) >> 2, c = (f - 5) & 3;
+    if (c == 3) { ((double*)a.state)[p32_f64_base(g) + (size_t)sp * g.N + cl] = v; return; }
+    v /= a.work[a.L.dsc + ((size_t)sp * g.nz + k) * g.nr + i];
+    ((float*)a.state)[(size_t)(5 + 3 * sp + c) * g.N + cl] = (float)v;
+  } else {
+    ((double*)a.state)[(size_t)f * g.N + cl] = v;
+  }
+}
+
 // Initial state: Sod annulus, or the disc with the column Gaussian vortex (streamfunction
 // psi = psi0 exp(-X^2/2 sr^2 - Y^2/2 sa^2), X = r - r_v, Y = r_v wrap(theta - theta_v),
 // centre vorticity 2 Ro Omega_K(r_v) with Ro = -amplitude), density noise
@@ -1162,7 +1364,7 @@ __global__ void __launch_bounds__(256) k_init_state(InitArgs a) {
     double q[MAXF];
     if (c.init_kind == RB_INIT_SOD) {
       background_full(a, r, z, q);
-      for (int f = 0; f < 5; ++f) a.state[(size_t)f * g.N + cl] = q[f];
+      for (int f = 0; f < 5; ++f) store_init(a, f, k, i, cl, q[f]);
       continue;
     }
     EqPoint e = eq_point(c, r, z);
@@ -1182,14 +1384,14 @@ __global__ void __launch_bounds__(256) k_init_state(InitArgs a) {
     const double xi = a.noise ? a.noise[cl] : 0.0;
     const double rho = e.rho * (1.0 + c.noise_amp * xi);
     gas_cons(c.gamma, rho, u, v, e.P, q);
-    for (int f = 0; f < 5; ++f) a.state[(size_t)f * g.N + cl] = q[f] - q0[f];
+    for (int f = 0; f < 5; ++f) store_init(a, f, k, i, cl, q[f] - q0[f]);
     for (int s = 0; s < c.n_dust; ++s) {
       const double rd = dust_layer(c, s, r, z);
       const int o = 5 + 4 * s;
-      a.state[(size_t)(o + 0) * g.N + cl] = rd * u;
-      a.state[(size_t)(o + 1) * g.N + cl] = rd * v;
-      a.state[(size_t)(o + 2) * g.N + cl] = 0.0;
-      a.state[(size_t)(o + 3) * g.N + cl] = rd;
+      store_init(a, o + 0, k, i, cl, rd * u);
+      store_init(a, o + 1, k, i, cl, rd * v);
+      store_init(a, o + 2, k, i, cl, 0.0);
+      store_init(a, o + 3, k, i, cl, rd);
     }
   }
 }
@@ -1203,29 +1405,34 @@ __global__ void k_fill(double* p, size_t n, double v) {
     p[q] = v;
 }
 
-// field f of the state -> full FP64 values (gas: E0 + E'; dust: as stored)
-__global__ void k_to_full(StageArgs a, const double* state, double* out, int f) {
+// field f of the state -> full FP64 values (gas: E0 + E'; dust: unscaled)
+template <bool P32>
+__global__ void k_to_full(StageArgs a, const void* state, double* out, int f) {
   const Geo& g = a.g;
   for (size_t c = (size_t)blockIdx.x * blockDim.x + threadIdx.x; c < g.N;
        c += (size_t)gridDim.x * blockDim.x) {
-    double v = state[(size_t)f * g.N + c];
-    if (f < 5) v += a.t.bgc[(c / g.nth) * 5 + f];
+    const size_t ki = c / g.nth;
+    double v = ld_cell<P32>(a, state, f, (int)(ki / g.nr), (int)(ki % g.nr), c);
+    if (f < 5) v += a.t.bgc[ki * 5 + f];
     out[c] = v;
   }
 }
-__global__ void k_from_full(StageArgs a, const double* in, double* state, int f) {
+template <bool P32>
+__global__ void k_from_full(StageArgs a, const double* in, void* state, int f) {
   const Geo& g = a.g;
   for (size_t c = (size_t)blockIdx.x * blockDim.x + threadIdx.x; c < g.N;
        c += (size_t)gridDim.x * blockDim.x) {
+    const size_t ki = c / g.nth;
     double v = in[c];
-    if (f < 5) v -= a.t.bgc[(c / g.nth) * 5 + f];
-    state[(size_t)f * g.N + c] = v;
+    if (f < 5) v -= a.t.bgc[ki * 5 + f];
+    st_cell<P32>(a, state, f, (int)(ki / g.nr), (int)(ki % g.nr), c, v);
   }
 }
 
 // mass of field f (density slot): per-block partial sums of rho V over fixed chunks,
 // each summed by a fixed tree (deterministic, FP64)
-__global__ void __launch_bounds__(256) k_mass(StageArgs a, const double* state, double* part, int f) {
+template <bool P32>
+__global__ void __launch_bounds__(256) k_mass(StageArgs a, const void* state, double* part, int f) {
   __shared__ double s_s[4];
   const Geo& g = a.g;
   const size_t chunk = (g.N + gridDim.x - 1) / gridDim.x;
@@ -1234,7 +1441,7 @@ __global__ void __launch_bounds__(256) k_mass(StageArgs a, const double* state, 
   for (size_t c = c0 + threadIdx.x; c < c1; c += blockDim.x) {
     const size_t ki = c / g.nth;
     const int i = (int)(ki % g.nr);
-    double v = state[(size_t)f * g.N + c];
+    double v = ld_cell<P32>(a, state, f, (int)(ki / g.nr), i, c);
     if (f < 5) v += a.t.bgc[ki * 5 + f];
     acc += v * a.t.rt[(size_t)i * RT_N + RT_V];
   }
@@ -1271,24 +1478,22 @@ hipError_t launch_init_state(const InitArgs& a, hipStream_t s) {
   return hipGetLastError();
 }
 
-template <int ND>
-static void stage_nd(const StageArgs& a, int blocks, hipStream_t s) {
-  const bool g75 = a.g.gamma == 1.4;
-  if (g75) hipLaunchKernelGGL((k_march<true, ND, true>), dim3(blocks), dim3(NT), 0, s, a, 0);
-  else hipLaunchKernelGGL((k_march<true, ND, false>), dim3(blocks), dim3(NT), 0, s, a, 0);
-  if (a.gas_only) return;
-  for (int sp = 0; sp < ND; ++sp)
-    hipLaunchKernelGGL((k_march<false, ND, true>), dim3(blocks), dim3(NT), 0, s, a, sp);
+template <int ND, bool P32>
+static void group_nd2(const StageArgs& a, int blocks, int group, hipStream_t s) {
+  if (group == 0) {
+    if (a.g.gamma == 1.4)
+      hipLaunchKernelGGL((k_march<true, ND, true, P32>), dim3(blocks), dim3(NT), 0, s, a, 0);
+    else
+      hipLaunchKernelGGL((k_march<true, ND, false, P32>), dim3(blocks), dim3(NT), 0, s, a, 0);
+  } else {
+    hipLaunchKernelGGL((k_march<false, ND, true, P32>), dim3(blocks), dim3(NT), 0, s, a, group - 1);
+  }
 }
 
 template <int ND>
 static void group_nd(const StageArgs& a, int blocks, int group, hipStream_t s) {
-  if (group == 0) {
-    if (a.g.gamma == 1.4) hipLaunchKernelGGL((k_march<true, ND, true>), dim3(blocks), dim3(NT), 0, s, a, 0);
-    else hipLaunchKernelGGL((k_march<true, ND, false>), dim3(blocks), dim3(NT), 0, s, a, 0);
-  } else {
-    hipLaunchKernelGGL((k_march<false, ND, true>), dim3(blocks), dim3(NT), 0, s, a, group - 1);
-  }
+  if (a.g.p32) group_nd2<ND, true>(a, blocks, group, s);
+  else group_nd2<ND, false>(a, blocks, group, s);
 }
 
 hipError_t launch_stage_group(const StageArgs& a, int blocks, int group, hipStream_t s) {
@@ -1304,26 +1509,30 @@ hipError_t launch_stage_group(const StageArgs& a, int blocks, int group, hipStre
 }
 
 hipError_t launch_stage(const StageArgs& a, int blocks, hipStream_t s) {
-  switch (a.g.nd) {
-    case 0: stage_nd<0>(a, blocks, s); break;
-    case 1: stage_nd<1>(a, blocks, s); break;
-    case 2: stage_nd<2>(a, blocks, s); break;
-    case 3: stage_nd<3>(a, blocks, s); break;
-    case 4: stage_nd<4>(a, blocks, s); break;
-    default: return hipErrorInvalidValue;
+  hipError_t e = launch_stage_group(a, blocks, 0, s);
+  if (e != hipSuccess || a.gas_only) return e;
+  for (int sp = 0; sp < a.g.nd; ++sp) {
+    e = launch_stage_group(a, blocks, 1 + sp, s);
+    if (e != hipSuccess) return e;
   }
-  return hipGetLastError();
+  return hipSuccess;
 }
 
-hipError_t launch_cfl(const StageArgs& a, const double* state, int blocks, int dt_idx,
+template <int ND>
+static void cfl_nd(const StageArgs& a, const void* state, int blocks, hipStream_t s) {
+  if (a.g.p32) hipLaunchKernelGGL((k_cfl<ND, true>), dim3(blocks), dim3(256), 0, s, a, state);
+  else hipLaunchKernelGGL((k_cfl<ND, false>), dim3(blocks), dim3(256), 0, s, a, state);
+}
+
+hipError_t launch_cfl(const StageArgs& a, const void* state, int blocks, int dt_idx,
                       hipStream_t s) {
   (void)dt_idx;
   switch (a.g.nd) {
-    case 0: hipLaunchKernelGGL(k_cfl<0>, dim3(blocks), dim3(256), 0, s, a, state); break;
-    case 1: hipLaunchKernelGGL(k_cfl<1>, dim3(blocks), dim3(256), 0, s, a, state); break;
-    case 2: hipLaunchKernelGGL(k_cfl<2>, dim3(blocks), dim3(256), 0, s, a, state); break;
-    case 3: hipLaunchKernelGGL(k_cfl<3>, dim3(blocks), dim3(256), 0, s, a, state); break;
-    case 4: hipLaunchKernelGGL(k_cfl<4>, dim3(blocks), dim3(256), 0, s, a, state); break;
+    case 0: cfl_nd<0>(a, state, blocks, s); break;
+    case 1: cfl_nd<1>(a, state, blocks, s); break;
+    case 2: cfl_nd<2>(a, state, blocks, s); break;
+    case 3: cfl_nd<3>(a, state, blocks, s); break;
+    case 4: cfl_nd<4>(a, state, blocks, s); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -1342,23 +1551,26 @@ hipError_t launch_fill(double* p, size_t n, double v, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_to_full(const StageArgs& a, const double* state, double* out, int f,
+hipError_t launch_to_full(const StageArgs& a, const void* state, double* out, int f,
                           hipStream_t s) {
   const int blocks = (int)std::min<size_t>((a.g.N + 255) / 256, 65536);
-  hipLaunchKernelGGL(k_to_full, dim3(blocks), dim3(256), 0, s, a, state, out, f);
+  if (a.g.p32) hipLaunchKernelGGL(k_to_full<true>, dim3(blocks), dim3(256), 0, s, a, state, out, f);
+  else hipLaunchKernelGGL(k_to_full<false>, dim3(blocks), dim3(256), 0, s, a, state, out, f);
   return hipGetLastError();
 }
 
-hipError_t launch_from_full(const StageArgs& a, const double* in, double* state, int f,
+hipError_t launch_from_full(const StageArgs& a, const double* in, void* state, int f,
                             hipStream_t s) {
   const int blocks = (int)std::min<size_t>((a.g.N + 255) / 256, 65536);
-  hipLaunchKernelGGL(k_from_full, dim3(blocks), dim3(256), 0, s, a, in, state, f);
+  if (a.g.p32) hipLaunchKernelGGL(k_from_full<true>, dim3(blocks), dim3(256), 0, s, a, in, state, f);
+  else hipLaunchKernelGGL(k_from_full<false>, dim3(blocks), dim3(256), 0, s, a, in, state, f);
   return hipGetLastError();
 }
 
-hipError_t launch_mass(const StageArgs& a, const double* state, double* partials, int f,
+hipError_t launch_mass(const StageArgs& a, const void* state, double* partials, int f,
                        int blocks, hipStream_t s) {
-  hipLaunchKernelGGL(k_mass, dim3(blocks), dim3(256), 0, s, a, state, partials, f);
+  if (a.g.p32) hipLaunchKernelGGL(k_mass<true>, dim3(blocks), dim3(256), 0, s, a, state, partials, f);
+  else hipLaunchKernelGGL(k_mass<false>, dim3(blocks), dim3(256), 0, s, a, state, partials, f);
   return hipGetLastError();
 }
 

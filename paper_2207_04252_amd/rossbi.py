@@ -85,6 +85,9 @@ def load() -> ctypes.CDLL:
     if not os.path.exists(LIB_PATH):
         raise RuntimeError(f"HIP library {LIB_PATH} is not built; run "
                            "`python -c 'import __graft_entry__ as g; g.build()'`")
+    # torch brings its own copy of the HIP runtime; it must be the one loaded when the
+    # library is, so that buffers and streams from torch belong to the library's runtime
+    import torch  # noqa: F401
     L = ctypes.CDLL(LIB_PATH)
     L.rb_query_sizes.argtypes = [ctypes.POINTER(rb_config), ctypes.POINTER(rb_buffers)]
     L.rb_init_state.argtypes = [ctypes.POINTER(rb_config), ctypes.POINTER(rb_buffers), _D, _D,
