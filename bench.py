@@ -25,6 +25,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
@@ -103,6 +105,52 @@ def precision_forms(rossbi, torch, steps):
     return out
 
 
+def adjoint_cost(rossbi, torch, steps, ckpt):
+    """Forward (rb_step), recorded forward (rb_record) and reverse sweep (rb_adjoint) of
+    the same CFL steps on the adjoint disc; the objective is the vortex-core dust mass."""
+    cfg = synth.C5_ADJOINT
+    xi = synth.noise(cfg)
+    log(f"adjoint: {cfg.name}, {steps} steps, checkpoints every {ckpt}")
+    sim = rossbi.Sim(cfg, noise=xi)
+    sim.step(2, check=True)
+    sim.set_fields(sim.fields())  # same state for all three runs below
+    x0 = sim.fields()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, dts = sim.step(steps, check=True)
+    torch.cuda.synchronize()
+    t_fwd = time.perf_counter() - t0
+    sim.set_fields(x0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.record(steps, ckpt, dt_list=dts)
+    torch.cuda.synchronize()
+    t_rec = time.perf_counter() - t0
+    lam = np.zeros((cfg.n_fields, cfg.nz, cfg.nr, cfg.nth))
+    rc = rossbi.cell_centres_r(cfg)
+    th = (np.arange(cfg.nth) + 0.5) * 2 * np.pi / cfg.nth
+    core = ((rc >= synth.CORE_R[0]) & (rc <= synth.CORE_R[1]))[:, None] & \
+           (np.abs(th - cfg.vortex_th0) < synth.CORE_DTH)[None, :]
+    lam[8] = (rossbi.cell_volumes(cfg)[:, None] * core)[None]
+    lam_d = torch.as_tensor(lam, device="cuda")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    g0, gst = sim.adjoint(lam_d)
+    torch.cuda.synchronize()
+    t_adj = time.perf_counter() - t0
+    sim.close()
+    fwd = 1e3 * t_fwd / steps
+    adj = 1e3 * t_adj / steps
+    return {"workload": cfg.name, "cells": cfg.n_cells, "steps": steps, "ckpt_every": ckpt,
+            "forward_ms_per_step": round(fwd, 4),
+            "record_ms_per_step": round(1e3 * t_rec / steps, 4),
+            "adjoint_ms_per_step": round(adj, 4),
+            "adjoint_over_forward": round(adj / fwd, 3),
+            "reverse_only_over_forward": round((adj - fwd) / fwd, 3),
+            "note": "adjoint = recompute of each checkpoint segment (one forward step per step) "
+                    "+ two transposed stage operators per step; dJ/dSt = %.6e" % gst[0]}
+
+
 def cpu_baseline(cfg, xi, budget_s):
     import oracle
     o = oracle.Oracle(cfg, noise=xi)
@@ -131,6 +179,8 @@ def main():
     ap.add_argument("--no-forms", action="store_true",
                     help="skip the FP64 / FP32-perturbation comparison on the dust discs")
     ap.add_argument("--forms-steps", type=int, default=40)
+    ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint cost measurement")
+    ap.add_argument("--adjoint-steps", type=int, default=200)
     ap.add_argument("--calib", action="store_true",
                     help="first copy 256 MiB device to device 3 times (counter calibration)")
     args = ap.parse_args()
@@ -202,6 +252,8 @@ def main():
     del sim
     if not args.no_forms:
         out["precision_forms"] = precision_forms(rossbi, torch, args.forms_steps)
+    if not args.no_adjoint:
+        out["adjoint"] = adjoint_cost(rossbi, torch, args.adjoint_steps, 20)
     if not args.no_cpu:
         log("cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(cfg, xi, args.cpu_seconds)

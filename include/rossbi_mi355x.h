@@ -111,6 +111,7 @@ typedef struct {
   double mass[5];         /* total gas mass, then each dust species                  */
   double outflow[5];      /* boundary mass outflow rate of the last second stage     */
   double dt_last;         /* last time step                                          */
+  int64_t fp64_resolves;  /* FP32-perturbation faces re-solved by the FP64 solver    */
 } rb_diag;
 
 typedef struct rb_ctx rb_ctx;
@@ -164,6 +165,47 @@ rb_status rb_diagnostics(rb_ctx* ctx, rb_diag* out);
  * each).  Enabling resets the totals. */
 rb_status rb_profile(rb_ctx* ctx, int enable);
 rb_status rb_profile_read(rb_ctx* ctx, double* total_ms, int64_t* launches);
+
+/* ---- discrete adjoint (FP64 precision only) --------------------------------------
+ *
+ * The adjoint of n RK2 steps is taken in two calls.  rb_record advances n steps like
+ * rb_step (same dt policies) and keeps a checkpoint of the state every ckpt_every steps
+ * and the time steps used.  rb_adjoint then sweeps backwards: for each checkpoint
+ * segment it recomputes the segment's states E^m and midpoints E* with the stage
+ * kernels and applies the transposed stage Jacobians (Sect. 2.5: E* = E^m + dt/(2V)
+ * (G(E^m) - R0), E^{m+1} = E^m + dt/V (G(E*) - R0)), the face fluxes differentiated on
+ * the branches the primal solves took (Riemann wave pattern, limiter, fallbacks) and
+ * p* by implicit differentiation of the pressure-function equation (Sect. 2.6).  The
+ * time steps are held fixed (the recorded ones).
+ *
+ * Workspace: caller-owned device memory of the size rb_adjoint_workspace returns
+ * (two state-sized vectors, ceil(n / ckpt_every) checkpoints, 2 ckpt_every - 1 segment
+ * states, Stokes partials); it must stay untouched between rb_record and rb_adjoint.
+ * Device vectors lambda_final and grad_state0 are FP64 fields in the layout of
+ * rb_get_fields ([field][k][i][j]); a gradient with respect to the full state equals
+ * the one with respect to the stored deviation.  Errors: RB_EINVAL for the FP32
+ * form, n < 1, ckpt_every < 1, a workspace that is too small, or rb_adjoint without a
+ * matching rb_record; device errors as rb_step. */
+rb_status rb_adjoint_workspace(const rb_ctx* ctx, int n, int ckpt_every, size_t* bytes);
+
+/* Advances n steps from the current state (as rb_step) and records checkpoints and time
+ * steps in the workspace.  dt_out (host, n entries, may be NULL) receives the steps. */
+rb_status rb_record(rb_ctx* ctx, int n, int ckpt_every, const rb_dt_policy* policy,
+                    double* dt_out, void* workspace, size_t workspace_bytes);
+
+/* Reverse sweep over the recorded steps.  lambda_final: dJ/dE after the n steps;
+ * grad_state0 receives dJ/dE before them; grad_stokes (host, n_dust entries, may be
+ * NULL) receives dJ/dSt of each dust species (constant-Stokes drag, Sect. 2.9).  The
+ * context's state is left at the end of the recorded steps. */
+rb_status rb_adjoint(rb_ctx* ctx, const void* lambda_final, void* grad_state0,
+                     double* grad_stokes, void* workspace, size_t workspace_bytes);
+
+/* Contracts a state cotangent lam (device, layout of rb_get_fields) with the derivative
+ * of the initial disc state with respect to the per-cell vortex amplitude: out[cell] =
+ * sum_f lam[f][cell] dE_f/dA(cell).  noise and amp (host, ncells each, may be NULL) must
+ * be those given to rb_init_state; out is a device array of ncells doubles. */
+rb_status rb_amp_gradient(rb_ctx* ctx, const double* noise, const double* amp, const void* lam,
+                          void* out);
 
 /* Message describing the last error on ctx; valid until the next call on ctx. */
 const char* rb_last_error(const rb_ctx* ctx);

@@ -129,6 +129,8 @@ def lib() -> ctypes.CDLL:
         L.or_threads.restype = ctypes.c_int
         L.or_count_ops.restype = ctypes.c_double
         L.or_count_ops.argtypes = [ctypes.POINTER(OrConfig), _D]
+        L.or_tangent_state.restype = ctypes.c_int
+        L.or_tangent_state.argtypes = [ctypes.POINTER(OrConfig), _D, _D, _D, ctypes.c_int, _D, _D, _D]
         _lib = L
     return _lib
 
@@ -279,6 +281,22 @@ def tangent(cfg: synth.Config, noise, amp, amp_dot, st_dot, dt_list):
                               len(dts), _ptr(dts), synth.CORE_R[0], synth.CORE_R[1], synth.CORE_DTH,
                               _ptr(J), _ptr(dJ))
     return status, J[0], dJ[0]
+
+
+def tangent_state(cfg: synth.Config, state0, dstate0, st_dot, dt_list):
+    """Forward-mode derivative of len(dt_list) steps from state0 along (dstate0, st_dot).
+    Returns (status, final state, its tangent)."""
+    s = to_struct(cfg)
+    shape = (cfg.n_fields, cfg.nz, cfg.nr, cfg.nth)
+    x0 = _f64(state0)
+    dx0 = _f64(dstate0)
+    st = _f64(np.zeros(4) if st_dot is None else np.pad(np.asarray(st_dot, float), (0, 4 - len(st_dot))))
+    dts = _f64(dt_list)
+    out = np.empty(shape)
+    dout = np.empty(shape)
+    status = lib().or_tangent_state(ctypes.byref(s), _ptr(x0), _ptr(dx0), _ptr(st), len(dts),
+                                    _ptr(dts), _ptr(out), _ptr(dout))
+    return status, out, dout
 
 
 def count_ops(cfg: synth.Config, noise=None) -> float:

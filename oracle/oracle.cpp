@@ -1250,4 +1250,24 @@ int or_tangent(const OrConfig* cfg, const double* noise, const double* amp, cons
   return st;
 }
 
+/* Tangent-linear run from a given state: the state carries the tangent dstate0 and the
+ * Stokes numbers the tangents st_dot; n steps with the given dt list.  Outputs the final
+ * state and its tangent (both nfields x ncells, full values). */
+int or_tangent_state(const OrConfig* cfg, const double* state0, const double* dstate0,
+                     const double* st_dot, int n, const double* dt_list, double* state_out,
+                     double* dstate_out) {
+  Sim<Dual> s;
+  if (!s.setup(*cfg)) return OR_EINVAL;
+  for (int q = 0; q < s.nd; ++q) s.stokes[q] = Dual(cfg->stokes[q], st_dot ? st_dot[q] : 0.0);
+  if (s.c.balanced) s.empty_run();
+  const size_t M = (size_t)s.nf * s.N;
+  for (size_t q = 0; q < M; ++q) s.E[q] = Dual(state0[q], dstate0 ? dstate0[q] : 0.0);
+  int st = s.run(n, 2, 0.0, dt_list, nullptr);
+  for (size_t q = 0; q < M; ++q) {
+    state_out[q] = s.E[q].v;
+    dstate_out[q] = s.E[q].d;
+  }
+  return st;
+}
+
 }  // extern "C"

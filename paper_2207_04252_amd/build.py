@@ -11,7 +11,7 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB_NAME = "librossbi_mi355x.so"
 LIB_PATH = os.path.join(HERE, LIB_NAME)
-SOURCES = ["rb_kernels.hip", "rb_api.hip"]
+SOURCES = ["rb_kernels.hip", "rb_adjoint.hip", "rb_api.hip"]
 
 # Device code: no packed FP32 instructions (-packed-fp32-ops), contraction only within
 # an expression, no fast-math.
@@ -29,9 +29,25 @@ def hipcc() -> str:
 
 
 def build(verbose: bool = False, extra: list[str] | None = None) -> str:
+    """Compile every source to an object (in parallel), then link the shared library."""
+    obj_dir = os.path.join(HERE, "_build")
+    os.makedirs(obj_dir, exist_ok=True)
+    flags = [f for f in HIPCC_FLAGS if f != "-shared"] + (extra or [])
+    procs = []
+    objs = []
+    for src in SOURCES:
+        obj = os.path.join(obj_dir, os.path.splitext(src)[0] + ".o")
+        cmd = [hipcc()] + flags + ["-I", INCLUDE, "-I", CSRC, "-c", os.path.join(CSRC, src),
+                                   "-o", obj]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        procs.append((src, subprocess.Popen(cmd)))
+        objs.append(obj)
+    failed = [src for src, p in procs if p.wait() != 0]
+    if failed:
+        raise RuntimeError(f"hipcc failed on {failed}")
     tmp = LIB_PATH + ".tmp"
-    cmd = [hipcc()] + HIPCC_FLAGS + (extra or []) + ["-I", INCLUDE, "-I", CSRC, "-o", tmp] + [
-        os.path.join(CSRC, s) for s in SOURCES]
+    cmd = [hipcc(), "--offload-arch=gfx950", "-fPIC", "-shared", "-o", tmp] + objs
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)

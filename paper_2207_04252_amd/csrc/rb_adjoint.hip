@@ -1,0 +1,803 @@
+// Discrete adjoint of the RK2 stage operator on gfx950 (FP64).
+//
+// A stage is E_out = base + c dt V^-1 (G(E) - R0).  Given a cotangent lambda of E_out,
+// the kernels here form J_G(E)^T w with w = c dt V^-1 lambda: the reverse of every
+// face flux -- the exact Riemann solution differentiated on the wave pattern the
+// primal solve took (star pressure by implicit differentiation of the pressure-function
+// equation, Sect. 2.6), the limited parabolic reconstruction on the limiter branch taken
+// (Sect. 2.7), the positivity fallback on the side it was taken -- scattered back to the
+// four cells of each face stencil, plus the cell-local reverse of the geometric and
+// gravity sources and of the gas-dust drag (Sect. 2.9, App. B).  The primal face
+// solves are recomputed with the forward solver itself (recording variant), so every
+// branch decision is the forward run's.
+//
+// Layout follows the forward stage kernel: a workgroup owns a 64 (theta) x 8 (r) tile
+// and marches through a chunk of z planes.  Each plane is staged in LDS with a
+// three-cell halo (a cell receives contributions from the faces 3/2 cells away); the
+// contributions of the theta and r faces to the tile's cells are accumulated in LDS in
+// a fixed order, one phase per stencil position, so results are deterministic.  The z
+// faces run from registers, one plane behind.
+#include "rb_device.h"
+
+namespace rb {
+
+// ------------------------------------------------------------------------------------
+// reverse of the building blocks
+
+// which argument minmod3 returned: 0 the first, 1 the second, 2 the third, 3 none (zero)
+__device__ __forceinline__ int minmod3_arg(double x, double y, double z) {
+  if (x > 0.0 && y > 0.0 && z > 0.0) return x <= fmin(y, z) ? 0 : (y <= z ? 1 : 2);
+  if (x < 0.0 && y < 0.0 && z < 0.0) return x >= fmax(y, z) ? 0 : (y >= z ? 1 : 2);
+  return 3;
+}
+
+// Derivative (cm, cp) of a limited face increment with respect to the backward and
+// forward differences dm = e0 - em, dp = ep - e0, on the branch the limiter took (the
+// arguments are the forward increments' own expressions).
+__device__ __forceinline__ void dinc_up_u(double em, double e0, double ep, double& cm, double& cp) {
+  const double dm = e0 - em, dp = ep - e0;
+  switch (minmod3_arg(fma(3.0, dp, dm) * 0.125, dm, dp)) {
+    case 0: cm = 0.125; cp = 0.375; break;
+    case 1: cm = 1.0; cp = 0.0; break;
+    case 2: cm = 0.0; cp = 1.0; break;
+    default: cm = 0.0; cp = 0.0;
+  }
+}
+__device__ __forceinline__ void dinc_lo_u(double em, double e0, double ep, double& cm, double& cp) {
+  const double dm = e0 - em, dp = ep - e0;
+  switch (minmod3_arg(-(fma(3.0, dm, dp) * 0.125), -dm, -dp)) {
+    case 0: cm = -0.375; cp = -0.125; break;
+    case 1: cm = -1.0; cp = 0.0; break;
+    case 2: cm = 0.0; cp = -1.0; break;
+    default: cm = 0.0; cp = 0.0;
+  }
+}
+__device__ __forceinline__ void dinc_up_c(double em, double e0, double ep, const double* co,
+                                          double& cm, double& cp) {
+  const double dm = e0 - em, dp = ep - e0;
+  switch (minmod3_arg(fma(co[RC_WPP], dp, co[RC_WPM] * dm), co[RC_LPM] * dm, co[RC_LPP] * dp)) {
+    case 0: cm = co[RC_WPM]; cp = co[RC_WPP]; break;
+    case 1: cm = co[RC_LPM]; cp = 0.0; break;
+    case 2: cm = 0.0; cp = co[RC_LPP]; break;
+    default: cm = 0.0; cp = 0.0;
+  }
+}
+__device__ __forceinline__ void dinc_lo_c(double em, double e0, double ep, const double* co,
+                                          double& cm, double& cp) {
+  const double dm = e0 - em, dp = ep - e0;
+  switch (minmod3_arg(fma(co[RC_WMP], dp, co[RC_WMM] * dm), co[RC_LMM] * dm, co[RC_LMP] * dp)) {
+    case 0: cm = co[RC_WMM]; cp = co[RC_WMP]; break;
+    case 1: cm = co[RC_LMM]; cp = 0.0; break;
+    case 2: cm = 0.0; cp = co[RC_LMP]; break;
+    default: cm = 0.0; cp = 0.0;
+  }
+}
+
+// One side's pressure function at p and its partial derivatives: df/dp, and df/drho_K,
+// df/dp_K at fixed p (shock: f = (p - p_K) sqrt(A/(p + B)); rarefaction:
+// f = 2 c_K/(g-1) ((p/p_K)^((g-1)/2g) - 1)).
+struct PD {
+  double f, df, fr, fp;
+};
+template <bool G75>
+__device__ __forceinline__ PD pfun_pd(double p, double rK, double pK, double cK, const GasC& c) {
+  PD o;
+  if (p > pK) {
+    const double ipb = 1.0 / (p + c.kshock * pK);
+    const double q = sqrt(c.a2 / rK * ipb);
+    o.f = (p - pK) * q;
+    o.df = q * (1.0 - 0.5 * (p - pK) * ipb);
+    o.fr = -0.5 * o.f / rK;
+    o.fp = -q - 0.5 * o.f * c.kshock * ipb;
+  } else {
+    Pow3<G75> w(p / pK, c);
+    o.f = c.g2m1 * cK * (w.p17 - 1.0);
+    o.df = w.pm67 / (rK * cK);
+    o.fr = -0.5 * o.f / rK;
+    o.fp = 0.5 * o.f / pK - cK * w.p17 / (c.g * pK);
+  }
+  return o;
+}
+
+// Reverse of F(W) for the sampled primitive state W = (rho, un, t1, t2, p); flb in the
+// order mass, normal momentum, two tangential momenta, energy.  Output: W cotangent.
+__device__ __forceinline__ void flux_rev(const GasC& c, const GasRec& w, const double flb[5],
+                                         double Wb[5]) {
+  const double m = w.rho * w.un;
+  const double ke = 0.5 * (w.un * w.un + w.t1 * w.t1 + w.t2 * w.t2);
+  const double en = w.p * c.inv_gm1 + w.rho * ke;
+  const double mb = flb[0] + flb[1] * w.un + flb[2] * w.t1 + flb[3] * w.t2;
+  const double enb = flb[4] * w.un;
+  Wb[0] = enb * ke + mb * w.un;
+  Wb[1] = flb[1] * m + flb[4] * (en + w.p) + enb * w.rho * w.un + mb * w.rho;
+  Wb[2] = flb[2] * m + enb * w.rho * w.t1;
+  Wb[3] = flb[3] * m + enb * w.rho * w.t2;
+  Wb[4] = flb[1] + flb[4] * w.un + enb * c.inv_gm1;
+}
+
+// Reverse of the Riemann solution at x/t = 0 on the recorded wave pattern: W cotangent
+// -> cotangents of the primitive face states WL, WR (rho, un, t1, t2, p).  The star
+// state depends on the face states directly and through p*, u*:
+//   f_L(p*) + f_R(p*) + u_R - u_L = 0,  u* = (u_L + u_R)/2 + (f_R(p*) - f_L(p*))/2.
+template <bool G75>
+__device__ void riemann_rev(const GasC& c, const double* WL, const double* WR, const GasRec& rec,
+                            const double* Wb, double* WLb, double* WRb) {
+#pragma unroll
+  for (int q = 0; q < 5; ++q) { WLb[q] = 0.0; WRb[q] = 0.0; }
+  const int br = rec.branch;
+  if (br == GR_LEFT) {
+#pragma unroll
+    for (int q = 0; q < 5; ++q) WLb[q] = Wb[q];
+    return;
+  }
+  if (br == GR_RIGHT) {
+#pragma unroll
+    for (int q = 0; q < 5; ++q) WRb[q] = Wb[q];
+    return;
+  }
+  if (br == GR_VACUUM) return;
+  if (br == GR_FAN_L || br == GR_FAN_R) {
+    // inside a fan: c_c = 2/(g+1) (c_K +- (g-1)/2 u_K), rho = rho_K (c_c/c_K)^(2/(g-1)),
+    // p = p_K (c_c/c_K)^(2g/(g-1)), un = +-c_c
+    const bool left = br == GR_FAN_L;
+    const double* W = left ? WL : WR;
+    double* Wk = left ? WLb : WRb;
+    const double sg = left ? 1.0 : -1.0;
+    const double rK = W[0], uK = W[1], pK = W[4];
+    const double cK = sqrt(c.g * pK / rK);
+    const double cc = c.a2 * (cK + sg * c.half_gm1 * uK);
+    const double ratio = cc / cK;
+    const double e1 = c.g2m1, e2 = 2.0 * c.g / (c.g - 1.0);
+    const double r1 = pow(ratio, e1 - 1.0), r2 = pow(ratio, e2 - 1.0);
+    const double ratb = Wb[0] * rK * e1 * r1 + Wb[4] * pK * e2 * r2;
+    Wk[0] += Wb[0] * r1 * ratio;
+    Wk[4] += Wb[4] * r2 * ratio;
+    const double ccb = sg * Wb[1] + ratb / cK;
+    const double cKb = -ratb * cc / (cK * cK) + c.a2 * ccb;
+    Wk[1] += sg * c.a2 * c.half_gm1 * ccb;
+    Wk[4] += cKb * cK / (2.0 * pK);
+    Wk[0] -= cKb * cK / (2.0 * rK);
+    Wk[2] += Wb[2];
+    Wk[3] += Wb[3];
+    return;
+  }
+  // star states
+  const bool left = br == GR_STAR_L_SHOCK || br == GR_STAR_L_RARE;
+  const double* W = left ? WL : WR;
+  double* Wk = left ? WLb : WRb;
+  const double ps = rec.ps;
+  double psb = Wb[4];
+  const double usb = Wb[1];
+  Wk[2] += Wb[2];
+  Wk[3] += Wb[3];
+  const double rK = W[0], pK = W[4];
+  if (br == GR_STAR_L_SHOCK || br == GR_STAR_R_SHOCK) {
+    // rho* = rho_K (q + k)/(k q + 1), q = p*/p_K, k = (g-1)/(g+1)
+    const double q = ps / pK, k = c.kshock, den = k * q + 1.0;
+    Wk[0] += Wb[0] * (q + k) / den;
+    const double qb = Wb[0] * rK * (1.0 - k * k) / (den * den);
+    psb += qb / pK;
+    Wk[4] -= qb * q / pK;
+  } else {
+    // rho* = rho_K (p*/p_K)^(1/g)
+    const double rho = rec.rho;
+    Wk[0] += Wb[0] * rho / rK;
+    psb += Wb[0] * rho / (c.g * ps);
+    Wk[4] -= Wb[0] * rho / (c.g * pK);
+  }
+  const double cL = sqrt(c.g * WL[4] / WL[0]), cR = sqrt(c.g * WR[4] / WR[0]);
+  const PD L = pfun_pd<G75>(ps, WL[0], WL[4], cL, c);
+  const PD R = pfun_pd<G75>(ps, WR[0], WR[4], cR, c);
+  // u*
+  WLb[1] += 0.5 * usb;
+  WRb[1] += 0.5 * usb;
+  psb += 0.5 * usb * (R.df - L.df);
+  WRb[0] += 0.5 * usb * R.fr;
+  WRb[4] += 0.5 * usb * R.fp;
+  WLb[0] -= 0.5 * usb * L.fr;
+  WLb[4] -= 0.5 * usb * L.fp;
+  // p*: dp* = -(dPhi) / (f_L' + f_R')
+  const double s = psb / (L.df + R.df);
+  WLb[1] += s;
+  WRb[1] -= s;
+  WLb[0] -= s * L.fr;
+  WLb[4] -= s * L.fp;
+  WRb[0] -= s * R.fr;
+  WRb[4] -= s * R.fp;
+}
+
+// Reverse of the face-frame primitives of a conservative gas state q (field order).
+template <int DIR>
+__device__ __forceinline__ void prim_rev(const double q[5], double gm1, const double Wb[5],
+                                         double qb[5]) {
+  const double ir = 1.0 / q[4];
+  const double vel[3] = {q[0] * ir, q[1] * ir, q[2] * ir};
+  double vb[3];
+  vb[Dirs<DIR>::n] = Wb[1];
+  vb[Dirs<DIR>::t1] = Wb[2];
+  vb[Dirs<DIR>::t2] = Wb[3];
+  const double pb = Wb[4] * gm1;
+  double dot = 0.0, v2 = 0.0;
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    qb[i] = vb[i] * ir - pb * vel[i];
+    dot += vb[i] * vel[i];
+    v2 += vel[i] * vel[i];
+  }
+  qb[3] = pb;
+  qb[4] = Wb[0] + 0.5 * pb * v2 - ir * dot;
+}
+
+// Reverse of one gas face: Fb (field order) is the cotangent of the face flux; the
+// contributions to the stencil cells A, B | C, D are added to cA..cD.
+template <int DIR, bool G75>
+__device__ void gas_face_vjp(const GasC& c, const double* eA, const double* eB, const double* eC,
+                             const double* eD, const double* coB, const double* coC,
+                             const double* bgf, const double* cenB, double sB,
+                             const double* cenC, double sC, const double* Fb, double* cA,
+                             double* cB, double* cC, double* cD) {
+  double qL[5], qR[5], cmB[5], cpB[5], cmC[5], cpC[5];
+#pragma unroll
+  for (int f = 0; f < 5; ++f) {
+    double iB, iC;
+    if (DIR == 0) {
+      iB = inc_up_c(eA[f], eB[f], eC[f], coB);
+      iC = inc_lo_c(eB[f], eC[f], eD[f], coC);
+      dinc_up_c(eA[f], eB[f], eC[f], coB, cmB[f], cpB[f]);
+      dinc_lo_c(eB[f], eC[f], eD[f], coC, cmC[f], cpC[f]);
+    } else {
+      iB = inc_up_u(eA[f], eB[f], eC[f]);
+      iC = inc_lo_u(eB[f], eC[f], eD[f]);
+      dinc_up_u(eA[f], eB[f], eC[f], cmB[f], cpB[f]);
+      dinc_lo_u(eB[f], eC[f], eD[f], cmC[f], cpC[f]);
+    }
+    qL[f] = bgf[f] + (eB[f] + iB);
+    qR[f] = bgf[f] + (eC[f] + iC);
+  }
+  Prim5 L = gas_prim<DIR>(qL, c.gm1);
+  Prim5 R = gas_prim<DIR>(qR, c.gm1);
+  bool fbL = false, fbR = false;
+  if (!(L.rho > 0.0 && L.p > 0.0)) {
+#pragma unroll
+    for (int f = 0; f < 5; ++f) qL[f] = cenB[f] + sB * eB[f];
+    L = gas_prim<DIR>(qL, c.gm1);
+    fbL = true;
+  }
+  if (!(R.rho > 0.0 && R.p > 0.0)) {
+#pragma unroll
+    for (int f = 0; f < 5; ++f) qR[f] = cenC[f] + sC * eC[f];
+    R = gas_prim<DIR>(qR, c.gm1);
+    fbR = true;
+  }
+  double fl[5];
+  TStat st = {0, 0, 0, 0, 0};
+  GasRec rec;
+  gas_riemann<G75, true>(c, L.rho, L.irho, L.un, L.t1, L.t2, L.p, R.rho, R.irho, R.un, R.t1, R.t2,
+                         R.p, fl, st, &rec);
+  const double flb[5] = {Fb[4], Fb[Dirs<DIR>::n], Fb[Dirs<DIR>::t1], Fb[Dirs<DIR>::t2], Fb[3]};
+  double Wb[5];
+  flux_rev(c, rec, flb, Wb);
+  const double WL[5] = {L.rho, L.un, L.t1, L.t2, L.p};
+  const double WR[5] = {R.rho, R.un, R.t1, R.t2, R.p};
+  double WLb[5], WRb[5];
+  riemann_rev<G75>(c, WL, WR, rec, Wb, WLb, WRb);
+  double qLb[5], qRb[5];
+  prim_rev<DIR>(qL, c.gm1, WLb, qLb);
+  prim_rev<DIR>(qR, c.gm1, WRb, qRb);
+#pragma unroll
+  for (int f = 0; f < 5; ++f) {
+    if (fbL) {
+      cB[f] += sB * qLb[f];
+    } else {
+      cA[f] -= cmB[f] * qLb[f];
+      cB[f] += (1.0 + cmB[f] - cpB[f]) * qLb[f];
+      cC[f] += cpB[f] * qLb[f];
+    }
+    if (fbR) {
+      cC[f] += sC * qRb[f];
+    } else {
+      cB[f] -= cmC[f] * qRb[f];
+      cC[f] += (1.0 + cmC[f] - cpC[f]) * qRb[f];
+      cD[f] += cpC[f] * qRb[f];
+    }
+  }
+}
+
+// Reverse of one dust face (variables reconstructed whole; a negative face density
+// falls back to the cell value).
+template <int DIR>
+__device__ void dust_face_vjp(const double* eA, const double* eB, const double* eC,
+                              const double* eD, const double* coB, const double* coC,
+                              const double* Fb, double* cA, double* cB, double* cC, double* cD) {
+  double qL[4], qR[4], cmB[4], cpB[4], cmC[4], cpC[4];
+#pragma unroll
+  for (int f = 0; f < 4; ++f) {
+    double iB, iC;
+    if (DIR == 0) {
+      iB = inc_up_c(eA[f], eB[f], eC[f], coB);
+      iC = inc_lo_c(eB[f], eC[f], eD[f], coC);
+      dinc_up_c(eA[f], eB[f], eC[f], coB, cmB[f], cpB[f]);
+      dinc_lo_c(eB[f], eC[f], eD[f], coC, cmC[f], cpC[f]);
+    } else {
+      iB = inc_up_u(eA[f], eB[f], eC[f]);
+      iC = inc_lo_u(eB[f], eC[f], eD[f]);
+      dinc_up_u(eA[f], eB[f], eC[f], cmB[f], cpB[f]);
+      dinc_lo_u(eB[f], eC[f], eD[f], cmC[f], cpC[f]);
+    }
+    qL[f] = eB[f] + iB;
+    qR[f] = eC[f] + iC;
+  }
+  const bool fbL = qL[3] < 0.0, fbR = qR[3] < 0.0;
+  if (fbL) {
+#pragma unroll
+    for (int f = 0; f < 4; ++f) qL[f] = eB[f];
+  }
+  if (fbR) {
+#pragma unroll
+    for (int f = 0; f < 4; ++f) qR[f] = eC[f];
+  }
+  double vL[3] = {0.0, 0.0, 0.0}, vR[3] = {0.0, 0.0, 0.0}, iL = 0.0, iR = 0.0;
+  if (qL[3] > 0.0) {
+    iL = 1.0 / qL[3];
+    vL[0] = qL[0] * iL; vL[1] = qL[1] * iL; vL[2] = qL[2] * iL;
+  }
+  if (qR[3] > 0.0) {
+    iR = 1.0 / qR[3];
+    vR[0] = qR[0] * iR; vR[1] = qR[1] * iR; vR[2] = qR[2] * iR;
+  }
+  double fl[4];
+  int side;
+  dust_riemann<true>(qL[3], vL[Dirs<DIR>::n], vL[Dirs<DIR>::t1], vL[Dirs<DIR>::t2], qR[3],
+                     vR[Dirs<DIR>::n], vR[Dirs<DIR>::t1], vR[Dirs<DIR>::t2], fl, &side);
+  const double flb[4] = {Fb[3], Fb[Dirs<DIR>::n], Fb[Dirs<DIR>::t1], Fb[Dirs<DIR>::t2]};
+  double qLb[4] = {0.0, 0.0, 0.0, 0.0}, qRb[4] = {0.0, 0.0, 0.0, 0.0};
+  // one side's flux (r u, r u^2, r u a, r u b) in terms of (r, u, a, b) = (rho, m/rho)
+  auto side_rev = [&](const double* q, const double* v, double inv, double wgt, double* qb) {
+    const double r = q[3];
+    if (!(r > 0.0)) return;
+    const double u = v[Dirs<DIR>::n], ta = v[Dirs<DIR>::t1], tb = v[Dirs<DIR>::t2];
+    const double rb = wgt * (flb[0] * u + flb[1] * u * u + flb[2] * u * ta + flb[3] * u * tb);
+    const double ub = wgt * (flb[0] * r + 2.0 * flb[1] * r * u + flb[2] * r * ta + flb[3] * r * tb);
+    const double ab = wgt * flb[2] * r * u, bb = wgt * flb[3] * r * u;
+    qb[Dirs<DIR>::n] += ub * inv;
+    qb[Dirs<DIR>::t1] += ab * inv;
+    qb[Dirs<DIR>::t2] += bb * inv;
+    qb[3] += rb - inv * (ub * u + ab * ta + bb * tb);
+  };
+  if (side == -1) side_rev(qL, vL, iL, 1.0, qLb);
+  else if (side == 1) side_rev(qR, vR, iR, 1.0, qRb);
+  else if (side == 0) {
+    side_rev(qL, vL, iL, 0.5, qLb);
+    side_rev(qR, vR, iR, 0.5, qRb);
+  }
+#pragma unroll
+  for (int f = 0; f < 4; ++f) {
+    if (fbL) {
+      cB[f] += qLb[f];
+    } else {
+      cA[f] -= cmB[f] * qLb[f];
+      cB[f] += (1.0 + cmB[f] - cpB[f]) * qLb[f];
+      cC[f] += cpB[f] * qLb[f];
+    }
+    if (fbR) {
+      cC[f] += qRb[f];
+    } else {
+      cB[f] -= cmC[f] * qRb[f];
+      cC[f] += (1.0 + cmC[f] - cpC[f]) * qRb[f];
+      cD[f] += cpC[f] * qRb[f];
+    }
+  }
+}
+
+// ------------------------------------------------------------------------------------
+// the adjoint stage kernel
+
+template <bool GAS, int ND, bool G75>
+__global__ void __launch_bounds__(NT) k_adj(AdjArgs A, int species) {
+  constexpr int NG = GAS ? 5 : 4;
+  constexpr int H = 3;
+  __shared__ double s_e[NG][TI + 2 * H][TJ + 2 * H];
+  __shared__ double s_at[NG][TI][TJ];
+  __shared__ double s_ar[NG][TI][TJ];
+  __shared__ double s_red[NT / 64];
+
+  const StageArgs& a = A.s;
+  const Geo& g = a.g;
+  const GasC gc = gas_consts(g.gamma);
+  const int F0 = GAS ? 0 : 5 + 4 * species;
+  const int tile = xcd_tile(blockIdx.x, gridDim.x);
+  const int tjb = tile % a.ntj;
+  const int tib = (tile / a.ntj) % a.nti;
+  const int kcb = tile / (a.ntj * a.nti);
+  const int tid = threadIdx.x, tj = tid & (TJ - 1), ti = tid / TJ;
+  const int j0 = tjb * TJ, i0 = tib * TI;
+  const int k0 = kcb * A.tk, k1 = min(g.nz, k0 + A.tk);
+  const int jg = j0 + tj;
+  const int ig = i0 + ti;
+  const bool act = jg < g.nth && ig < g.nr;
+  const bool colok = jg < g.nth;
+  const int igc = min(ig, g.nr - 1);
+  const bool twod = g.twod != 0;
+  const double* E = (const double*)a.in;
+  const double* cot = A.cot;
+  const size_t N = g.N;
+  const double cw = A.cw;
+  const double* rt = a.t.rt + (size_t)igc * RT_N;
+  const double invV = rt[RT_INVV], Az = rt[RT_AZ], invrc = rt[RT_INVRC], omk = rt[RT_OMK];
+
+  using DR = std::integral_constant<int, 0>;
+  using DT = std::integral_constant<int, 1>;
+  using DZ = std::integral_constant<int, 2>;
+  auto face = [&](auto dirc, const double* eA, const double* eB, const double* eC,
+                  const double* eD, const double* coB, const double* coC, const double* bgf,
+                  const double* cB, double sB, const double* cC, double sC, const double* Fb,
+                  double* oA, double* oB, double* oC, double* oD) {
+    constexpr int D = decltype(dirc)::value;
+    if constexpr (GAS)
+      gas_face_vjp<D, G75>(gc, eA, eB, eC, eD, coB, coC, bgf, cB, sB, cC, sC, Fb, oA, oB, oC, oD);
+    else
+      dust_face_vjp<D>(eA, eB, eC, eD, coB, coC, Fb, oA, oB, oC, oD);
+  };
+  auto jwrap = [&](int j) {
+    j %= g.nth;
+    return j < 0 ? j + g.nth : j;
+  };
+  // w of an interior cell per unit face area: cw V^-1 lambda
+  auto wc = [&](int f, int k, int i, int j) -> double {
+    if (k < 0 || k >= g.nz || i < 0 || i >= g.nr) return 0.0;
+    return cw * a.t.rt[(size_t)i * RT_N + RT_INVV] *
+           cot[(size_t)(F0 + f) * N + ((size_t)k * g.nr + i) * g.nth + j];
+  };
+
+  // theta face between tile columns cb and cb + 1 (tile-relative, s_e column cb + H) of
+  // tile row r: contributions to columns cb - 1 .. cb + 2
+  auto theta_face = [&](int k, int r, int cb, double* oA, double* oB, double* oC, double* oD) {
+    double eA[NG], eB[NG], eC[NG], eD[NG], Fb[NG];
+    const int i = i0 + r;
+    const int jb = jwrap(j0 + cb), jc = jwrap(j0 + cb + 1);
+    const double ath = a.t.rt[(size_t)i * RT_N + RT_ATH];
+#pragma unroll
+    for (int f = 0; f < NG; ++f) {
+      eA[f] = s_e[f][r + H][cb + H - 1]; eB[f] = s_e[f][r + H][cb + H];
+      eC[f] = s_e[f][r + H][cb + H + 1]; eD[f] = s_e[f][r + H][cb + H + 2];
+      Fb[f] = ath * (wc(f, k, i, jc) - wc(f, k, i, jb));
+      oA[f] = 0.0; oB[f] = 0.0; oC[f] = 0.0; oD[f] = 0.0;
+    }
+    const double* bgf = a.t.bgc + ((size_t)k * g.nr + i) * 5;
+    face(DT(), eA, eB, eC, eD, nullptr, nullptr, bgf, bgf, 1.0, bgf, 1.0, Fb, oA, oB, oC, oD);
+  };
+  // r face between tile rows rb and rb + 1 (s_e row rb + H) of tile column cl
+  auto r_face = [&](int k, int rb, int cl, double* oA, double* oB, double* oC, double* oD) {
+    double eA[NG], eB[NG], eC[NG], eD[NG], Fb[NG];
+    const int ib = i0 + rb;
+    const int j = jwrap(j0 + cl);
+    const double ar = a.t.ar[ib + 1];
+#pragma unroll
+    for (int f = 0; f < NG; ++f) {
+      eA[f] = s_e[f][rb + H - 1][cl + H]; eB[f] = s_e[f][rb + H][cl + H];
+      eC[f] = s_e[f][rb + H + 1][cl + H]; eD[f] = s_e[f][rb + H + 2][cl + H];
+      Fb[f] = ar * (wc(f, k, ib + 1, j) - wc(f, k, ib, j));
+      oA[f] = 0.0; oB[f] = 0.0; oC[f] = 0.0; oD[f] = 0.0;
+    }
+    const double* bgf = a.t.bgr + ((size_t)k * (g.nr + 1) + (ib + 1)) * 5;
+    double sB = 1.0, sC = 1.0;
+    const double* cB = GAS ? centre_ptr(a, k, ib, sB) : nullptr;
+    const double* cC = GAS ? centre_ptr(a, k, ib + 1, sC) : nullptr;
+    face(DR(), eA, eB, eC, eD, rco_ptr(a, ib), rco_ptr(a, ib + 1), bgf, cB, sB, cC, sC, Fb, oA,
+         oB, oC, oD);
+  };
+
+  // z ring of the thread's column (cells kf-1 .. kf+2 of the face kf+1/2) and the z
+  // contributions of cells k-1, k, k+1 (relative to the face being processed)
+  double za[NG], zb[NG], zc[NG], hold[NG];
+  double ra[NG], rb_[NG], rc[NG], rd[NG];
+  const int jw = jwrap(jg);
+#pragma unroll
+  for (int f = 0; f < NG; ++f) { za[f] = 0.0; zb[f] = 0.0; zc[f] = 0.0; hold[f] = 0.0; }
+  double stb = 0.0;  // Stokes-number partial (dust)
+
+  auto z_face = [&](int kf, double* oA, double* oB, double* oC, double* oD) {
+    double Fb[NG];
+#pragma unroll
+    for (int f = 0; f < NG; ++f) {
+      Fb[f] = Az * (wc(f, kf + 1, igc, jw) - wc(f, kf, igc, jw));
+      oA[f] = 0.0; oB[f] = 0.0; oC[f] = 0.0; oD[f] = 0.0;
+    }
+    double sB = 1.0, sC = 1.0;
+    const double* cB = GAS ? centre_ptr(a, kf, igc, sB) : nullptr;
+    const double* cC = GAS ? centre_ptr(a, kf + 1, igc, sC) : nullptr;
+    const double* bgf = a.t.bgz + ((size_t)(kf + 1) * g.nr + igc) * 5;
+    face(DZ(), ra, rb_, rc, rd, nullptr, nullptr, bgf, cB, sB, cC, sC, Fb, oA, oB, oC, oD);
+  };
+  auto z_real = [&](int kf) { return !twod && kf >= -1 && kf <= g.nz - 1; };
+  auto ring_load = [&](double* dst, int k) {
+#pragma unroll
+    for (int f = 0; f < NG; ++f) dst[f] = fetch<false>(a, E, F0 + f, k, ig, jw);
+  };
+  auto ring_shift = [&](int knew) {
+#pragma unroll
+    for (int f = 0; f < NG; ++f) { ra[f] = rb_[f]; rb_[f] = rc[f]; rc[f] = rd[f]; }
+    ring_load(rd, knew);
+  };
+  auto finalize = [&](int k, const double* zz) {
+    if (!act) return;
+    const size_t cell = ((size_t)k * g.nr + ig) * g.nth + jg;
+#pragma unroll
+    for (int f = 0; f < NG; ++f) {
+      const size_t o = (size_t)(F0 + f) * N + cell;
+      double v = hold[f] + zz[f];
+      if (A.base1) v += A.base1[o];
+      if (A.base2) v += A.base2[o];
+      A.out[o] = v;
+    }
+  };
+
+  // faces k0-3/2 and k0-1/2 (their contributions to cells k0, k0+1)
+  if (!twod) {
+    ring_load(ra, k0 - 3); ring_load(rb_, k0 - 2); ring_load(rc, k0 - 1); ring_load(rd, k0);
+    double oA[NG], oB[NG], oC[NG], oD[NG];
+    if (act && z_real(k0 - 2)) {
+      z_face(k0 - 2, oA, oB, oC, oD);
+#pragma unroll
+      for (int f = 0; f < NG; ++f) zb[f] += oD[f];
+    }
+    ring_shift(k0 + 1);
+    if (act && z_real(k0 - 1)) {
+      z_face(k0 - 1, oA, oB, oC, oD);
+#pragma unroll
+      for (int f = 0; f < NG; ++f) { zb[f] += oC[f]; zc[f] += oD[f]; }
+    }
+    ring_shift(k0 + 2);
+  }
+
+  for (int k = k0; k < k1; ++k) {
+    // ---- stage the plane with a three-cell halo; clear the tile accumulators
+    for (int h = tid; h < (TI + 2 * H) * (TJ + 2 * H); h += NT) {
+      const int rr = h / (TJ + 2 * H), cc = h % (TJ + 2 * H);
+      const int ii = i0 + rr - H;
+      const int jj = jwrap(j0 + cc - H);
+#pragma unroll
+      for (int f = 0; f < NG; ++f) s_e[f][rr][cc] = fetch<false>(a, E, F0 + f, k, ii, jj);
+    }
+#pragma unroll
+    for (int f = 0; f < NG; ++f) { s_at[f][ti][tj] = 0.0; s_ar[f][ti][tj] = 0.0; }
+    __syncthreads();
+
+    double oA[NG], oB[NG], oC[NG], oD[NG];
+    // ---- theta faces j+1/2 of the thread's own cell; four ordered scatter phases
+    const bool tok = ig < g.nr;
+    if (tok) theta_face(k, ti, tj, oA, oB, oC, oD);
+#pragma unroll
+    for (int ph = 0; ph < 4; ++ph) {
+      const int col = tj - 1 + ph;
+      if (tok && col >= 0 && col < TJ) {
+        const double* o = ph == 0 ? oA : ph == 1 ? oB : ph == 2 ? oC : oD;
+#pragma unroll
+        for (int f = 0; f < NG; ++f) s_at[f][ti][col] += o[f];
+      }
+      __syncthreads();
+    }
+    // ---- r faces i+1/2 of the thread's own cell
+    const bool rok = ig < g.nr && colok;
+    if (rok) r_face(k, ti, tj, oA, oB, oC, oD);
+#pragma unroll
+    for (int ph = 0; ph < 4; ++ph) {
+      const int row = ti - 1 + ph;
+      if (rok && row >= 0 && row < TI) {
+        const double* o = ph == 0 ? oA : ph == 1 ? oB : ph == 2 ? oC : oD;
+#pragma unroll
+        for (int f = 0; f < NG; ++f) s_ar[f][row][tj] += o[f];
+      }
+      __syncthreads();
+    }
+    // ---- the remaining faces within 3/2 cells of the tile: theta faces at tile columns
+    //      -3/2, -1/2, 64+1/2 of each row (threads 0..23), r faces at tile rows -3/2,
+    //      -1/2, 8+1/2 of each column (threads 24..215)
+    int ekind = 0, eline = 0, epos = 0;  // 1 theta, 2 r; tile row/column; face lower cell
+    if (tid < 3 * TI) {
+      const int q = tid % 3;
+      ekind = 1; eline = tid / 3; epos = q == 0 ? -2 : (q == 1 ? -1 : TJ);
+      if (i0 + eline >= g.nr) ekind = 0;
+    } else if (tid < 3 * TI + 3 * TJ) {
+      const int e = tid - 3 * TI;
+      const int q = e / TJ;
+      ekind = 2; eline = e % TJ; epos = q == 0 ? -2 : (q == 1 ? -1 : TI);
+      const int ib = i0 + epos;
+      if (ib + 1 < 0 || ib >= g.nr || j0 + eline >= g.nth) ekind = 0;
+    }
+    if (ekind == 1) theta_face(k, eline, epos, oA, oB, oC, oD);
+    else if (ekind == 2) r_face(k, epos, eline, oA, oB, oC, oD);
+#pragma unroll
+    for (int ph = 0; ph < 4; ++ph) {
+      const int t = epos - 1 + ph;  // target cell along the face normal
+      if (ekind == 1 && t >= 0 && t < TJ) {
+        const double* o = ph == 0 ? oA : ph == 1 ? oB : ph == 2 ? oC : oD;
+#pragma unroll
+        for (int f = 0; f < NG; ++f) s_at[f][eline][t] += o[f];
+      } else if (ekind == 2 && t >= 0 && t < TI) {
+        const double* o = ph == 0 ? oA : ph == 1 ? oB : ph == 2 ? oC : oD;
+#pragma unroll
+        for (int f = 0; f < NG; ++f) s_ar[f][t][eline] += o[f];
+      }
+      __syncthreads();
+    }
+    // ---- in-plane total of the thread's cell, plus the reverse of its sources
+    double cur[NG];
+#pragma unroll
+    for (int f = 0; f < NG; ++f) cur[f] = s_at[f][ti][tj] + s_ar[f][ti][tj];
+    if (act) {
+      const size_t cell = ((size_t)k * g.nr + ig) * g.nth + jg;
+      const double gr = a.t.grav[((size_t)k * g.nr + ig) * 2 + 0];
+      const double gz = a.t.grav[((size_t)k * g.nr + ig) * 2 + 1];
+      const double* bgc = a.t.bgc + ((size_t)k * g.nr + ig) * 5;
+      double q[5], sg[5];
+#pragma unroll
+      for (int f = 0; f < 5; ++f) {
+        q[f] = bgc[f] + E[(size_t)f * N + cell];
+        sg[f] = cw * cot[(size_t)f * N + cell];
+      }
+      const double ir = 1.0 / q[4];
+      const double U[3] = {q[0] * ir, q[1] * ir, q[2] * ir};
+      if constexpr (GAS) {
+        const double gm1 = gc.gm1;
+        const double u = U[0], v = U[1], w = U[2];
+        // S_r = (m_th v + p)/r + rho g_r, S_th = -m_r v / r, S_z = rho g_z,
+        // S_E = m_r g_r + m_z g_z
+        cur[0] += sg[0] * (-gm1 * u * invrc) + sg[1] * (-v * invrc) + sg[3] * gr;
+        cur[1] += sg[0] * ((2.0 - gm1) * v * invrc) + sg[1] * (-u * invrc);
+        cur[2] += sg[0] * (-gm1 * w * invrc) + sg[3] * gz;
+        cur[3] += sg[0] * gm1 * invrc;
+        cur[4] += sg[0] * ((-v * v + 0.5 * gm1 * (u * u + v * v + w * w)) * invrc + gr) +
+                  sg[1] * (u * v * invrc) + sg[2] * gz;
+        // drag D_s = rho_d (v_d - v) Omega_K / St on the gas (+) and the dust (-), and
+        // v . D in the gas energy
+        double Ub[3] = {0.0, 0.0, 0.0}, Dt[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+        for (int s = 0; s < ND; ++s) {
+          const int o = 5 + 4 * s;
+          const double rdn = E[(size_t)(o + 3) * N + cell];
+          double vd[3] = {0.0, 0.0, 0.0};
+          if (rdn > 0.0) {
+            const double id = 1.0 / rdn;
+#pragma unroll
+            for (int c2 = 0; c2 < 3; ++c2) vd[c2] = E[(size_t)(o + c2) * N + cell] * id;
+          }
+          const double its = omk * g.inv_st[s];
+#pragma unroll
+          for (int c2 = 0; c2 < 3; ++c2) {
+            Dt[c2] += rdn * (vd[c2] - U[c2]) * its;
+            const double Db = sg[c2] + sg[3] * U[c2] - cw * cot[(size_t)(o + c2) * N + cell];
+            Ub[c2] -= its * rdn * Db;
+          }
+        }
+        double dot = 0.0;
+#pragma unroll
+        for (int c2 = 0; c2 < 3; ++c2) {
+          Ub[c2] += sg[3] * Dt[c2];
+          cur[c2] += Ub[c2] * ir;
+          dot += Ub[c2] * U[c2];
+        }
+        cur[4] -= dot * ir;
+      } else {
+        const double m[3] = {E[(size_t)F0 * N + cell], E[(size_t)(F0 + 1) * N + cell],
+                             E[(size_t)(F0 + 2) * N + cell]};
+        const double rdn = E[(size_t)(F0 + 3) * N + cell];
+        double sd[4];
+#pragma unroll
+        for (int f = 0; f < 4; ++f) sd[f] = cw * cot[(size_t)(F0 + f) * N + cell];
+        double vd[3] = {0.0, 0.0, 0.0};
+        if (rdn > 0.0) {
+          const double id = 1.0 / rdn;
+          vd[0] = m[0] * id; vd[1] = m[1] * id; vd[2] = m[2] * id;
+          // S_r = m_th v_d / r + rho_d g_r, S_th = -m_r v_d / r
+          cur[1] += sd[0] * 2.0 * vd[1] * invrc - sd[1] * vd[0] * invrc;
+          cur[0] += -sd[1] * vd[1] * invrc;
+          cur[3] += sd[0] * (-vd[1] * vd[1] * invrc) + sd[1] * (vd[0] * vd[1] * invrc);
+        }
+        cur[3] += sd[0] * gr + sd[2] * gz;
+        const double its = omk * g.inv_st[species];
+        const double st = 1.0 / g.inv_st[species];
+        double dotU = 0.0, dotD = 0.0;
+#pragma unroll
+        for (int c2 = 0; c2 < 3; ++c2) {
+          const double Ds = rdn * (vd[c2] - U[c2]) * its;
+          const double Db = sg[c2] + sg[3] * U[c2] - sd[c2];
+          if (rdn > 0.0) cur[c2] += its * Db;
+          dotU += Db * U[c2];
+          dotD += Db * Ds;
+        }
+        cur[3] -= its * dotU;
+        stb -= dotD / st;
+      }
+    }
+    // ---- z face k+1/2: completes cell k-1
+    if (!twod) {
+      double zd[NG];
+#pragma unroll
+      for (int f = 0; f < NG; ++f) zd[f] = 0.0;
+      if (act && z_real(k)) {
+        z_face(k, oA, oB, oC, oD);
+#pragma unroll
+        for (int f = 0; f < NG; ++f) {
+          za[f] += oA[f]; zb[f] += oB[f]; zc[f] += oC[f]; zd[f] = oD[f];
+        }
+      }
+      if (k - 1 >= k0) finalize(k - 1, za);
+#pragma unroll
+      for (int f = 0; f < NG; ++f) {
+        za[f] = zb[f]; zb[f] = zc[f]; zc[f] = zd[f]; hold[f] = cur[f];
+      }
+      ring_shift(k + 3);
+    } else {
+#pragma unroll
+      for (int f = 0; f < NG; ++f) hold[f] = cur[f];
+      finalize(k, za);
+    }
+  }
+  // ---- last face k1+1/2 completes cell k1-1
+  if (!twod && k1 > k0) {
+    double oA[NG], oB[NG], oC[NG], oD[NG];
+    if (act && z_real(k1)) {
+      z_face(k1, oA, oB, oC, oD);
+#pragma unroll
+      for (int f = 0; f < NG; ++f) za[f] += oA[f];
+    }
+    finalize(k1 - 1, za);
+  }
+  // ---- Stokes-number partial of the block (dust)
+  if constexpr (!GAS) {
+    const double ws = wave_sum(stb);
+    if ((tid & 63) == 0) s_red[tid / 64] = ws;
+    __syncthreads();
+    if (tid == 0) {
+      double acc = 0.0;
+      for (int w = 0; w < NT / 64; ++w) acc += s_red[w];
+      A.stpart[blockIdx.x] = acc;
+    }
+  }
+}
+
+// acc[0] += sum of parts[0 .. n) in a fixed order
+__global__ void __launch_bounds__(256) k_st_accum(const double* parts, int n, double* acc) {
+  __shared__ double s_s[4];
+  double v = 0.0;
+  for (int b = threadIdx.x; b < n; b += blockDim.x) v += parts[b];
+  v = wave_sum(v);
+  if ((threadIdx.x & 63) == 0) s_s[threadIdx.x / 64] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) acc[0] += (s_s[0] + s_s[1]) + (s_s[2] + s_s[3]);
+}
+
+// ------------------------------------------------------------------------------------
+// launchers
+
+template <int ND>
+static void adj_nd(const AdjArgs& a, int blocks, int group, hipStream_t s) {
+  if (group == 0) {
+    if (a.s.g.gamma == 1.4)
+      hipLaunchKernelGGL((k_adj<true, ND, true>), dim3(blocks), dim3(NT), 0, s, a, 0);
+    else
+      hipLaunchKernelGGL((k_adj<true, ND, false>), dim3(blocks), dim3(NT), 0, s, a, 0);
+  } else {
+    if constexpr (ND > 0)
+      hipLaunchKernelGGL((k_adj<false, ND, true>), dim3(blocks), dim3(NT), 0, s, a, group - 1);
+  }
+}
+
+hipError_t launch_adj_group(const AdjArgs& a, int blocks, int group, hipStream_t s) {
+  switch (a.s.g.nd) {
+    case 0: adj_nd<0>(a, blocks, group, s); break;
+    case 1: adj_nd<1>(a, blocks, group, s); break;
+    case 2: adj_nd<2>(a, blocks, group, s); break;
+    case 3: adj_nd<3>(a, blocks, group, s); break;
+    default: adj_nd<4>(a, blocks, group, s); break;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_st_accum(const double* parts, int nblocks, double* acc, hipStream_t s) {
+  hipLaunchKernelGGL(k_st_accum, dim3(1), dim3(256), 0, s, parts, nblocks, acc);
+  return hipGetLastError();
+}
+
+}  // namespace rb

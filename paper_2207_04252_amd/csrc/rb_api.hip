@@ -34,6 +34,10 @@ struct rb_ctx {
   size_t ev_used = 0;
   double prof_ms[3] = {0, 0, 0};
   int64_t prof_n[3] = {0, 0, 0};
+  // recorded run for the adjoint (rb_record)
+  int rec_n = 0, rec_k = 0;
+  std::vector<double> rec_dts;
+  void* rec_ws = nullptr;
 };
 
 namespace {
@@ -538,6 +542,7 @@ rb_status rb_diagnostics(rb_ctx* x, rb_diag* out) {
     out->outflow[s] = c.outflow[s];
   }
   out->dt_last = x->dt_last;
+  out->fp64_resolves = (int64_t)c.nresolve;
   return RB_OK;
 }
 
@@ -552,6 +557,202 @@ rb_status rb_profile(rb_ctx* x, int enable) {
 rb_status rb_profile_read(rb_ctx* x, double* total_ms, int64_t* launches) {
   if (!x || !total_ms || !launches) return RB_EINVAL;
   for (int k = 0; k < 3; ++k) { total_ms[k] = x->prof_ms[k]; launches[k] = x->prof_n[k]; }
+  return RB_OK;
+}
+
+}  // extern "C"
+
+// ---- discrete adjoint ------------------------------------------------------------
+
+namespace {
+
+// workspace layout, in doubles, each part 256-byte aligned
+struct AdjLayout {
+  size_t S, lam, nu, ck, segE, segS, stp, sta, total;
+  int nseg, nblocks, tk, nkc;
+};
+
+AdjLayout adj_layout(const rb_ctx* x, int n, int k) {
+  AdjLayout A;
+  const Layout& L = x->L;
+  // z chunking: one block per CU suffices (LDS and registers hold one per CU); long
+  // chunks keep the three extra z faces per chunk cheap
+  const int tiles = L.ntj * L.nti;
+  int tk = x->g.nz;
+  if (x->g.nz > 1) {
+    const int cand[5] = {32, 16, 8, 4, 2};
+    tk = 2;
+    for (int q = 0; q < 5; ++q) {
+      if ((size_t)tiles * ((x->g.nz + cand[q] - 1) / cand[q]) >= 256) { tk = cand[q]; break; }
+    }
+    tk = std::min(tk, x->g.nz);
+  }
+  A.tk = tk;
+  A.nkc = (x->g.nz + tk - 1) / tk;
+  A.nblocks = tiles * A.nkc;
+  A.S = (size_t)x->g.nf * x->g.N;
+  A.nseg = (n + k - 1) / k;
+  size_t o = 0;
+  auto take = [&](size_t m) { size_t at = o; o += up32(m); return at; };
+  A.lam = take(A.S);
+  A.nu = take(A.S);
+  A.ck = o; o += (size_t)A.nseg * up32(A.S);
+  A.segE = o; o += (size_t)std::max(k - 1, 0) * up32(A.S);
+  A.segS = o; o += (size_t)k * up32(A.S);
+  A.stp = take(A.nblocks);
+  A.sta = take(4);
+  A.total = o;
+  return A;
+}
+
+}  // namespace
+
+extern "C" {
+
+rb_status rb_adjoint_workspace(const rb_ctx* x, int n, int ckpt_every, size_t* bytes) {
+  if (!x || !bytes || n < 1 || ckpt_every < 1) return RB_EINVAL;
+  if (x->g.p32) return RB_EINVAL;
+  *bytes = adj_layout(x, n, std::min(ckpt_every, n)).total * sizeof(double);
+  return RB_OK;
+}
+
+rb_status rb_record(rb_ctx* x, int n, int ckpt_every, const rb_dt_policy* policy, double* dt_out,
+                    void* ws, size_t ws_bytes) {
+  if (!x || !policy || !ws || n < 1 || ckpt_every < 1) return RB_EINVAL;
+  if (x->g.p32) return fail(x, RB_EINVAL, "the adjoint is FP64 only");
+  const int k = std::min(ckpt_every, n);
+  const AdjLayout A = adj_layout(x, n, k);
+  if (ws_bytes < A.total * sizeof(double)) return fail(x, RB_EINVAL, "workspace too small");
+  if (policy->kind == RB_DT_LIST && !policy->dt_list) return fail(x, RB_EINVAL, "dt_list is null");
+  x->rec_n = 0;
+  x->rec_ws = nullptr;
+  x->rec_dts.assign(n, 0.0);
+  double* w = (double*)ws;
+  const size_t bytes = A.S * sizeof(double);
+  for (int seg = 0; seg < A.nseg; ++seg) {
+    const int m0 = seg * k, len = std::min(k, n - m0);
+    HIPCHK(x, hipMemcpyAsync(w + A.ck + (size_t)seg * up32(A.S), x->state, bytes,
+                             hipMemcpyDeviceToDevice, x->stream), "checkpoint");
+    rb_dt_policy p = *policy;
+    if (p.kind == RB_DT_LIST) p.dt_list = policy->dt_list + m0;
+    const rb_status st = rb_step(x, len, &p, x->rec_dts.data() + m0);
+    if (st != RB_OK) return st;
+  }
+  if (dt_out) std::memcpy(dt_out, x->rec_dts.data(), n * sizeof(double));
+  x->rec_n = n;
+  x->rec_k = k;
+  x->rec_ws = ws;
+  return RB_OK;
+}
+
+rb_status rb_adjoint(rb_ctx* x, const void* lambda_final, void* grad_state0, double* grad_stokes,
+                     void* ws, size_t ws_bytes) {
+  if (!x || !lambda_final || !grad_state0 || !ws) return RB_EINVAL;
+  if (x->g.p32) return fail(x, RB_EINVAL, "the adjoint is FP64 only");
+  if (x->rec_n < 1 || x->rec_ws != ws) return fail(x, RB_EINVAL, "no matching rb_record");
+  const int n = x->rec_n, k = x->rec_k;
+  const AdjLayout A = adj_layout(x, n, k);
+  if (ws_bytes < A.total * sizeof(double)) return fail(x, RB_EINVAL, "workspace too small");
+  double* w = (double*)ws;
+  double* lam = w + A.lam;
+  double* nu = w + A.nu;
+  const size_t bytes = A.S * sizeof(double);
+  HIPCHK(x, hipMemcpyAsync(lam, lambda_final, bytes, hipMemcpyDeviceToDevice, x->stream), "lambda");
+  HIPCHK(x, launch_fill(w + A.sta, 4, 0.0, x->stream), "clear");
+  StageArgs a = base_args(x);
+  double* dtlog = x->work + x->L.dtlog;
+  AdjArgs J;
+  std::memset(&J, 0, sizeof(J));
+  J.tk = A.tk;
+  J.nkc = A.nkc;
+  J.stpart = w + A.stp;
+  auto vjp = [&](const double* E, double cw, const double* cot, const double* b1, const double* b2,
+                 double* out) -> hipError_t {
+    J.s = a;
+    J.s.in = E;
+    J.cot = cot; J.base1 = b1; J.base2 = b2; J.out = out; J.cw = cw;
+    for (int grp = 0; grp <= x->g.nd; ++grp) {
+      hipError_t e = launch_adj_group(J, A.nblocks, grp, x->stream);
+      if (e != hipSuccess) return e;
+      if (grp > 0) {
+        e = launch_st_accum(J.stpart, A.nblocks, w + A.sta + (grp - 1), x->stream);
+        if (e != hipSuccess) return e;
+      }
+    }
+    return hipSuccess;
+  };
+  std::vector<double> hd(k + 1);
+  for (int seg = A.nseg - 1; seg >= 0; --seg) {
+    const int m0 = seg * k, len = std::min(k, n - m0);
+    for (int q = 0; q < len; ++q) hd[q] = x->rec_dts[m0 + q];
+    hd[len] = hd[len - 1];
+    HIPCHK(x, hipMemcpyAsync(dtlog, hd.data(), (len + 1) * sizeof(double), hipMemcpyHostToDevice,
+                             x->stream), "upload dt");
+    // states of the segment: E_0 the checkpoint, E_q (q >= 1) and midpoints S_q
+    auto Eq = [&](int q) {
+      return q == 0 ? w + A.ck + (size_t)seg * up32(A.S) : w + A.segE + (size_t)(q - 1) * up32(A.S);
+    };
+    auto Sq = [&](int q) { return w + A.segS + (size_t)q * up32(A.S); };
+    for (int q = 0; q < len; ++q) {
+      a.step = (int)(m0 + q);
+      a.dt_idx = q;
+      a.mode = MODE_UPDATE;
+      a.gas_only = 0;
+      a.in = Eq(q); a.base = Eq(q); a.out = Sq(q); a.coef = 0.5; a.second = 0;
+      HIPCHK(x, run_stage(x, a), "recompute stage 1");
+      if (q + 1 < len) {
+        a.in = Sq(q); a.base = Eq(q); a.out = Eq(q + 1); a.coef = 1.0; a.second = 1;
+        HIPCHK(x, run_stage(x, a), "recompute stage 2");
+      }
+    }
+    // reverse: nu = J_G(S)^T (dt/V lambda); lambda <- lambda + nu + J_G(E)^T (dt/(2V) nu)
+    for (int q = len - 1; q >= 0; --q) {
+      const double dt = x->rec_dts[m0 + q];
+      HIPCHK(x, vjp(Sq(q), dt, lam, nullptr, nullptr, nu), "adjoint stage 2");
+      HIPCHK(x, vjp(Eq(q), 0.5 * dt, nu, lam, nu, lam), "adjoint stage 1");
+    }
+  }
+  HIPCHK(x, hipMemcpyAsync(grad_state0, lam, bytes, hipMemcpyDeviceToDevice, x->stream), "gradient");
+  double sta[4] = {0, 0, 0, 0};
+  HIPCHK(x, hipMemcpyAsync(sta, w + A.sta, 4 * sizeof(double), hipMemcpyDeviceToHost, x->stream),
+         "stokes");
+  Ctrl c;
+  HIPCHK(x, hipMemcpyAsync(&c, x->work + x->L.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, x->stream),
+         "read control");
+  HIPCHK(x, hipStreamSynchronize(x->stream), "sync");
+  if (grad_stokes)
+    for (int s = 0; s < x->g.nd; ++s) grad_stokes[s] = sta[s];
+  if (c.status & FL_HARD) {
+    x->hard = status_of_flags(c.status & FL_HARD);
+    return fail(x, (rb_status)x->hard, "hard error while recomputing a recorded segment");
+  }
+  return RB_OK;
+}
+
+rb_status rb_amp_gradient(rb_ctx* x, const double* noise, const double* amp, const void* lam,
+                          void* out) {
+  if (!x || !lam || !out) return RB_EINVAL;
+  if (x->cfg.init_kind != RB_INIT_DISC) return fail(x, RB_EINVAL, "no vortex in this initial state");
+  const size_t N = x->g.N;
+  InitArgs ia;
+  std::memset(&ia, 0, sizeof(ia));
+  ia.g = x->g;
+  ia.cfg = x->cfg;
+  ia.work = x->work;
+  ia.L = x->L;
+  ia.state = x->state;
+  if (noise) {
+    HIPCHK(x, hipMemcpyAsync(x->stage, noise, N * sizeof(double), hipMemcpyHostToDevice, x->stream),
+           "noise");
+    ia.noise = (const double*)x->stage;
+  }
+  if (amp) {
+    HIPCHK(x, hipMemcpyAsync((double*)x->stage + N, amp, N * sizeof(double), hipMemcpyHostToDevice,
+                             x->stream), "amp");
+    ia.amp = (const double*)x->stage + N;
+  }
+  HIPCHK(x, launch_amp_grad(ia, (const double*)lam, (double*)out, x->stream), "amp gradient");
+  HIPCHK(x, hipStreamSynchronize(x->stream), "sync");
   return RB_OK;
 }
 

@@ -1,0 +1,674 @@
+// Device-side building blocks shared by the forward stage kernels and the adjoint
+// kernels: reconstruction, exact gas and pressureless dust Riemann solvers, face
+// fluxes, state access with ghost cells, wave reductions, tile order.
+#pragma once
+
+#include <math.h>
+
+#include <type_traits>
+
+#include "rb_internal.h"
+
+namespace rb {
+
+// ------------------------------------------------------------------------------------
+// small helpers
+
+template <class T>
+__device__ __forceinline__ T minmod3(T x, T y, T z) {
+  if (x > T(0) && y > T(0) && z > T(0)) return fmin(x, fmin(y, z));
+  if (x < T(0) && y < T(0) && z < T(0)) return fmax(x, fmax(y, z));
+  return T(0);
+}
+
+// Uniform direction (index coordinates): the three-point parabola gives the upper-face
+// increment (dm + 3 dp)/8 and the lower-face increment -(3 dm + dp)/8, limited by the
+// one-sided differences (Sect. 2.7).  Written so that mirrored data give exactly
+// opposite increments.
+template <class T>
+__device__ __forceinline__ T inc_up_u(T em, T e0, T ep) {
+  T dm = e0 - em, dp = ep - e0;
+  return minmod3<T>(fma(T(3), dp, dm) * T(0.125), dm, dp);
+}
+template <class T>
+__device__ __forceinline__ T inc_lo_u(T em, T e0, T ep) {
+  T dm = e0 - em, dp = ep - e0;
+  return minmod3<T>(-(fma(T(3), dm, dp) * T(0.125)), -dm, -dp);
+}
+// Non-uniform r: precomputed parabola weights and limiter bounds of the cell.
+template <class T>
+__device__ __forceinline__ T inc_up_c(T em, T e0, T ep, const double* co) {
+  T dm = e0 - em, dp = ep - e0;
+  return minmod3<T>(fma(T(co[RC_WPP]), dp, T(co[RC_WPM]) * dm), T(co[RC_LPM]) * dm,
+                    T(co[RC_LPP]) * dp);
+}
+template <class T>
+__device__ __forceinline__ T inc_lo_c(T em, T e0, T ep, const double* co) {
+  T dm = e0 - em, dp = ep - e0;
+  return minmod3<T>(fma(T(co[RC_WMP]), dp, T(co[RC_WMM]) * dm), T(co[RC_LMM]) * dm,
+                    T(co[RC_LMP]) * dp);
+}
+
+// x^(-1/7) for x > 0: FP32 hardware log2/exp2 seed, then Newton on z^-7 = x written as
+// z <- z + (z/7)(1 - x z^7) (quadratic convergence, three steps reach FP64 accuracy;
+// x = 1 is a fixed point).
+__device__ __forceinline__ double inv_root7(double x) {
+  if (x == 1.0) return 1.0;
+  float xf = fminf(fmaxf((float)x, 1e-30f), 1e30f);
+  double z = (double)__builtin_amdgcn_exp2f(-0.142857142857142857f * __builtin_amdgcn_logf(xf));
+  const double k7 = 1.0 / 7.0;
+#pragma unroll
+  for (int it = 0; it < 3; ++it) {
+    double z2 = z * z;
+    double z3 = z2 * z;
+    double z7 = z3 * z3 * z;
+    z = fma(z * k7, fma(-x, z7, 1.0), z);
+  }
+  return z;
+}
+
+// 1/x for normal positive or negative x: hardware estimate and two Newton steps
+// (within an ulp of the correctly rounded quotient).
+__device__ __forceinline__ double frcp(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  double e = fma(-x, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-x, r, 1.0);
+  return fma(r, e, r);
+}
+
+struct GasC {
+  double g, gm1, inv_gm1, g2m1, gm1_2g, gp1_2g, kshock, a2, half_gm1;
+};
+
+__device__ __forceinline__ GasC gas_consts(double g) {
+  GasC c;
+  c.g = g;
+  c.gm1 = g - 1.0;
+  c.inv_gm1 = 1.0 / (g - 1.0);
+  c.g2m1 = 2.0 / (g - 1.0);
+  c.gm1_2g = (g - 1.0) / (2.0 * g);
+  c.gp1_2g = (g + 1.0) / (2.0 * g);
+  c.kshock = (g - 1.0) / (g + 1.0);
+  c.a2 = 2.0 / (g + 1.0);
+  c.half_gm1 = 0.5 * (g - 1.0);
+  return c;
+}
+
+// Powers of x = p/p_K needed by the exact solver: x^((g-1)/2g), x^(-(g+1)/2g), x^(1/g).
+// With g = 7/5 they are x^(1/7), x^(-6/7), x^(5/7), all from one x^(-1/7).
+template <bool G75> struct Pow3 {
+  double p17, pm67, p57;
+  __device__ __forceinline__ Pow3(double x, const GasC& c) {
+    if (G75) {
+      double z = inv_root7(x);
+      double z2 = z * z;
+      double z6 = z2 * z2 * z2;
+      p17 = x * z6;
+      pm67 = z6;
+      p57 = x * z2;
+    } else {
+      p17 = pow(x, c.gm1_2g);
+      pm67 = pow(x, -c.gp1_2g);
+      p57 = pow(x, 1.0 / c.g);
+    }
+  }
+};
+
+template <bool G75>
+__device__ __forceinline__ double ipow_fan_rho(double ratio, const GasC& c) {
+  if (G75) { double r2 = ratio * ratio; return r2 * r2 * ratio; }
+  return pow(ratio, c.g2m1);
+}
+template <bool G75>
+__device__ __forceinline__ double ipow_fan_p(double ratio, const GasC& c) {
+  if (G75) { double r2 = ratio * ratio; double r3 = r2 * ratio; return r3 * r3 * ratio; }
+  return pow(ratio, 2.0 * c.g / (c.g - 1.0));
+}
+
+// One side of the pressure function of the exact solver (Sect. 2.6) and its derivative.
+// Per-side constants of the pressure function: A = 2/((g+1) rho), B = (g-1)/(g+1) p,
+// 1/p and 1/(rho c).
+struct Side {
+  double r, u, p, c, A, B, ip, irc;
+};
+
+__device__ __forceinline__ Side make_side(double r, double ir, double u, double p, double c,
+                                          const GasC& g) {
+  Side s;
+  s.r = r; s.u = u; s.p = p; s.c = c;
+  s.A = g.a2 * ir;
+  s.B = g.kshock * p;
+  s.ip = frcp(p);
+  s.irc = ir * frcp(c);
+  return s;
+}
+
+template <bool G75>
+__device__ __forceinline__ void pfun(double p, const Side& K, const GasC& c, double& f,
+                                     double& df) {
+  if (p > K.p) {
+    double ipb = frcp(p + K.B);
+    double q = sqrt(K.A * ipb);
+    f = (p - K.p) * q;
+    df = q * (1.0 - 0.5 * (p - K.p) * ipb);
+  } else {
+    Pow3<G75> w(p * K.ip, c);
+    f = c.g2m1 * K.c * (w.p17 - 1.0);
+    df = w.pm67 * K.irc;
+  }
+}
+
+struct TStat {
+  int fall, vac, maxit, noconv, resolve;
+};
+
+// Wave pattern taken by the exact gas solver at x/t = 0 (kept by the adjoint, which
+// differentiates the branch the primal solve took).
+enum : int {
+  GR_LEFT = 0,      // the left state
+  GR_RIGHT,         // the right state
+  GR_FAN_L,         // inside the left rarefaction fan
+  GR_FAN_R,         // inside the right rarefaction fan
+  GR_VACUUM,        // inside a vacuum region
+  GR_STAR_L_SHOCK,  // left star state behind a shock
+  GR_STAR_L_RARE,   // left star state behind a rarefaction
+  GR_STAR_R_SHOCK,
+  GR_STAR_R_RARE
+};
+struct GasRec {
+  int branch;
+  double ps, us;                 // star pressure and velocity (star branches)
+  double rho, un, t1, t2, p;     // the sampled state
+};
+
+// Exact Riemann problem of the ideal gas sampled at x/t = 0 (Sect. 2.6): Newton on p*
+// from the primitive-variable guess (relative change <= 1e-12, at most 50 iterations),
+// star velocity, then the wave pattern at x/t = 0; tangential velocities come from the
+// side of the contact.  Output: mass, normal momentum, two tangential momenta, energy.
+template <bool G75, bool REC = false>
+__device__ void gas_riemann(const GasC& c, double rL, double irL, double uL, double aL, double bL,
+                            double pL, double rR, double irR, double uR, double aR, double bR,
+                            double pR, double fl[5], TStat& st, GasRec* rec = nullptr) {
+  const double cL = sqrt(c.g * pL * irL);
+  const double cR = sqrt(c.g * pR * irR);
+  const double du = uR - uL;
+  double rho, un, t1, t2, p;
+  if (c.g2m1 * (cL + cR) <= du) {
+    // vacuum between two rarefactions
+    st.vac++;
+    double sHL = uL - cL, sSL = uL + c.g2m1 * cL, sSR = uR - c.g2m1 * cR, sHR = uR + cR;
+    int br;
+    if (0.0 <= sHL) { rho = rL; un = uL; t1 = aL; t2 = bL; p = pL; br = GR_LEFT; }
+    else if (0.0 < sSL) {
+      double cc = c.a2 * (cL + c.half_gm1 * uL);
+      double ratio = cc / cL;
+      rho = rL * ipow_fan_rho<G75>(ratio, c); un = cc; p = pL * ipow_fan_p<G75>(ratio, c);
+      t1 = aL; t2 = bL; br = GR_FAN_L;
+    } else if (0.0 <= sSR) { rho = 0.0; un = 0.0; t1 = 0.0; t2 = 0.0; p = 0.0; br = GR_VACUUM; }
+    else if (0.0 < sHR) {
+      double cc = c.a2 * (cR - c.half_gm1 * uR);
+      double ratio = cc / cR;
+      rho = rR * ipow_fan_rho<G75>(ratio, c); un = -cc; p = pR * ipow_fan_p<G75>(ratio, c);
+      t1 = aR; t2 = bR; br = GR_FAN_R;
+    } else { rho = rR; un = uR; t1 = aR; t2 = bR; p = pR; br = GR_RIGHT; }
+    if constexpr (REC) rec->branch = br;
+  } else {
+    const Side L = make_side(rL, irL, uL, pL, cL, c);
+    const Side R = make_side(rR, irR, uR, pR, cR, c);
+    // Supersonic faces: with u_L >= c_L, let p_hi be the star pressure at which a left
+    // shock would stand still.  If f(p_hi) >= 0 then p* <= p_hi (f increases), so the
+    // left wave (rarefaction with head u_L - c_L >= 0, or shock with speed >= 0) lies
+    // at x/t >= 0, and u* = u_L - f_L(p*) >= u_L - f_L(p_hi) >= 0: the solution at x/t = 0
+    // is the left state, which is what the full solve returns.  Mirror for u_R <= -c_R.
+    if (uL >= cL) {
+      const double m = uL / cL;
+      const double phi = pL * (m * m - c.gm1_2g) / c.gp1_2g;
+      double fL, dL, fR, dR;
+      pfun<G75>(phi, L, c, fL, dL);
+      pfun<G75>(phi, R, c, fR, dR);
+      if (fL + fR + du >= 0.0 && uL - fL >= 0.0) {
+        if constexpr (REC) {
+          rec->branch = GR_LEFT;
+          rec->rho = rL; rec->un = uL; rec->t1 = aL; rec->t2 = bL; rec->p = pL;
+        }
+        const double m0 = rL * uL;
+        const double en = pL * c.inv_gm1 + 0.5 * rL * (uL * uL + aL * aL + bL * bL);
+        fl[0] = m0; fl[1] = m0 * uL + pL; fl[2] = m0 * aL; fl[3] = m0 * bL; fl[4] = (en + pL) * uL;
+        return;
+      }
+    } else if (uR <= -cR) {
+      const double m = -uR / cR;
+      const double phi = pR * (m * m - c.gm1_2g) / c.gp1_2g;
+      double fL, dL, fR, dR;
+      pfun<G75>(phi, L, c, fL, dL);
+      pfun<G75>(phi, R, c, fR, dR);
+      if (fL + fR + du >= 0.0 && uR + fR <= 0.0) {
+        if constexpr (REC) {
+          rec->branch = GR_RIGHT;
+          rec->rho = rR; rec->un = uR; rec->t1 = aR; rec->t2 = bR; rec->p = pR;
+        }
+        const double m0 = rR * uR;
+        const double en = pR * c.inv_gm1 + 0.5 * rR * (uR * uR + aR * aR + bR * bR);
+        fl[0] = m0; fl[1] = m0 * uR + pR; fl[2] = m0 * aR; fl[3] = m0 * bR; fl[4] = (en + pR) * uR;
+        return;
+      }
+    }
+    double ppv = 0.5 * (pL + pR) - 0.125 * du * (rL + rR) * (cL + cR);
+    double ps = fmax(ppv, 1e-8 * fmin(pL, pR));
+    int it = 0;
+    bool conv = false;
+    double fL = 0.0, dL = 1.0, fR = 0.0, dR = 1.0, dp = 0.0;
+    while (it < 50) {
+      ++it;
+      pfun<G75>(ps, L, c, fL, dL);
+      pfun<G75>(ps, R, c, fR, dR);
+      double pn = ps - (fL + fR + du) / (dL + dR);
+      if (pn < 1e-8 * ps) pn = 1e-8 * ps;
+      dp = pn - ps;
+      // relative change 2|dp|/(p_new + p_old) <= 1e-12, written without a division
+      bool done = 2.0 * fabs(dp) <= 1e-12 * (pn + ps);
+      ps = pn;
+      if (done) { conv = true; break; }
+    }
+    st.maxit = max(st.maxit, it);
+    if (!conv) st.noconv = 1;
+    // star velocity at the converged p*: the last iterate's f and f' extrapolated over
+    // the final (<= 1e-12 relative) Newton update; the neglected term is O(dp^2)
+    double us = 0.5 * (uL + uR) + 0.5 * ((fR + dR * dp) - (fL + dL * dp));
+    p = ps;
+    int br;
+    if (0.0 <= us) {
+      t1 = aL; t2 = bL;
+      if (ps > pL) {
+        double q = ps * L.ip;
+        double sL = uL - cL * sqrt(c.gp1_2g * q + c.gm1_2g);
+        if (0.0 <= sL) { rho = rL; un = uL; p = pL; br = GR_LEFT; }
+        else { rho = rL * (q + c.kshock) * frcp(c.kshock * q + 1.0); un = us; br = GR_STAR_L_SHOCK; }
+      } else {
+        double sHL = uL - cL;
+        if (0.0 <= sHL) { rho = rL; un = uL; p = pL; br = GR_LEFT; }
+        else {
+          Pow3<G75> w(ps * L.ip, c);
+          double sTL = us - cL * w.p17;
+          if (0.0 > sTL) { rho = rL * w.p57; un = us; br = GR_STAR_L_RARE; }
+          else {
+            double cc = c.a2 * (cL + c.half_gm1 * uL);
+            double ratio = cc / cL;
+            rho = rL * ipow_fan_rho<G75>(ratio, c); un = cc; p = pL * ipow_fan_p<G75>(ratio, c);
+            br = GR_FAN_L;
+          }
+        }
+      }
+    } else {
+      t1 = aR; t2 = bR;
+      if (ps > pR) {
+        double q = ps * R.ip;
+        double sR = uR + cR * sqrt(c.gp1_2g * q + c.gm1_2g);
+        if (0.0 >= sR) { rho = rR; un = uR; p = pR; br = GR_RIGHT; }
+        else { rho = rR * (q + c.kshock) * frcp(c.kshock * q + 1.0); un = us; br = GR_STAR_R_SHOCK; }
+      } else {
+        double sHR = uR + cR;
+        if (0.0 >= sHR) { rho = rR; un = uR; p = pR; br = GR_RIGHT; }
+        else {
+          Pow3<G75> w(ps * R.ip, c);
+          double sTR = us + cR * w.p17;
+          if (0.0 <= sTR) { rho = rR * w.p57; un = us; br = GR_STAR_R_RARE; }
+          else {
+            double cc = c.a2 * (cR - c.half_gm1 * uR);
+            double ratio = cc / cR;
+            rho = rR * ipow_fan_rho<G75>(ratio, c); un = -cc; p = pR * ipow_fan_p<G75>(ratio, c);
+            br = GR_FAN_R;
+          }
+        }
+      }
+    }
+    if constexpr (REC) { rec->branch = br; rec->ps = ps; rec->us = us; }
+  }
+  if constexpr (REC) { rec->rho = rho; rec->un = un; rec->t1 = t1; rec->t2 = t2; rec->p = p; }
+  double en = p * c.inv_gm1 + 0.5 * rho * (un * un + t1 * t1 + t2 * t2);
+  double m = rho * un;
+  fl[0] = m;
+  fl[1] = m * un + p;
+  fl[2] = m * t1;
+  fl[3] = m * t2;
+  fl[4] = (en + p) * un;
+}
+
+// Exact pressureless Riemann problem at x/t = 0 (Sect. 2.9): diverging or equal streams
+// leave vacuum between them (upwind state or zero flux); converging streams form a
+// delta shock of speed (sqrt(rho_L) u_L + sqrt(rho_R) u_R)/(sqrt(rho_L) + sqrt(rho_R)),
+// the flux being the upwind one and the mean of both at a standing shock.  The sign
+// of the shock speed is formed without contraction so that mirrored states give zero.
+// With REC the side taken is stored in *rec: -1 left, +1 right, 0 mean, 2 no flux.
+template <bool REC = false>
+__device__ void dust_riemann(double rL, double uL, double aL, double bL, double rR, double uR,
+                             double aR, double bR, double fl[4], int* rec = nullptr) {
+#pragma clang fp contract(off)
+  fl[0] = 0.0; fl[1] = 0.0; fl[2] = 0.0; fl[3] = 0.0;
+  if constexpr (REC) *rec = 2;
+  if (!(rL > 0.0)) { rL = 0.0; uL = 0.0; aL = 0.0; bL = 0.0; }
+  if (!(rR > 0.0)) { rR = 0.0; uR = 0.0; aR = 0.0; bR = 0.0; }
+  if (rL + rR == 0.0) return;
+  int side;  // -1 left, +1 right, 0 mean
+  if (uL <= uR) {
+    if (uL > 0.0) side = -1;
+    else if (uR < 0.0) side = 1;
+    else return;
+  } else {
+    double xa = sqrt(rL) * uL;
+    double xb = sqrt(rR) * uR;
+    double num = xa + xb;
+    side = num > 0.0 ? -1 : (num < 0.0 ? 1 : 0);
+  }
+  if constexpr (REC) *rec = side;
+  double mL = rL * uL, mR = rR * uR;
+  if (side < 0) { fl[0] = mL; fl[1] = mL * uL; fl[2] = mL * aL; fl[3] = mL * bL; }
+  else if (side > 0) { fl[0] = mR; fl[1] = mR * uR; fl[2] = mR * aR; fl[3] = mR * bR; }
+  else {
+    fl[0] = 0.5 * (mL + mR);
+    fl[1] = 0.5 * (mL * uL + mR * uR);
+    fl[2] = 0.5 * (mL * aL + mR * aR);
+    fl[3] = 0.5 * (mL * bL + mR * bR);
+  }
+}
+
+// normal / tangential velocity slots of direction DIR (0 r, 1 theta, 2 z)
+template <int DIR> struct Dirs {
+  static constexpr int n = DIR;
+  static constexpr int t1 = DIR == 0 ? 1 : 0;
+  static constexpr int t2 = DIR == 2 ? 1 : 2;
+};
+
+struct Prim5 {
+  double rho, irho, un, t1, t2, p;
+};
+
+template <int DIR>
+__device__ __forceinline__ Prim5 gas_prim(const double q[5], double gm1) {
+  Prim5 w;
+  double inv = frcp(q[4]);
+  w.irho = inv;
+  double u = q[0] * inv, v = q[1] * inv, z = q[2] * inv;
+  w.rho = q[4];
+  w.p = gm1 * (q[3] - 0.5 * (q[0] * u + q[1] * v + q[2] * z));
+  double vel[3] = {u, v, z};
+  w.un = vel[Dirs<DIR>::n];
+  w.t1 = vel[Dirs<DIR>::t1];
+  w.t2 = vel[Dirs<DIR>::t2];
+  return w;
+}
+
+// Reconstructed gas face states (Sect. 2.7: E0 at the face + E' + limited parabola
+// increment), positivity fallback to the cell-centre state, exact Riemann problem,
+// F* = F(E*) in field order.  Cells A, B | C, D along DIR; the face lies between B and C.
+template <int DIR, bool G75>
+__device__ __forceinline__ void gas_face(const GasC& c, const double* eA, const double* eB,
+                                         const double* eC, const double* eD, const double* coB,
+                                         const double* coC, const double* bgf, const double* cenB,
+                                         double sB, const double* cenC, double sC, double F[5],
+                                         TStat& st) {
+  double qL[5], qR[5];
+#pragma unroll
+  for (int f = 0; f < 5; ++f) {
+    double iB, iC;
+    if (DIR == 0) {
+      iB = inc_up_c(eA[f], eB[f], eC[f], coB);
+      iC = inc_lo_c(eB[f], eC[f], eD[f], coC);
+    } else {
+      iB = inc_up_u(eA[f], eB[f], eC[f]);
+      iC = inc_lo_u(eB[f], eC[f], eD[f]);
+    }
+    qL[f] = bgf[f] + (eB[f] + iB);
+    qR[f] = bgf[f] + (eC[f] + iC);
+  }
+  Prim5 L = gas_prim<DIR>(qL, c.gm1);
+  Prim5 R = gas_prim<DIR>(qR, c.gm1);
+  if (!(L.rho > 0.0 && L.p > 0.0)) {
+#pragma unroll
+    for (int f = 0; f < 5; ++f) qL[f] = cenB[f] + sB * eB[f];
+    L = gas_prim<DIR>(qL, c.gm1);
+    st.fall++;
+  }
+  if (!(R.rho > 0.0 && R.p > 0.0)) {
+#pragma unroll
+    for (int f = 0; f < 5; ++f) qR[f] = cenC[f] + sC * eC[f];
+    R = gas_prim<DIR>(qR, c.gm1);
+    st.fall++;
+  }
+  double fl[5];
+  gas_riemann<G75>(c, L.rho, L.irho, L.un, L.t1, L.t2, L.p, R.rho, R.irho, R.un, R.t1, R.t2, R.p,
+                   fl, st);
+  F[4] = fl[0];
+  F[Dirs<DIR>::n] = fl[1];
+  F[Dirs<DIR>::t1] = fl[2];
+  F[Dirs<DIR>::t2] = fl[3];
+  F[3] = fl[4];
+}
+
+// Dust face: the dust variables are reconstructed whole (no stationary reference);
+// a face density below zero falls back to the cell-centre state.
+template <int DIR>
+__device__ __forceinline__ void dust_face(const double* eA, const double* eB, const double* eC,
+                                          const double* eD, const double* coB, const double* coC,
+                                          double F[4], TStat& st) {
+  double qL[4], qR[4];
+#pragma unroll
+  for (int f = 0; f < 4; ++f) {
+    double iB, iC;
+    if (DIR == 0) {
+      iB = inc_up_c(eA[f], eB[f], eC[f], coB);
+      iC = inc_lo_c(eB[f], eC[f], eD[f], coC);
+    } else {
+      iB = inc_up_u(eA[f], eB[f], eC[f]);
+      iC = inc_lo_u(eB[f], eC[f], eD[f]);
+    }
+    qL[f] = eB[f] + iB;
+    qR[f] = eC[f] + iC;
+  }
+  if (qL[3] < 0.0) {
+#pragma unroll
+    for (int f = 0; f < 4; ++f) qL[f] = eB[f];
+    st.fall++;
+  }
+  if (qR[3] < 0.0) {
+#pragma unroll
+    for (int f = 0; f < 4; ++f) qR[f] = eC[f];
+    st.fall++;
+  }
+  double vL[3] = {0.0, 0.0, 0.0}, vR[3] = {0.0, 0.0, 0.0};
+  if (qL[3] > 0.0) {
+    double inv = 1.0 / qL[3];
+    vL[0] = qL[0] * inv; vL[1] = qL[1] * inv; vL[2] = qL[2] * inv;
+  }
+  if (qR[3] > 0.0) {
+    double inv = 1.0 / qR[3];
+    vR[0] = qR[0] * inv; vR[1] = qR[1] * inv; vR[2] = qR[2] * inv;
+  }
+  double fl[4];
+  dust_riemann(qL[3], vL[Dirs<DIR>::n], vL[Dirs<DIR>::t1], vL[Dirs<DIR>::t2], qR[3],
+               vR[Dirs<DIR>::n], vR[Dirs<DIR>::t1], vR[Dirs<DIR>::t2], fl);
+  F[3] = fl[0];
+  F[Dirs<DIR>::n] = fl[1];
+  F[Dirs<DIR>::t1] = fl[2];
+  F[Dirs<DIR>::t2] = fl[3];
+}
+
+}  // namespace rb
+
+#include "rb_pert32.h"
+
+namespace rb {
+
+// FP32-perturbation gas face: reconstructed perturbations about the face background,
+// the perturbation Riemann problem and the flux change dF = F* - F(W0); faces the FP32
+// form cannot take (strong perturbation, transonic fan, no convergence, non-positive
+// face state) are re-solved in FP64 on the full states.
+template <int DIR>
+__device__ __forceinline__ void gas_face_p32(const GasC& c, const float* eA, const float* eB,
+                                             const float* eC, const float* eD, const double* coB,
+                                             const double* coC, const double* bgf,
+                                             const double* cenB, double sB, const double* cenC,
+                                             double sC, float F[5], TStat& st) {
+  float qL[5], qR[5];
+#pragma unroll
+  for (int f = 0; f < 5; ++f) {
+    float iB, iC;
+    if (DIR == 0) {
+      iB = inc_up_c<float>(eA[f], eB[f], eC[f], coB);
+      iC = inc_lo_c<float>(eB[f], eC[f], eD[f], coC);
+    } else {
+      iB = inc_up_u<float>(eA[f], eB[f], eC[f]);
+      iC = inc_lo_u<float>(eB[f], eC[f], eD[f]);
+    }
+    qL[f] = eB[f] + iB;
+    qR[f] = eC[f] + iC;
+  }
+  const BgW b = bg_prims<DIR>(bgf, c.g);
+  const float gm1 = (float)c.gm1;
+  const PW L = pert_prims<DIR>(b, qL, gm1);
+  const PW R = pert_prims<DIR>(b, qR, gm1);
+  const bool okL = (b.rho + (double)L.rho > 0.0) && (b.p + (double)L.p > 0.0);
+  const bool okR = (b.rho + (double)R.rho > 0.0) && (b.p + (double)R.p > 0.0);
+  PW W;
+  float fl[5];
+  if (okL && okR && riemann_pert(b, L, R, c, W, st)) {
+    flux_pert(b, W, (float)c.inv_gm1, fl);
+  } else {
+    st.resolve++;
+    double qL64[5], qR64[5];
+#pragma unroll
+    for (int f = 0; f < 5; ++f) {
+      qL64[f] = okL ? bgf[f] + (double)qL[f] : cenB[f] + sB * (double)eB[f];
+      qR64[f] = okR ? bgf[f] + (double)qR[f] : cenC[f] + sC * (double)eC[f];
+    }
+    if (!okL) st.fall++;
+    if (!okR) st.fall++;
+    const Prim5 PL = gas_prim<DIR>(qL64, c.gm1);
+    const Prim5 PR = gas_prim<DIR>(qR64, c.gm1);
+    double f64[5];
+    gas_riemann<true>(c, PL.rho, PL.irho, PL.un, PL.t1, PL.t2, PL.p, PR.rho, PR.irho, PR.un, PR.t1,
+                      PR.t2, PR.p, f64, st);
+    const double m0 = b.rho * b.un;
+    fl[0] = (float)(f64[0] - m0);
+    fl[1] = (float)(f64[1] - (m0 * b.un + b.p));
+    fl[2] = (float)(f64[2] - m0 * b.t1);
+    fl[3] = (float)(f64[3] - m0 * b.t2);
+    fl[4] = (float)(f64[4] - b.h * b.un);
+  }
+  F[4] = fl[0];
+  F[Dirs<DIR>::n] = fl[1];
+  F[Dirs<DIR>::t1] = fl[2];
+  F[Dirs<DIR>::t2] = fl[3];
+  F[3] = fl[4];
+}
+
+// ------------------------------------------------------------------------------------
+// state access with ghost cells (Sect. 2.4): r and z ghosts come from tables, theta wraps
+
+// FP32-perturbation storage layout: the gas deviation (5 fields) and the dust momenta
+// (3 per species, divided by the species' initial-layer density) in FP32, then the dust
+// densities in FP64 (mass is accumulated in FP64).  f64_base: first double of that part.
+__device__ __forceinline__ size_t p32_f64_base(const Geo& g) {
+  return (((size_t)(5 + 3 * g.nd) * g.N + 63) / 64 * 64) / 2;
+}
+
+// interior value of field f (FP64 storage, or the FP32-perturbation layout above)
+template <bool P32>
+__device__ __forceinline__ double ld_cell(const StageArgs& a, const void* st, int f, int k, int i,
+                                          size_t cell) {
+  const Geo& g = a.g;
+  if (P32) {
+    if (f < 5) return (double)((const float*)st)[(size_t)f * g.N + cell];
+    const int sp = (f - 5) >> 2, c = (f - 5) & 3;
+    if (c == 3) return ((const double*)st)[p32_f64_base(g) + (size_t)sp * g.N + cell];
+    const double v = (double)((const float*)st)[(size_t)(5 + 3 * sp + c) * g.N + cell];
+    return v * a.t.dsc[((size_t)sp * g.nz + k) * g.nr + i];
+  }
+  return ((const double*)st)[(size_t)f * g.N + cell];
+}
+
+template <bool P32>
+__device__ __forceinline__ void st_cell(const StageArgs& a, void* st, int f, int k, int i,
+                                        size_t cell, double v) {
+  const Geo& g = a.g;
+  if (P32) {
+    if (f < 5) { ((float*)st)[(size_t)f * g.N + cell] = (float)v; return; }
+    const int sp = (f - 5) >> 2, c = (f - 5) & 3;
+    if (c == 3) { ((double*)st)[p32_f64_base(g) + (size_t)sp * g.N + cell] = v; return; }
+    v /= a.t.dsc[((size_t)sp * g.nz + k) * g.nr + i];
+    ((float*)st)[(size_t)(5 + 3 * sp + c) * g.N + cell] = (float)v;
+  } else {
+    ((double*)st)[(size_t)f * g.N + cell] = v;
+  }
+}
+
+template <bool P32>
+__device__ __forceinline__ double fetch(const StageArgs& a, const void* st, int f, int k, int i,
+                                        int j) {
+  const Geo& g = a.g;
+  if (k < 0 || k >= g.nz) {
+    int side = k < 0 ? 0 : 1;
+    int layer = min(k < 0 ? -1 - k : k - g.nz, 1);
+    int ii = min(max(i, 0), g.nr - 1);
+    return a.t.ghz[((size_t)(side * 2 + layer) * g.nr + ii) * g.nf + f];
+  }
+  if (i < 0 || i >= g.nr) {
+    int side = i < 0 ? 0 : 1;
+    int layer = min(i < 0 ? -1 - i : i - g.nr, 1);
+    return a.t.ghr[((size_t)(side * 2 + layer) * g.nz + k) * g.nf + f];
+  }
+  return ld_cell<P32>(a, st, f, k, i, ((size_t)k * g.nr + i) * g.nth + j);
+}
+
+// centre state used by the gas fallback: E0(centre) + E' for interior cells (scale 1),
+// the ghost's full state (scale 0) otherwise
+__device__ __forceinline__ const double* centre_ptr(const StageArgs& a, int k, int i, double& s) {
+  const Geo& g = a.g;
+  if (k < 0 || k >= g.nz) {
+    s = 0.0;
+    int ii = min(max(i, 0), g.nr - 1);
+    return a.t.ghzf + ((size_t)(k < 0 ? 0 : 1) * g.nr + ii) * 5;
+  }
+  if (i < 0 || i >= g.nr) {
+    s = 0.0;
+    return a.t.ghrf + ((size_t)(i < 0 ? 0 : 1) * g.nz + k) * 5;
+  }
+  s = 1.0;
+  return a.t.bgc + ((size_t)k * g.nr + i) * 5;
+}
+
+__device__ __forceinline__ const double* rco_ptr(const StageArgs& a, int i) {
+  int c = min(max(i, -1), a.g.nr);
+  return a.t.rco + (size_t)(c + 1) * RC_N;
+}
+
+__device__ __forceinline__ double wave_min(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o, 64));
+  return v;
+}
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+__device__ __forceinline__ int wave_isum(int v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+__device__ __forceinline__ int wave_imax(int v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
+// XCD-aware tile order: workgroup b is dispatched to XCD b % 8; give every XCD a
+// contiguous range of tiles so that halo re-reads hit its own L2.
+__device__ __forceinline__ int xcd_tile(int b, int nblk) {
+  int q = nblk >> 3, rem = nblk & 7, x = b & 7;
+  return x * q + min(x, rem) + (b >> 3);
+}
+
+}  // namespace rb

@@ -112,6 +112,20 @@ struct InitArgs {
   void* state;
 };
 
+// Vector-Jacobian product of one stage update E_out = base + c dt V^-1 (G(E) - R0):
+// out = base1 + base2 + (dE_out/dE)^T-part of G, i.e. out = base1 + base2 + J_G(E)^T w with
+// w = cw V^-1 cot (cot the cotangent of E_out).  FP64 state layout.
+struct AdjArgs {
+  StageArgs s;          // geometry and tables; s.in = E, the state the operator is taken at
+  const double* cot;    // cotangent of the stage output
+  const double* base1;  // added to out, may be null
+  const double* base2;  // added to out, may be null
+  double* out;
+  double cw;            // stage coefficient x dt
+  double* stpart;       // per-block Stokes-number partials (dust groups)
+  int tk, nkc;          // z chunking of the adjoint launch
+};
+
 // launchers (rb_kernels.hip)
 hipError_t launch_tables(const InitArgs& a, hipStream_t s);
 hipError_t launch_init_state(const InitArgs& a, hipStream_t s);
@@ -129,5 +143,12 @@ hipError_t launch_from_full(const StageArgs& a, const double* in, void* state, i
 hipError_t launch_mass(const StageArgs& a, const void* state, double* partials, int f,
                        int blocks, hipStream_t s);
 hipError_t launch_sum(const double* partials, int n, double* out, hipStream_t s);
+// d(initial state)/d(vortex amplitude) contracted with a state cotangent, per cell
+hipError_t launch_amp_grad(const InitArgs& a, const double* lam, double* out, hipStream_t s);
+
+// launchers (rb_adjoint.hip)
+hipError_t launch_adj_group(const AdjArgs& a, int blocks, int group, hipStream_t s);
+// acc[species] += sum of the per-block Stokes partials (one block, fixed order)
+hipError_t launch_st_accum(const double* parts, int nblocks, double* acc, hipStream_t s);
 
 }  // namespace rb

@@ -65,14 +65,15 @@ class rb_diag(ctypes.Structure):
         ("fallbacks", ctypes.c_int64), ("vacuum_faces", ctypes.c_int64),
         ("max_newton", ctypes.c_int32), ("pad", ctypes.c_int32),
         ("mass", ctypes.c_double * 5), ("outflow", ctypes.c_double * 5),
-        ("dt_last", ctypes.c_double),
+        ("dt_last", ctypes.c_double), ("fp64_resolves", ctypes.c_int64),
     ]
 
 
 # names exported by the library, in the order of include/rossbi_mi355x.h
 EXPORTS = ("rb_query_sizes", "rb_init_state", "rb_step", "rb_get_fields", "rb_set_fields",
            "rb_eval_operator", "rb_get_residual", "rb_cfl_dt", "rb_diagnostics", "rb_profile",
-           "rb_profile_read", "rb_last_error", "rb_destroy")
+           "rb_profile_read", "rb_adjoint_workspace", "rb_record", "rb_adjoint",
+           "rb_amp_gradient", "rb_last_error", "rb_destroy")
 
 _lib = None
 
@@ -101,6 +102,13 @@ def load() -> ctypes.CDLL:
     L.rb_diagnostics.argtypes = [ctypes.c_void_p, ctypes.POINTER(rb_diag)]
     L.rb_profile.argtypes = [ctypes.c_void_p, ctypes.c_int]
     L.rb_profile_read.argtypes = [ctypes.c_void_p, _D, ctypes.POINTER(ctypes.c_int64)]
+    L.rb_adjoint_workspace.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int,
+                                       ctypes.POINTER(ctypes.c_size_t)]
+    L.rb_record.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int,
+                            ctypes.POINTER(rb_dt_policy), _D, ctypes.c_void_p, ctypes.c_size_t]
+    L.rb_adjoint.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, _D,
+                             ctypes.c_void_p, ctypes.c_size_t]
+    L.rb_amp_gradient.argtypes = [ctypes.c_void_p, _D, _D, ctypes.c_void_p, ctypes.c_void_p]
     L.rb_last_error.argtypes = [ctypes.c_void_p]
     L.rb_last_error.restype = ctypes.c_char_p
     L.rb_destroy.argtypes = [ctypes.c_void_p]
@@ -197,8 +205,8 @@ class Sim:
     def error(self) -> str:
         return self.lib.rb_last_error(self.ctx).decode()
 
-    def step(self, n: int, dt: float | None = None, dt_list=None, check: bool = False):
-        """rb_step: n steps (CFL default, fixed dt, or dt list). Returns (status, dts)."""
+    @staticmethod
+    def _policy(dt, dt_list):
         pol = rb_dt_policy()
         lst = None
         if dt_list is not None:
@@ -208,6 +216,11 @@ class Sim:
             pol.kind, pol.dt = RB_DT_FIXED, float(dt)
         else:
             pol.kind = RB_DT_CFL
+        return pol, lst
+
+    def step(self, n: int, dt: float | None = None, dt_list=None, check: bool = False):
+        """rb_step: n steps (CFL default, fixed dt, or dt list). Returns (status, dts)."""
+        pol, lst = self._policy(dt, dt_list)
         dts = np.zeros(max(n, 1))
         st = self.lib.rb_step(self.ctx, n, ctypes.byref(pol), _ptr(dts))
         if check and st != RB_OK:
@@ -271,3 +284,121 @@ class Sim:
 
     def mass(self) -> np.ndarray:
         return np.array(self.diagnostics().mass)[: 1 + self.cfg.n_dust]
+
+    # ---- discrete adjoint
+    def record(self, n: int, ckpt_every: int = 20, dt: float | None = None, dt_list=None):
+        """rb_record: n steps with checkpoints every ckpt_every steps (workspace held by
+        this object until the next record).  Returns the time steps."""
+        import torch
+        size = ctypes.c_size_t()
+        st = self.lib.rb_adjoint_workspace(self.ctx, n, ckpt_every, ctypes.byref(size))
+        if st != RB_OK:
+            raise RbError(st, "rb_adjoint_workspace")
+        self._ws = torch.empty(size.value, dtype=torch.uint8, device=self.state.device)
+        pol, lst = self._policy(dt, dt_list)
+        dts = np.zeros(n)
+        st = self.lib.rb_record(self.ctx, n, ckpt_every, ctypes.byref(pol), _ptr(dts),
+                                ctypes.c_void_p(self._ws.data_ptr()), size.value)
+        if st != RB_OK:
+            raise RbError(st, self.error())
+        return dts
+
+    def adjoint(self, lam_final):
+        """rb_adjoint: lam_final = dJ/dE after the recorded steps (array or torch tensor of
+        the fields' shape).  Returns (dJ/dE before them as a float64 device tensor,
+        dJ/dSt per dust species)."""
+        import torch
+        lam = torch.as_tensor(lam_final, dtype=torch.float64, device=self.state.device)
+        lam = lam.reshape(self.shape).contiguous()
+        grad = torch.empty_like(lam)
+        gst = np.zeros(max(self.cfg.n_dust, 1))
+        st = self.lib.rb_adjoint(self.ctx, ctypes.c_void_p(lam.data_ptr()),
+                                 ctypes.c_void_p(grad.data_ptr()), _ptr(gst),
+                                 ctypes.c_void_p(self._ws.data_ptr()), self._ws.numel())
+        if st != RB_OK:
+            raise RbError(st, self.error())
+        return grad, gst[: self.cfg.n_dust]
+
+    def amp_gradient(self, grad_state0, noise=None, amp=None):
+        """rb_amp_gradient: dJ/dA per cell from dJ/dE of the initial state (noise and amp
+        as given at initialisation).  Returns a float64 device tensor (nz, nr, ntheta)."""
+        import torch
+        lam = torch.as_tensor(grad_state0, dtype=torch.float64, device=self.state.device)
+        lam = lam.reshape(self.shape).contiguous()
+        out = torch.empty(self.shape[1:], dtype=torch.float64, device=self.state.device)
+        nz = None if noise is None else np.ascontiguousarray(noise, dtype=np.float64)
+        am = None if amp is None else np.ascontiguousarray(amp, dtype=np.float64)
+        st = self.lib.rb_amp_gradient(self.ctx, _ptr(nz), _ptr(am), ctypes.c_void_p(lam.data_ptr()),
+                                      ctypes.c_void_p(out.data_ptr()))
+        if st != RB_OK:
+            raise RbError(st, self.error())
+        return out
+
+
+def radial_faces(cfg: synth.Config) -> np.ndarray:
+    """Radial face positions of the mesh (log-spaced or uniform)."""
+    i = np.arange(cfg.nr + 1, dtype=np.float64)
+    if cfg.log_r:
+        return cfg.r_in * (cfg.r_out / cfg.r_in) ** (i / cfg.nr)
+    return cfg.r_in + (cfg.r_out - cfg.r_in) * i / cfg.nr
+
+
+def cell_centres_r(cfg: synth.Config) -> np.ndarray:
+    """Radial cell centres, the mid-points of the radial faces."""
+    rf = radial_faces(cfg)
+    return 0.5 * (rf[1:] + rf[:-1])
+
+
+def cell_volumes(cfg: synth.Config) -> np.ndarray:
+    """Cell volumes per radial row (1/2 (r+^2 - r-^2) dtheta dz)."""
+    rf = radial_faces(cfg)
+    dth = 2.0 * np.pi / cfg.nth
+    dz = 1.0 if cfg.nz == 1 else 2.0 * cfg.z_half / cfg.nz
+    return 0.5 * (rf[1:] ** 2 - rf[:-1] ** 2) * dth * dz
+
+
+def _make_disc_run():
+    import torch
+
+    class DiscRun(torch.autograd.Function):
+        """n RK2 steps of the disc from its initial state, differentiable with respect to
+        the per-cell vortex amplitude field and the Stokes numbers.  Forward: rb_record
+        (checkpoints every ckpt_every steps); backward: rb_adjoint + rb_amp_gradient.
+        Returns the final fields (float64, on the device)."""
+
+        @staticmethod
+        def forward(ctx, amp, stokes, cfg, n, ckpt_every, noise, dt_list):
+            st_vals = tuple(float(v) for v in stokes.detach().cpu().numpy())
+            c2 = cfg.with_(stokes=st_vals) if cfg.n_dust else cfg
+            amp_np = amp.detach().cpu().numpy().astype(np.float64).reshape(cfg.nz, cfg.nr, cfg.nth)
+            sim = Sim(c2, noise=noise, amp=amp_np, device=amp.device if amp.is_cuda else "cuda")
+            dts = sim.record(n, ckpt_every, dt_list=dt_list)
+            out = torch.as_tensor(sim.fields(), device=sim.state.device)
+            ctx.sim, ctx.noise, ctx.amp_np, ctx.dts = sim, noise, amp_np, dts
+            ctx.amp_shape, ctx.amp_device = amp.shape, amp.device
+            return out
+
+        @staticmethod
+        def backward(ctx, grad_out):
+            sim = ctx.sim
+            g0, gst = sim.adjoint(grad_out.detach())
+            gamp = sim.amp_gradient(g0, noise=ctx.noise, amp=ctx.amp_np)
+            sim.close()
+            ctx.sim = None
+            gamp = gamp.reshape(ctx.amp_shape).to(ctx.amp_device)
+            gst_t = torch.as_tensor(gst, dtype=torch.float64)
+            return gamp, gst_t, None, None, None, None, None
+
+    return DiscRun
+
+
+_disc_run = None
+
+
+def disc_run(amp, stokes, cfg: synth.Config, n: int, ckpt_every: int = 20, noise=None,
+             dt_list=None):
+    """Differentiable n-step disc run (torch.autograd): see DiscRun."""
+    global _disc_run
+    if _disc_run is None:
+        _disc_run = _make_disc_run()
+    return _disc_run.apply(amp, stokes, cfg, n, ckpt_every, noise, dt_list)
