@@ -42,10 +42,16 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
+KERNEL_SOURCES = ("rb_kernels.hip", "rb_device.h", "rb_pert32.h", "rb_internal.h")
+
+
 def kernel_hash():
-    p = os.path.join(ROOT, "paper_2207_04252_amd", "csrc", "rb_kernels.hip")
-    with open(p, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    """Hash of the sources the stage kernels are compiled from."""
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2207_04252_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
 def measured_traffic(workload):
