@@ -11,12 +11,15 @@
 // solves are recomputed with the forward solver itself (recording variant), so every
 // branch decision is the forward run's.
 //
-// Layout follows the forward stage kernel: a workgroup owns a 64 (theta) x 8 (r) tile
-// and marches through a chunk of z planes.  Each plane is staged in LDS with a
-// three-cell halo (a cell receives contributions from the faces 3/2 cells away); the
-// contributions of the theta and r faces to the tile's cells are accumulated in LDS in
-// a fixed order, one phase per stencil position, so results are deterministic.  The z
-// faces run from registers, one plane behind.
+// k_adj_plane follows the forward stage kernel's tiles: a workgroup owns a 64 (theta) x
+// 8 (r) tile and a chunk of z planes.  Each plane is staged in LDS with a three-cell halo
+// (a cell receives contributions from the faces 3/2 cells away); the contributions of
+// the theta and r faces to the tile's cells are accumulated in LDS in a fixed order, one
+// phase per stencil position, so results are deterministic.  k_adj_z then marches every
+// column upwards in registers and adds the z faces' contributions, each cell's in the
+// order of its faces.
+#include <algorithm>
+
 #include "rb_device.h"
 
 namespace rb {
@@ -229,76 +232,116 @@ __device__ __forceinline__ void prim_rev(const double q[5], double gm1, const do
 }
 
 // Reverse of one gas face: Fb (field order) is the cotangent of the face flux; the
-// contributions to the stencil cells A, B | C, D are added to cA..cD.
-template <int DIR, bool G75>
-__device__ void gas_face_vjp(const GasC& c, const double* eA, const double* eB, const double* eC,
-                             const double* eD, const double* coB, const double* coC,
-                             const double* bgf, const double* cenB, double sB,
-                             const double* cenC, double sC, const double* Fb, double* cA,
-                             double* cB, double* cC, double* cD) {
-  double qL[5], qR[5], cmB[5], cpB[5], cmC[5], cpC[5];
+// contributions to the stencil cells A, B | C, D are added to cA..cD.  The face states
+// are rebuilt for the reverse sweep rather than kept across the solve (registers).
+template <int DIR>
+__device__ __forceinline__ void gas_face_states(const double* eA, const double* eB,
+                                                const double* eC, const double* eD,
+                                                const double* coB, const double* coC,
+                                                const double* bgf, double qL[5], double qR[5]) {
 #pragma unroll
   for (int f = 0; f < 5; ++f) {
     double iB, iC;
     if (DIR == 0) {
       iB = inc_up_c(eA[f], eB[f], eC[f], coB);
       iC = inc_lo_c(eB[f], eC[f], eD[f], coC);
-      dinc_up_c(eA[f], eB[f], eC[f], coB, cmB[f], cpB[f]);
-      dinc_lo_c(eB[f], eC[f], eD[f], coC, cmC[f], cpC[f]);
     } else {
       iB = inc_up_u(eA[f], eB[f], eC[f]);
       iC = inc_lo_u(eB[f], eC[f], eD[f]);
-      dinc_up_u(eA[f], eB[f], eC[f], cmB[f], cpB[f]);
-      dinc_lo_u(eB[f], eC[f], eD[f], cmC[f], cpC[f]);
     }
     qL[f] = bgf[f] + (eB[f] + iB);
     qR[f] = bgf[f] + (eC[f] + iC);
   }
+}
+
+template <int DIR, bool G75>
+__device__ void gas_face_vjp(const GasC& c, const double* eA, const double* eB, const double* eC,
+                             const double* eD, const double* coB, const double* coC,
+                             const double* bgf, const double* cenB, double sB,
+                             const double* cenC, double sC, const double* Fb, double* cA,
+                             double* cB, double* cC, double* cD) {
+  double qL[5], qR[5];
+  gas_face_states<DIR>(eA, eB, eC, eD, coB, coC, bgf, qL, qR);
   Prim5 L = gas_prim<DIR>(qL, c.gm1);
   Prim5 R = gas_prim<DIR>(qR, c.gm1);
-  bool fbL = false, fbR = false;
-  if (!(L.rho > 0.0 && L.p > 0.0)) {
+  const bool fbL = !(L.rho > 0.0 && L.p > 0.0);
+  const bool fbR = !(R.rho > 0.0 && R.p > 0.0);
+  if (fbL) {
 #pragma unroll
     for (int f = 0; f < 5; ++f) qL[f] = cenB[f] + sB * eB[f];
     L = gas_prim<DIR>(qL, c.gm1);
-    fbL = true;
   }
-  if (!(R.rho > 0.0 && R.p > 0.0)) {
+  if (fbR) {
 #pragma unroll
     for (int f = 0; f < 5; ++f) qR[f] = cenC[f] + sC * eC[f];
     R = gas_prim<DIR>(qR, c.gm1);
-    fbR = true;
   }
-  double fl[5];
-  TStat st = {0, 0, 0, 0, 0};
-  GasRec rec;
-  gas_riemann<G75, true>(c, L.rho, L.irho, L.un, L.t1, L.t2, L.p, R.rho, R.irho, R.un, R.t1, R.t2,
-                         R.p, fl, st, &rec);
-  const double flb[5] = {Fb[4], Fb[Dirs<DIR>::n], Fb[Dirs<DIR>::t1], Fb[Dirs<DIR>::t2], Fb[3]};
-  double Wb[5];
-  flux_rev(c, rec, flb, Wb);
-  const double WL[5] = {L.rho, L.un, L.t1, L.t2, L.p};
-  const double WR[5] = {R.rho, R.un, R.t1, R.t2, R.p};
   double WLb[5], WRb[5];
-  riemann_rev<G75>(c, WL, WR, rec, Wb, WLb, WRb);
-  double qLb[5], qRb[5];
-  prim_rev<DIR>(qL, c.gm1, WLb, qLb);
-  prim_rev<DIR>(qR, c.gm1, WRb, qRb);
+  {
+    double fl[5];
+    TStat st = {0, 0, 0, 0, 0};
+    GasRec rec;
+    gas_riemann<G75, true>(c, L.rho, L.irho, L.un, L.t1, L.t2, L.p, R.rho, R.irho, R.un, R.t1,
+                           R.t2, R.p, fl, st, &rec);
+    const double flb[5] = {Fb[4], Fb[Dirs<DIR>::n], Fb[Dirs<DIR>::t1], Fb[Dirs<DIR>::t2], Fb[3]};
+    double Wb[5];
+    flux_rev(c, rec, flb, Wb);
+    const double WL[5] = {L.rho, L.un, L.t1, L.t2, L.p};
+    const double WR[5] = {R.rho, R.un, R.t1, R.t2, R.p};
+    riemann_rev<G75>(c, WL, WR, rec, Wb, WLb, WRb);
+  }
+  // left face state -> cells A, B, C (or B alone after a fallback)
+  {
+    double qb[5];
+    if (!fbL) {
+      double q2[5], q3[5];
+      gas_face_states<DIR>(eA, eB, eC, eD, coB, coC, bgf, q2, q3);
+      prim_rev<DIR>(q2, c.gm1, WLb, qb);
+    } else {
+      double q2[5];
 #pragma unroll
-  for (int f = 0; f < 5; ++f) {
-    if (fbL) {
-      cB[f] += sB * qLb[f];
-    } else {
-      cA[f] -= cmB[f] * qLb[f];
-      cB[f] += (1.0 + cmB[f] - cpB[f]) * qLb[f];
-      cC[f] += cpB[f] * qLb[f];
+      for (int f = 0; f < 5; ++f) q2[f] = cenB[f] + sB * eB[f];
+      prim_rev<DIR>(q2, c.gm1, WLb, qb);
     }
-    if (fbR) {
-      cC[f] += sC * qRb[f];
+#pragma unroll
+    for (int f = 0; f < 5; ++f) {
+      if (fbL) {
+        cB[f] += sB * qb[f];
+      } else {
+        double cm, cp;
+        if (DIR == 0) dinc_up_c(eA[f], eB[f], eC[f], coB, cm, cp);
+        else dinc_up_u(eA[f], eB[f], eC[f], cm, cp);
+        cA[f] -= cm * qb[f];
+        cB[f] += (1.0 + cm - cp) * qb[f];
+        cC[f] += cp * qb[f];
+      }
+    }
+  }
+  // right face state -> cells B, C, D (or C alone)
+  {
+    double qb[5];
+    if (!fbR) {
+      double q2[5], q3[5];
+      gas_face_states<DIR>(eA, eB, eC, eD, coB, coC, bgf, q2, q3);
+      prim_rev<DIR>(q3, c.gm1, WRb, qb);
     } else {
-      cB[f] -= cmC[f] * qRb[f];
-      cC[f] += (1.0 + cmC[f] - cpC[f]) * qRb[f];
-      cD[f] += cpC[f] * qRb[f];
+      double q3[5];
+#pragma unroll
+      for (int f = 0; f < 5; ++f) q3[f] = cenC[f] + sC * eC[f];
+      prim_rev<DIR>(q3, c.gm1, WRb, qb);
+    }
+#pragma unroll
+    for (int f = 0; f < 5; ++f) {
+      if (fbR) {
+        cC[f] += sC * qb[f];
+      } else {
+        double cm, cp;
+        if (DIR == 0) dinc_lo_c(eB[f], eC[f], eD[f], coC, cm, cp);
+        else dinc_lo_u(eB[f], eC[f], eD[f], cm, cp);
+        cB[f] -= cm * qb[f];
+        cC[f] += (1.0 + cm - cp) * qb[f];
+        cD[f] += cp * qb[f];
+      }
     }
   }
 }
@@ -390,21 +433,60 @@ __device__ void dust_face_vjp(const double* eA, const double* eB, const double* 
 }
 
 // ------------------------------------------------------------------------------------
-// the adjoint stage kernel
+// the adjoint stage kernels: the theta and r faces and the cell-local sources of a tile
+// of planes (k_adj_plane, LDS-staged), then the z faces of every column (k_adj_z,
+// registers only, adding into the output of the first).  Two kernels keep each one's
+// register footprint within the file (one kernel holding both spilled to scratch).
+
+// group-independent set-up shared by both kernels
+template <bool GAS>
+struct AdjCtx {
+  static constexpr int NG = GAS ? 5 : 4;
+  const AdjArgs& A;
+  const StageArgs& a;
+  const Geo& g;
+  GasC gc;
+  int F0;
+  __device__ AdjCtx(const AdjArgs& A_, int species)
+      : A(A_), a(A_.s), g(A_.s.g), gc(gas_consts(A_.s.g.gamma)), F0(GAS ? 0 : 5 + 4 * species) {}
+  __device__ int jwrap(int j) const {
+    j %= g.nth;
+    return j < 0 ? j + g.nth : j;
+  }
+  // w = cw V^-1 lambda of an interior cell (zero outside the grid)
+  __device__ double wc(int f, int k, int i, int j) const {
+    if (k < 0 || k >= g.nz || i < 0 || i >= g.nr) return 0.0;
+    return A.cw * a.t.rt[(size_t)i * RT_N + RT_INVV] *
+           A.cot[(size_t)(F0 + f) * g.N + ((size_t)k * g.nr + i) * g.nth + j];
+  }
+};
+
+template <int D, bool GAS, bool G75>
+__device__ __forceinline__ void face_vjp(const GasC& gc, const double* eA, const double* eB,
+                                         const double* eC, const double* eD, const double* coB,
+                                         const double* coC, const double* bgf, const double* cB,
+                                         double sB, const double* cC, double sC, const double* Fb,
+                                         double* oA, double* oB, double* oC, double* oD) {
+  if constexpr (GAS)
+    gas_face_vjp<D, G75>(gc, eA, eB, eC, eD, coB, coC, bgf, cB, sB, cC, sC, Fb, oA, oB, oC, oD);
+  else
+    dust_face_vjp<D>(eA, eB, eC, eD, coB, coC, Fb, oA, oB, oC, oD);
+}
 
 template <bool GAS, int ND, bool G75>
-__global__ void __launch_bounds__(NT) k_adj(AdjArgs A, int species) {
-  constexpr int NG = GAS ? 5 : 4;
+__global__ void __launch_bounds__(NT) k_adj_plane(AdjArgs A, int species) {
+  using C = AdjCtx<GAS>;
+  constexpr int NG = C::NG;
   constexpr int H = 3;
   __shared__ double s_e[NG][TI + 2 * H][TJ + 2 * H];
   __shared__ double s_at[NG][TI][TJ];
   __shared__ double s_ar[NG][TI][TJ];
   __shared__ double s_red[NT / 64];
 
-  const StageArgs& a = A.s;
-  const Geo& g = a.g;
-  const GasC gc = gas_consts(g.gamma);
-  const int F0 = GAS ? 0 : 5 + 4 * species;
+  const C X(A, species);
+  const StageArgs& a = X.a;
+  const Geo& g = X.g;
+  const int F0 = X.F0;
   const int tile = xcd_tile(blockIdx.x, gridDim.x);
   const int tjb = tile % a.ntj;
   const int tib = (tile / a.ntj) % a.nti;
@@ -417,145 +499,61 @@ __global__ void __launch_bounds__(NT) k_adj(AdjArgs A, int species) {
   const bool act = jg < g.nth && ig < g.nr;
   const bool colok = jg < g.nth;
   const int igc = min(ig, g.nr - 1);
-  const bool twod = g.twod != 0;
   const double* E = (const double*)a.in;
   const double* cot = A.cot;
   const size_t N = g.N;
   const double cw = A.cw;
   const double* rt = a.t.rt + (size_t)igc * RT_N;
-  const double invV = rt[RT_INVV], Az = rt[RT_AZ], invrc = rt[RT_INVRC], omk = rt[RT_OMK];
-
+  const double invrc = rt[RT_INVRC], omk = rt[RT_OMK];
   using DR = std::integral_constant<int, 0>;
   using DT = std::integral_constant<int, 1>;
-  using DZ = std::integral_constant<int, 2>;
-  auto face = [&](auto dirc, const double* eA, const double* eB, const double* eC,
-                  const double* eD, const double* coB, const double* coC, const double* bgf,
-                  const double* cB, double sB, const double* cC, double sC, const double* Fb,
-                  double* oA, double* oB, double* oC, double* oD) {
-    constexpr int D = decltype(dirc)::value;
-    if constexpr (GAS)
-      gas_face_vjp<D, G75>(gc, eA, eB, eC, eD, coB, coC, bgf, cB, sB, cC, sC, Fb, oA, oB, oC, oD);
-    else
-      dust_face_vjp<D>(eA, eB, eC, eD, coB, coC, Fb, oA, oB, oC, oD);
-  };
-  auto jwrap = [&](int j) {
-    j %= g.nth;
-    return j < 0 ? j + g.nth : j;
-  };
-  // w of an interior cell per unit face area: cw V^-1 lambda
-  auto wc = [&](int f, int k, int i, int j) -> double {
-    if (k < 0 || k >= g.nz || i < 0 || i >= g.nr) return 0.0;
-    return cw * a.t.rt[(size_t)i * RT_N + RT_INVV] *
-           cot[(size_t)(F0 + f) * N + ((size_t)k * g.nr + i) * g.nth + j];
-  };
 
-  // theta face between tile columns cb and cb + 1 (tile-relative, s_e column cb + H) of
-  // tile row r: contributions to columns cb - 1 .. cb + 2
+  // theta face between tile columns cb and cb + 1 (s_e column cb + H) of tile row r:
+  // contributions to columns cb - 1 .. cb + 2
   auto theta_face = [&](int k, int r, int cb, double* oA, double* oB, double* oC, double* oD) {
     double eA[NG], eB[NG], eC[NG], eD[NG], Fb[NG];
     const int i = i0 + r;
-    const int jb = jwrap(j0 + cb), jc = jwrap(j0 + cb + 1);
+    const int jb = X.jwrap(j0 + cb), jc = X.jwrap(j0 + cb + 1);
     const double ath = a.t.rt[(size_t)i * RT_N + RT_ATH];
 #pragma unroll
     for (int f = 0; f < NG; ++f) {
       eA[f] = s_e[f][r + H][cb + H - 1]; eB[f] = s_e[f][r + H][cb + H];
       eC[f] = s_e[f][r + H][cb + H + 1]; eD[f] = s_e[f][r + H][cb + H + 2];
-      Fb[f] = ath * (wc(f, k, i, jc) - wc(f, k, i, jb));
+      Fb[f] = ath * (X.wc(f, k, i, jc) - X.wc(f, k, i, jb));
       oA[f] = 0.0; oB[f] = 0.0; oC[f] = 0.0; oD[f] = 0.0;
     }
     const double* bgf = a.t.bgc + ((size_t)k * g.nr + i) * 5;
-    face(DT(), eA, eB, eC, eD, nullptr, nullptr, bgf, bgf, 1.0, bgf, 1.0, Fb, oA, oB, oC, oD);
+    face_vjp<DT::value, GAS, G75>(X.gc, eA, eB, eC, eD, nullptr, nullptr, bgf, bgf, 1.0, bgf, 1.0,
+                                  Fb, oA, oB, oC, oD);
   };
   // r face between tile rows rb and rb + 1 (s_e row rb + H) of tile column cl
   auto r_face = [&](int k, int rb, int cl, double* oA, double* oB, double* oC, double* oD) {
     double eA[NG], eB[NG], eC[NG], eD[NG], Fb[NG];
     const int ib = i0 + rb;
-    const int j = jwrap(j0 + cl);
+    const int j = X.jwrap(j0 + cl);
     const double ar = a.t.ar[ib + 1];
 #pragma unroll
     for (int f = 0; f < NG; ++f) {
       eA[f] = s_e[f][rb + H - 1][cl + H]; eB[f] = s_e[f][rb + H][cl + H];
       eC[f] = s_e[f][rb + H + 1][cl + H]; eD[f] = s_e[f][rb + H + 2][cl + H];
-      Fb[f] = ar * (wc(f, k, ib + 1, j) - wc(f, k, ib, j));
+      Fb[f] = ar * (X.wc(f, k, ib + 1, j) - X.wc(f, k, ib, j));
       oA[f] = 0.0; oB[f] = 0.0; oC[f] = 0.0; oD[f] = 0.0;
     }
     const double* bgf = a.t.bgr + ((size_t)k * (g.nr + 1) + (ib + 1)) * 5;
     double sB = 1.0, sC = 1.0;
     const double* cB = GAS ? centre_ptr(a, k, ib, sB) : nullptr;
     const double* cC = GAS ? centre_ptr(a, k, ib + 1, sC) : nullptr;
-    face(DR(), eA, eB, eC, eD, rco_ptr(a, ib), rco_ptr(a, ib + 1), bgf, cB, sB, cC, sC, Fb, oA,
-         oB, oC, oD);
+    face_vjp<DR::value, GAS, G75>(X.gc, eA, eB, eC, eD, rco_ptr(a, ib), rco_ptr(a, ib + 1), bgf,
+                                  cB, sB, cC, sC, Fb, oA, oB, oC, oD);
   };
 
-  // z ring of the thread's column (cells kf-1 .. kf+2 of the face kf+1/2) and the z
-  // contributions of cells k-1, k, k+1 (relative to the face being processed)
-  double za[NG], zb[NG], zc[NG], hold[NG];
-  double ra[NG], rb_[NG], rc[NG], rd[NG];
-  const int jw = jwrap(jg);
-#pragma unroll
-  for (int f = 0; f < NG; ++f) { za[f] = 0.0; zb[f] = 0.0; zc[f] = 0.0; hold[f] = 0.0; }
   double stb = 0.0;  // Stokes-number partial (dust)
-
-  auto z_face = [&](int kf, double* oA, double* oB, double* oC, double* oD) {
-    double Fb[NG];
-#pragma unroll
-    for (int f = 0; f < NG; ++f) {
-      Fb[f] = Az * (wc(f, kf + 1, igc, jw) - wc(f, kf, igc, jw));
-      oA[f] = 0.0; oB[f] = 0.0; oC[f] = 0.0; oD[f] = 0.0;
-    }
-    double sB = 1.0, sC = 1.0;
-    const double* cB = GAS ? centre_ptr(a, kf, igc, sB) : nullptr;
-    const double* cC = GAS ? centre_ptr(a, kf + 1, igc, sC) : nullptr;
-    const double* bgf = a.t.bgz + ((size_t)(kf + 1) * g.nr + igc) * 5;
-    face(DZ(), ra, rb_, rc, rd, nullptr, nullptr, bgf, cB, sB, cC, sC, Fb, oA, oB, oC, oD);
-  };
-  auto z_real = [&](int kf) { return !twod && kf >= -1 && kf <= g.nz - 1; };
-  auto ring_load = [&](double* dst, int k) {
-#pragma unroll
-    for (int f = 0; f < NG; ++f) dst[f] = fetch<false>(a, E, F0 + f, k, ig, jw);
-  };
-  auto ring_shift = [&](int knew) {
-#pragma unroll
-    for (int f = 0; f < NG; ++f) { ra[f] = rb_[f]; rb_[f] = rc[f]; rc[f] = rd[f]; }
-    ring_load(rd, knew);
-  };
-  auto finalize = [&](int k, const double* zz) {
-    if (!act) return;
-    const size_t cell = ((size_t)k * g.nr + ig) * g.nth + jg;
-#pragma unroll
-    for (int f = 0; f < NG; ++f) {
-      const size_t o = (size_t)(F0 + f) * N + cell;
-      double v = hold[f] + zz[f];
-      if (A.base1) v += A.base1[o];
-      if (A.base2) v += A.base2[o];
-      A.out[o] = v;
-    }
-  };
-
-  // faces k0-3/2 and k0-1/2 (their contributions to cells k0, k0+1)
-  if (!twod) {
-    ring_load(ra, k0 - 3); ring_load(rb_, k0 - 2); ring_load(rc, k0 - 1); ring_load(rd, k0);
-    double oA[NG], oB[NG], oC[NG], oD[NG];
-    if (act && z_real(k0 - 2)) {
-      z_face(k0 - 2, oA, oB, oC, oD);
-#pragma unroll
-      for (int f = 0; f < NG; ++f) zb[f] += oD[f];
-    }
-    ring_shift(k0 + 1);
-    if (act && z_real(k0 - 1)) {
-      z_face(k0 - 1, oA, oB, oC, oD);
-#pragma unroll
-      for (int f = 0; f < NG; ++f) { zb[f] += oC[f]; zc[f] += oD[f]; }
-    }
-    ring_shift(k0 + 2);
-  }
-
   for (int k = k0; k < k1; ++k) {
     // ---- stage the plane with a three-cell halo; clear the tile accumulators
     for (int h = tid; h < (TI + 2 * H) * (TJ + 2 * H); h += NT) {
       const int rr = h / (TJ + 2 * H), cc = h % (TJ + 2 * H);
       const int ii = i0 + rr - H;
-      const int jj = jwrap(j0 + cc - H);
+      const int jj = X.jwrap(j0 + cc - H);
 #pragma unroll
       for (int f = 0; f < NG; ++f) s_e[f][rr][cc] = fetch<false>(a, E, F0 + f, k, ii, jj);
     }
@@ -621,128 +619,102 @@ __global__ void __launch_bounds__(NT) k_adj(AdjArgs A, int species) {
       }
       __syncthreads();
     }
-    // ---- in-plane total of the thread's cell, plus the reverse of its sources
+    // ---- in-plane total of the thread's cell, the reverse of its sources, the bases
+    if (!act) continue;
     double cur[NG];
 #pragma unroll
     for (int f = 0; f < NG; ++f) cur[f] = s_at[f][ti][tj] + s_ar[f][ti][tj];
-    if (act) {
-      const size_t cell = ((size_t)k * g.nr + ig) * g.nth + jg;
-      const double gr = a.t.grav[((size_t)k * g.nr + ig) * 2 + 0];
-      const double gz = a.t.grav[((size_t)k * g.nr + ig) * 2 + 1];
-      const double* bgc = a.t.bgc + ((size_t)k * g.nr + ig) * 5;
-      double q[5], sg[5];
+    const size_t cell = ((size_t)k * g.nr + ig) * g.nth + jg;
+    const double gr = a.t.grav[((size_t)k * g.nr + ig) * 2 + 0];
+    const double gz = a.t.grav[((size_t)k * g.nr + ig) * 2 + 1];
+    const double* bgc = a.t.bgc + ((size_t)k * g.nr + ig) * 5;
+    double q[5], sg[5];
 #pragma unroll
-      for (int f = 0; f < 5; ++f) {
-        q[f] = bgc[f] + E[(size_t)f * N + cell];
-        sg[f] = cw * cot[(size_t)f * N + cell];
-      }
-      const double ir = 1.0 / q[4];
-      const double U[3] = {q[0] * ir, q[1] * ir, q[2] * ir};
-      if constexpr (GAS) {
-        const double gm1 = gc.gm1;
-        const double u = U[0], v = U[1], w = U[2];
-        // S_r = (m_th v + p)/r + rho g_r, S_th = -m_r v / r, S_z = rho g_z,
-        // S_E = m_r g_r + m_z g_z
-        cur[0] += sg[0] * (-gm1 * u * invrc) + sg[1] * (-v * invrc) + sg[3] * gr;
-        cur[1] += sg[0] * ((2.0 - gm1) * v * invrc) + sg[1] * (-u * invrc);
-        cur[2] += sg[0] * (-gm1 * w * invrc) + sg[3] * gz;
-        cur[3] += sg[0] * gm1 * invrc;
-        cur[4] += sg[0] * ((-v * v + 0.5 * gm1 * (u * u + v * v + w * w)) * invrc + gr) +
-                  sg[1] * (u * v * invrc) + sg[2] * gz;
-        // drag D_s = rho_d (v_d - v) Omega_K / St on the gas (+) and the dust (-), and
-        // v . D in the gas energy
-        double Ub[3] = {0.0, 0.0, 0.0}, Dt[3] = {0.0, 0.0, 0.0};
+    for (int f = 0; f < 5; ++f) {
+      q[f] = bgc[f] + E[(size_t)f * N + cell];
+      sg[f] = cw * cot[(size_t)f * N + cell];
+    }
+    const double ir = 1.0 / q[4];
+    const double U[3] = {q[0] * ir, q[1] * ir, q[2] * ir};
+    if constexpr (GAS) {
+      const double gm1 = X.gc.gm1;
+      const double u = U[0], v = U[1], w = U[2];
+      // S_r = (m_th v + p)/r + rho g_r, S_th = -m_r v / r, S_z = rho g_z,
+      // S_E = m_r g_r + m_z g_z
+      cur[0] += sg[0] * (-gm1 * u * invrc) + sg[1] * (-v * invrc) + sg[3] * gr;
+      cur[1] += sg[0] * ((2.0 - gm1) * v * invrc) + sg[1] * (-u * invrc);
+      cur[2] += sg[0] * (-gm1 * w * invrc) + sg[3] * gz;
+      cur[3] += sg[0] * gm1 * invrc;
+      cur[4] += sg[0] * ((-v * v + 0.5 * gm1 * (u * u + v * v + w * w)) * invrc + gr) +
+                sg[1] * (u * v * invrc) + sg[2] * gz;
+      // drag D_s = rho_d (v_d - v) Omega_K / St on the gas (+) and the dust (-), and
+      // v . D in the gas energy
+      double Ub[3] = {0.0, 0.0, 0.0}, Dt[3] = {0.0, 0.0, 0.0};
 #pragma unroll
-        for (int s = 0; s < ND; ++s) {
-          const int o = 5 + 4 * s;
-          const double rdn = E[(size_t)(o + 3) * N + cell];
-          double vd[3] = {0.0, 0.0, 0.0};
-          if (rdn > 0.0) {
-            const double id = 1.0 / rdn;
-#pragma unroll
-            for (int c2 = 0; c2 < 3; ++c2) vd[c2] = E[(size_t)(o + c2) * N + cell] * id;
-          }
-          const double its = omk * g.inv_st[s];
-#pragma unroll
-          for (int c2 = 0; c2 < 3; ++c2) {
-            Dt[c2] += rdn * (vd[c2] - U[c2]) * its;
-            const double Db = sg[c2] + sg[3] * U[c2] - cw * cot[(size_t)(o + c2) * N + cell];
-            Ub[c2] -= its * rdn * Db;
-          }
-        }
-        double dot = 0.0;
-#pragma unroll
-        for (int c2 = 0; c2 < 3; ++c2) {
-          Ub[c2] += sg[3] * Dt[c2];
-          cur[c2] += Ub[c2] * ir;
-          dot += Ub[c2] * U[c2];
-        }
-        cur[4] -= dot * ir;
-      } else {
-        const double m[3] = {E[(size_t)F0 * N + cell], E[(size_t)(F0 + 1) * N + cell],
-                             E[(size_t)(F0 + 2) * N + cell]};
-        const double rdn = E[(size_t)(F0 + 3) * N + cell];
-        double sd[4];
-#pragma unroll
-        for (int f = 0; f < 4; ++f) sd[f] = cw * cot[(size_t)(F0 + f) * N + cell];
+      for (int s = 0; s < ND; ++s) {
+        const int o = 5 + 4 * s;
+        const double rdn = E[(size_t)(o + 3) * N + cell];
         double vd[3] = {0.0, 0.0, 0.0};
         if (rdn > 0.0) {
           const double id = 1.0 / rdn;
-          vd[0] = m[0] * id; vd[1] = m[1] * id; vd[2] = m[2] * id;
-          // S_r = m_th v_d / r + rho_d g_r, S_th = -m_r v_d / r
-          cur[1] += sd[0] * 2.0 * vd[1] * invrc - sd[1] * vd[0] * invrc;
-          cur[0] += -sd[1] * vd[1] * invrc;
-          cur[3] += sd[0] * (-vd[1] * vd[1] * invrc) + sd[1] * (vd[0] * vd[1] * invrc);
+#pragma unroll
+          for (int c2 = 0; c2 < 3; ++c2) vd[c2] = E[(size_t)(o + c2) * N + cell] * id;
         }
-        cur[3] += sd[0] * gr + sd[2] * gz;
-        const double its = omk * g.inv_st[species];
-        const double st = 1.0 / g.inv_st[species];
-        double dotU = 0.0, dotD = 0.0;
+        const double its = omk * g.inv_st[s];
 #pragma unroll
         for (int c2 = 0; c2 < 3; ++c2) {
-          const double Ds = rdn * (vd[c2] - U[c2]) * its;
-          const double Db = sg[c2] + sg[3] * U[c2] - sd[c2];
-          if (rdn > 0.0) cur[c2] += its * Db;
-          dotU += Db * U[c2];
-          dotD += Db * Ds;
-        }
-        cur[3] -= its * dotU;
-        stb -= dotD / st;
-      }
-    }
-    // ---- z face k+1/2: completes cell k-1
-    if (!twod) {
-      double zd[NG];
-#pragma unroll
-      for (int f = 0; f < NG; ++f) zd[f] = 0.0;
-      if (act && z_real(k)) {
-        z_face(k, oA, oB, oC, oD);
-#pragma unroll
-        for (int f = 0; f < NG; ++f) {
-          za[f] += oA[f]; zb[f] += oB[f]; zc[f] += oC[f]; zd[f] = oD[f];
+          Dt[c2] += rdn * (vd[c2] - U[c2]) * its;
+          const double Db = sg[c2] + sg[3] * U[c2] - cw * cot[(size_t)(o + c2) * N + cell];
+          Ub[c2] -= its * rdn * Db;
         }
       }
-      if (k - 1 >= k0) finalize(k - 1, za);
+      double dot = 0.0;
 #pragma unroll
-      for (int f = 0; f < NG; ++f) {
-        za[f] = zb[f]; zb[f] = zc[f]; zc[f] = zd[f]; hold[f] = cur[f];
+      for (int c2 = 0; c2 < 3; ++c2) {
+        Ub[c2] += sg[3] * Dt[c2];
+        cur[c2] += Ub[c2] * ir;
+        dot += Ub[c2] * U[c2];
       }
-      ring_shift(k + 3);
+      cur[4] -= dot * ir;
     } else {
+      const double m[3] = {E[(size_t)F0 * N + cell], E[(size_t)(F0 + 1) * N + cell],
+                           E[(size_t)(F0 + 2) * N + cell]};
+      const double rdn = E[(size_t)(F0 + 3) * N + cell];
+      double sd[4];
 #pragma unroll
-      for (int f = 0; f < NG; ++f) hold[f] = cur[f];
-      finalize(k, za);
-    }
-  }
-  // ---- last face k1+1/2 completes cell k1-1
-  if (!twod && k1 > k0) {
-    double oA[NG], oB[NG], oC[NG], oD[NG];
-    if (act && z_real(k1)) {
-      z_face(k1, oA, oB, oC, oD);
+      for (int f = 0; f < 4; ++f) sd[f] = cw * cot[(size_t)(F0 + f) * N + cell];
+      double vd[3] = {0.0, 0.0, 0.0};
+      if (rdn > 0.0) {
+        const double id = 1.0 / rdn;
+        vd[0] = m[0] * id; vd[1] = m[1] * id; vd[2] = m[2] * id;
+        // S_r = m_th v_d / r + rho_d g_r, S_th = -m_r v_d / r
+        cur[1] += sd[0] * 2.0 * vd[1] * invrc - sd[1] * vd[0] * invrc;
+        cur[0] += -sd[1] * vd[1] * invrc;
+        cur[3] += sd[0] * (-vd[1] * vd[1] * invrc) + sd[1] * (vd[0] * vd[1] * invrc);
+      }
+      cur[3] += sd[0] * gr + sd[2] * gz;
+      const double its = omk * g.inv_st[species];
+      const double st = 1.0 / g.inv_st[species];
+      double dotU = 0.0, dotD = 0.0;
 #pragma unroll
-      for (int f = 0; f < NG; ++f) za[f] += oA[f];
+      for (int c2 = 0; c2 < 3; ++c2) {
+        const double Ds = rdn * (vd[c2] - U[c2]) * its;
+        const double Db = sg[c2] + sg[3] * U[c2] - sd[c2];
+        if (rdn > 0.0) cur[c2] += its * Db;
+        dotU += Db * U[c2];
+        dotD += Db * Ds;
+      }
+      cur[3] -= its * dotU;
+      stb -= dotD / st;
     }
-    finalize(k1 - 1, za);
+#pragma unroll
+    for (int f = 0; f < NG; ++f) {
+      const size_t o = (size_t)(F0 + f) * N + cell;
+      double v = cur[f];
+      if (A.base1) v += A.base1[o];
+      if (A.base2) v += A.base2[o];
+      A.out[o] = v;
+    }
   }
   // ---- Stokes-number partial of the block (dust)
   if constexpr (!GAS) {
@@ -754,6 +726,86 @@ __global__ void __launch_bounds__(NT) k_adj(AdjArgs A, int species) {
       for (int w = 0; w < NT / 64; ++w) acc += s_red[w];
       A.stpart[blockIdx.x] = acc;
     }
+  }
+}
+
+// z faces: one thread per column and chunk of planes, marching up; adds the four stencil
+// contributions of every z face to the output written by k_adj_plane (each cell
+// completed in order: its faces k-3/2 .. k+3/2, lower first).
+template <bool GAS, int ND, bool G75>
+__global__ void __launch_bounds__(256) k_adj_z(AdjArgs A, int species, int tkz) {
+  using C = AdjCtx<GAS>;
+  constexpr int NG = C::NG;
+  const C X(A, species);
+  const StageArgs& a = X.a;
+  const Geo& g = X.g;
+  const int F0 = X.F0;
+  const size_t ncol = (size_t)g.nr * g.nth;
+  const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const size_t col = t % ncol;
+  const int kc = (int)(t / ncol);
+  const int k0 = kc * tkz;
+  if (k0 >= g.nz) return;
+  const int k1 = min(g.nz, k0 + tkz);
+  const int ig = (int)(col / g.nth), jg = (int)(col % g.nth);
+  const double* E = (const double*)a.in;
+  const double Az = a.t.rt[(size_t)ig * RT_N + RT_AZ];
+
+  double ra[NG], rb[NG], rc[NG], rd[NG];  // cells kf-1 .. kf+2 of the face kf+1/2
+  auto load = [&](double* dst, int k) {
+#pragma unroll
+    for (int f = 0; f < NG; ++f) dst[f] = fetch<false>(a, E, F0 + f, k, ig, jg);
+  };
+  // adds the face's contributions into oA..oD
+  auto zface = [&](int kf, double* oA, double* oB, double* oC, double* oD) {
+    double Fb[NG];
+#pragma unroll
+    for (int f = 0; f < NG; ++f) Fb[f] = Az * (X.wc(f, kf + 1, ig, jg) - X.wc(f, kf, ig, jg));
+    double sB = 1.0, sC = 1.0;
+    const double* cB = GAS ? centre_ptr(a, kf, ig, sB) : nullptr;
+    const double* cC = GAS ? centre_ptr(a, kf + 1, ig, sC) : nullptr;
+    const double* bgf = a.t.bgz + ((size_t)(kf + 1) * g.nr + ig) * 5;
+    face_vjp<2, GAS, G75>(X.gc, ra, rb, rc, rd, nullptr, nullptr, bgf, cB, sB, cC, sC, Fb, oA, oB,
+                          oC, oD);
+  };
+  auto real = [&](int kf) { return kf >= -1 && kf <= g.nz - 1; };
+  auto add_out = [&](int k, const double* v) {
+    const size_t cell = ((size_t)k * g.nr + ig) * g.nth + jg;
+#pragma unroll
+    for (int f = 0; f < NG; ++f) A.out[(size_t)(F0 + f) * g.N + cell] += v[f];
+  };
+
+  // contributions of the faces below cell k to cells k (zb) and k+1 (zc); za = cell k-1
+  // za, zb, zc, zd: cells k-1, k, k+1, k+2 of the face k+1/2 being processed; the
+  // contributions to cells below k0 (faces k0-3/2, k0-1/2) land in scratch accumulators
+  double za[NG], zb[NG], zc[NG], zd[NG];
+#pragma unroll
+  for (int f = 0; f < NG; ++f) { za[f] = 0.0; zb[f] = 0.0; zc[f] = 0.0; zd[f] = 0.0; }
+  load(ra, k0 - 3); load(rb, k0 - 2); load(rc, k0 - 1); load(rd, k0);
+  // face k0-3/2: cells k0-3 .. k0 -> (za, za, za, zb); only its last one is kept
+  if (real(k0 - 2)) {
+    zface(k0 - 2, zd, zd, zc, zb);
+#pragma unroll
+    for (int f = 0; f < NG; ++f) { zc[f] = 0.0; zd[f] = 0.0; }
+  }
+#pragma unroll
+  for (int f = 0; f < NG; ++f) { ra[f] = rb[f]; rb[f] = rc[f]; rc[f] = rd[f]; }
+  load(rd, k0 + 1);
+  // face k0-1/2: cells k0-2 .. k0+1 -> (-, -, zb, zc)
+  if (real(k0 - 1)) {
+    zface(k0 - 1, zd, za, zb, zc);
+#pragma unroll
+    for (int f = 0; f < NG; ++f) { za[f] = 0.0; zd[f] = 0.0; }
+  }
+  for (int k = k0; k <= k1; ++k) {
+#pragma unroll
+    for (int f = 0; f < NG; ++f) { ra[f] = rb[f]; rb[f] = rc[f]; rc[f] = rd[f]; }
+    load(rd, k + 2);
+    // face k+1/2 (cells k-1, k, k+1, k+2)
+    if (real(k)) zface(k, za, zb, zc, zd);
+    if (k - 1 >= k0) add_out(k - 1, za);
+#pragma unroll
+    for (int f = 0; f < NG; ++f) { za[f] = zb[f]; zb[f] = zc[f]; zc[f] = zd[f]; zd[f] = 0.0; }
   }
 }
 
@@ -772,25 +824,40 @@ __global__ void __launch_bounds__(256) k_st_accum(const double* parts, int n, do
 // launchers
 
 template <int ND>
-static void adj_nd(const AdjArgs& a, int blocks, int group, hipStream_t s) {
+static void adj_nd(const AdjArgs& a, int blocks, int zblocks, int tkz, int group, hipStream_t s) {
   if (group == 0) {
-    if (a.s.g.gamma == 1.4)
-      hipLaunchKernelGGL((k_adj<true, ND, true>), dim3(blocks), dim3(NT), 0, s, a, 0);
-    else
-      hipLaunchKernelGGL((k_adj<true, ND, false>), dim3(blocks), dim3(NT), 0, s, a, 0);
+    if (a.s.g.gamma == 1.4) {
+      hipLaunchKernelGGL((k_adj_plane<true, ND, true>), dim3(blocks), dim3(NT), 0, s, a, 0);
+      if (!a.s.g.twod)
+        hipLaunchKernelGGL((k_adj_z<true, ND, true>), dim3(zblocks), dim3(256), 0, s, a, 0, tkz);
+    } else {
+      hipLaunchKernelGGL((k_adj_plane<true, ND, false>), dim3(blocks), dim3(NT), 0, s, a, 0);
+      if (!a.s.g.twod)
+        hipLaunchKernelGGL((k_adj_z<true, ND, false>), dim3(zblocks), dim3(256), 0, s, a, 0, tkz);
+    }
   } else {
-    if constexpr (ND > 0)
-      hipLaunchKernelGGL((k_adj<false, ND, true>), dim3(blocks), dim3(NT), 0, s, a, group - 1);
+    if constexpr (ND > 0) {
+      hipLaunchKernelGGL((k_adj_plane<false, ND, true>), dim3(blocks), dim3(NT), 0, s, a, group - 1);
+      if (!a.s.g.twod)
+        hipLaunchKernelGGL((k_adj_z<false, ND, true>), dim3(zblocks), dim3(256), 0, s, a, group - 1,
+                           tkz);
+    }
   }
 }
 
 hipError_t launch_adj_group(const AdjArgs& a, int blocks, int group, hipStream_t s) {
+  // z kernel: whole columns when they alone give 2048 wavefronts (8 per SIMD), else
+  // chunks of 8 planes (each chunk re-solves the 3 faces below its first plane)
+  const size_t ncol = (size_t)a.s.g.nr * a.s.g.nth;
+  const int tkz = ncol / 64 >= 2048 ? a.s.g.nz : std::min(8, a.s.g.nz);
+  const size_t nthreads = ncol * (size_t)((a.s.g.nz + tkz - 1) / tkz);
+  const int zblocks = (int)((nthreads + 255) / 256);
   switch (a.s.g.nd) {
-    case 0: adj_nd<0>(a, blocks, group, s); break;
-    case 1: adj_nd<1>(a, blocks, group, s); break;
-    case 2: adj_nd<2>(a, blocks, group, s); break;
-    case 3: adj_nd<3>(a, blocks, group, s); break;
-    default: adj_nd<4>(a, blocks, group, s); break;
+    case 0: adj_nd<0>(a, blocks, zblocks, tkz, group, s); break;
+    case 1: adj_nd<1>(a, blocks, zblocks, tkz, group, s); break;
+    case 2: adj_nd<2>(a, blocks, zblocks, tkz, group, s); break;
+    case 3: adj_nd<3>(a, blocks, zblocks, tkz, group, s); break;
+    default: adj_nd<4>(a, blocks, zblocks, tkz, group, s); break;
   }
   return hipGetLastError();
 }

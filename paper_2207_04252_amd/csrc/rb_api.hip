@@ -575,21 +575,10 @@ struct AdjLayout {
 AdjLayout adj_layout(const rb_ctx* x, int n, int k) {
   AdjLayout A;
   const Layout& L = x->L;
-  // z chunking: one block per CU suffices (LDS and registers hold one per CU); long
-  // chunks keep the three extra z faces per chunk cheap
-  const int tiles = L.ntj * L.nti;
-  int tk = x->g.nz;
-  if (x->g.nz > 1) {
-    const int cand[5] = {32, 16, 8, 4, 2};
-    tk = 2;
-    for (int q = 0; q < 5; ++q) {
-      if ((size_t)tiles * ((x->g.nz + cand[q] - 1) / cand[q]) >= 256) { tk = cand[q]; break; }
-    }
-    tk = std::min(tk, x->g.nz);
-  }
-  A.tk = tk;
-  A.nkc = (x->g.nz + tk - 1) / tk;
-  A.nblocks = tiles * A.nkc;
+  // the in-plane adjoint kernel uses the forward stage kernel's tiles and z chunks
+  A.tk = L.tk;
+  A.nkc = L.nkc;
+  A.nblocks = L.nblocks;
   A.S = (size_t)x->g.nf * x->g.N;
   A.nseg = (n + k - 1) / k;
   size_t o = 0;

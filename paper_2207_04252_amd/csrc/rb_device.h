@@ -78,7 +78,7 @@ __device__ __forceinline__ double frcp(double x) {
 }
 
 struct GasC {
-  double g, gm1, inv_gm1, g2m1, gm1_2g, gp1_2g, kshock, a2, half_gm1;
+  double g, gm1, inv_gm1, g2m1, gm1_2g, gp1_2g, kshock, a2, half_gm1, inv_g, inv_gp1_2g;
 };
 
 __device__ __forceinline__ GasC gas_consts(double g) {
@@ -92,6 +92,8 @@ __device__ __forceinline__ GasC gas_consts(double g) {
   c.kshock = (g - 1.0) / (g + 1.0);
   c.a2 = 2.0 / (g + 1.0);
   c.half_gm1 = 0.5 * (g - 1.0);
+  c.inv_g = 1.0 / g;
+  c.inv_gp1_2g = (2.0 * g) / (g + 1.0);
   return c;
 }
 
@@ -190,9 +192,61 @@ template <bool G75, bool REC = false>
 __device__ void gas_riemann(const GasC& c, double rL, double irL, double uL, double aL, double bL,
                             double pL, double rR, double irR, double uR, double aR, double bR,
                             double pR, double fl[5], TStat& st, GasRec* rec = nullptr) {
-  const double cL = sqrt(c.g * pL * irL);
-  const double cR = sqrt(c.g * pR * irR);
   const double du = uR - uL;
+  const double c2L = c.g * pL * irL, c2R = c.g * pR * irR;
+  // Supersonic faces.  With u_L >= c_L, let p_hi be the star pressure at which a left
+  // shock would stand still, p_hi = (rho_L u_L^2 / g - (g-1)/(2g) p_L) (2g)/(g+1).  If
+  // p_hi >= p_R then f_R(p_hi) >= 0, and f_L(p_hi) + du >= 0 gives f(p_hi) >= 0, so
+  // p* <= p_hi (f increases): the left wave (rarefaction with head u_L - c_L >= 0, or shock
+  // with speed >= 0) lies at x/t >= 0, and u* = u_L - f_L(p*) >= u_L - f_L(p_hi) >= 0: the
+  // solution at x/t = 0 is the left state, which is what the full solve returns.  Both
+  // tests are taken on squares (f_L(p_hi)^2 = (p_hi - p_L)^2 A_L / (p_hi + B_L)), so no
+  // square root or division is needed; faces that may open a vacuum are left to the full
+  // solve.  Mirror for u_R <= -c_R.
+  {
+    const double g2 = c.g2m1 * c.g2m1;
+    const bool novac_L = du <= 0.0 || du * du < g2 * c2L;
+    const bool novac_R = du <= 0.0 || du * du < g2 * c2R;
+    if (uL > 0.0 && uL * uL >= c2L && novac_L) {
+      const double u2 = uL * uL;
+      const double phi = (rL * u2 * c.inv_g - c.gm1_2g * pL) * c.inv_gp1_2g;
+      if (phi >= pR) {
+        const double D = phi - pL;
+        const double D2A = D * D * (c.a2 * irL);
+        const double pb = phi + c.kshock * pL;
+        if ((du >= 0.0 || D2A >= du * du * pb) && u2 * pb >= D2A) {
+          if constexpr (REC) {
+            rec->branch = GR_LEFT;
+            rec->rho = rL; rec->un = uL; rec->t1 = aL; rec->t2 = bL; rec->p = pL;
+          }
+          const double m0 = rL * uL;
+          const double en = pL * c.inv_gm1 + 0.5 * rL * (uL * uL + aL * aL + bL * bL);
+          fl[0] = m0; fl[1] = m0 * uL + pL; fl[2] = m0 * aL; fl[3] = m0 * bL; fl[4] = (en + pL) * uL;
+          return;
+        }
+      }
+    } else if (uR < 0.0 && uR * uR >= c2R && novac_R) {
+      const double u2 = uR * uR;
+      const double phi = (rR * u2 * c.inv_g - c.gm1_2g * pR) * c.inv_gp1_2g;
+      if (phi >= pL) {
+        const double D = phi - pR;
+        const double D2A = D * D * (c.a2 * irR);
+        const double pb = phi + c.kshock * pR;
+        if ((du >= 0.0 || D2A >= du * du * pb) && u2 * pb >= D2A) {
+          if constexpr (REC) {
+            rec->branch = GR_RIGHT;
+            rec->rho = rR; rec->un = uR; rec->t1 = aR; rec->t2 = bR; rec->p = pR;
+          }
+          const double m0 = rR * uR;
+          const double en = pR * c.inv_gm1 + 0.5 * rR * (uR * uR + aR * aR + bR * bR);
+          fl[0] = m0; fl[1] = m0 * uR + pR; fl[2] = m0 * aR; fl[3] = m0 * bR; fl[4] = (en + pR) * uR;
+          return;
+        }
+      }
+    }
+  }
+  const double cL = sqrt(c2L);
+  const double cR = sqrt(c2R);
   double rho, un, t1, t2, p;
   if (c.g2m1 * (cL + cR) <= du) {
     // vacuum between two rarefactions
@@ -216,44 +270,6 @@ __device__ void gas_riemann(const GasC& c, double rL, double irL, double uL, dou
   } else {
     const Side L = make_side(rL, irL, uL, pL, cL, c);
     const Side R = make_side(rR, irR, uR, pR, cR, c);
-    // Supersonic faces: with u_L >= c_L, let p_hi be the star pressure at which a left
-    // shock would stand still.  If f(p_hi) >= 0 then p* <= p_hi (f increases), so the
-    // left wave (rarefaction with head u_L - c_L >= 0, or shock with speed >= 0) lies
-    // at x/t >= 0, and u* = u_L - f_L(p*) >= u_L - f_L(p_hi) >= 0: the solution at x/t = 0
-    // is the left state, which is what the full solve returns.  Mirror for u_R <= -c_R.
-    if (uL >= cL) {
-      const double m = uL / cL;
-      const double phi = pL * (m * m - c.gm1_2g) / c.gp1_2g;
-      double fL, dL, fR, dR;
-      pfun<G75>(phi, L, c, fL, dL);
-      pfun<G75>(phi, R, c, fR, dR);
-      if (fL + fR + du >= 0.0 && uL - fL >= 0.0) {
-        if constexpr (REC) {
-          rec->branch = GR_LEFT;
-          rec->rho = rL; rec->un = uL; rec->t1 = aL; rec->t2 = bL; rec->p = pL;
-        }
-        const double m0 = rL * uL;
-        const double en = pL * c.inv_gm1 + 0.5 * rL * (uL * uL + aL * aL + bL * bL);
-        fl[0] = m0; fl[1] = m0 * uL + pL; fl[2] = m0 * aL; fl[3] = m0 * bL; fl[4] = (en + pL) * uL;
-        return;
-      }
-    } else if (uR <= -cR) {
-      const double m = -uR / cR;
-      const double phi = pR * (m * m - c.gm1_2g) / c.gp1_2g;
-      double fL, dL, fR, dR;
-      pfun<G75>(phi, L, c, fL, dL);
-      pfun<G75>(phi, R, c, fR, dR);
-      if (fL + fR + du >= 0.0 && uR + fR <= 0.0) {
-        if constexpr (REC) {
-          rec->branch = GR_RIGHT;
-          rec->rho = rR; rec->un = uR; rec->t1 = aR; rec->t2 = bR; rec->p = pR;
-        }
-        const double m0 = rR * uR;
-        const double en = pR * c.inv_gm1 + 0.5 * rR * (uR * uR + aR * aR + bR * bR);
-        fl[0] = m0; fl[1] = m0 * uR + pR; fl[2] = m0 * aR; fl[3] = m0 * bR; fl[4] = (en + pR) * uR;
-        return;
-      }
-    }
     double ppv = 0.5 * (pL + pR) - 0.125 * du * (rL + rR) * (cL + cR);
     double ps = fmax(ppv, 1e-8 * fmin(pL, pR));
     int it = 0;
