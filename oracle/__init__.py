@@ -39,7 +39,7 @@ class OrConfig(ctypes.Structure):
     _fields_ = [
         ("nr", ctypes.c_int32), ("nth", ctypes.c_int32), ("nz", ctypes.c_int32),
         ("log_r", ctypes.c_int32), ("init_kind", ctypes.c_int32), ("balanced", ctypes.c_int32),
-        ("n_dust", ctypes.c_int32), ("pad0", ctypes.c_int32),
+        ("n_dust", ctypes.c_int32), ("indirect", ctypes.c_int32),
         ("r_in", ctypes.c_double), ("r_out", ctypes.c_double), ("z_half", ctypes.c_double),
         ("gamma", ctypes.c_double), ("GM", ctypes.c_double), ("cfl", ctypes.c_double),
         ("sod_r0", ctypes.c_double), ("sod_left", ctypes.c_double * 3),
@@ -71,6 +71,7 @@ def to_struct(cfg: synth.Config) -> OrConfig:
     s.log_r = int(cfg.log_r)
     s.init_kind = cfg.init_kind
     s.balanced = int(cfg.balanced)
+    s.indirect = int(getattr(cfg, "indirect", False))
     s.n_dust = cfg.n_dust
     s.r_in, s.r_out, s.z_half = cfg.r_in, cfg.r_out, cfg.z_half
     s.gamma, s.GM, s.cfl = cfg.gamma, cfg.GM, cfg.cfl
@@ -129,6 +130,8 @@ def lib() -> ctypes.CDLL:
         L.or_threads.restype = ctypes.c_int
         L.or_count_ops.restype = ctypes.c_double
         L.or_count_ops.argtypes = [ctypes.POINTER(OrConfig), _D]
+        L.or_indirect_sums.argtypes = [ctypes.c_void_p, _D, _D]
+        L.or_indirect_sums.restype = None
         L.or_tangent_state.restype = ctypes.c_int
         L.or_tangent_state.argtypes = [ctypes.POINTER(OrConfig), _D, _D, _D, ctypes.c_int, _D, _D, _D]
         _lib = L
@@ -233,6 +236,12 @@ class Oracle:
         d = OrDiag()
         lib().or_diag(self.h, ctypes.byref(d))
         return d
+
+    def indirect_sums(self):
+        """(A, B) of the indirect gravity for the current state."""
+        A = ctypes.c_double(); B = ctypes.c_double()
+        lib().or_indirect_sums(self.h, ctypes.byref(A), ctypes.byref(B))
+        return A.value, B.value
 
     def core_dust_mass(self) -> float:
         return lib().or_core_dust_mass(self.h, synth.CORE_R[0], synth.CORE_R[1], synth.CORE_DTH)

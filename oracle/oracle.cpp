@@ -50,7 +50,7 @@
 extern "C" {
 
 typedef struct {
-  int32_t nr, nth, nz, log_r, init_kind, balanced, n_dust, pad0;
+  int32_t nr, nth, nz, log_r, init_kind, balanced, n_dust, indirect;
   double r_in, r_out, z_half, gamma, GM, cfl;
   double sod_r0, sod_left[3], sod_right[3];
   double h0, beta_T, rho_mid0, beta_rho;
@@ -624,6 +624,8 @@ struct Sim {
   }
 
   const T* cur = nullptr; /* state whose operator is being evaluated */
+  bool in_empty_run = false;
+  double last_A = 0.0, last_B = 0.0; /* indirect-gravity sums of the last evaluation */
 
   /* gas conservative -> primitive in the frame of direction d (0 r, 1 theta, 2 z) */
   Prim<T> to_prim_gas(const T* q, int d) const {
@@ -785,6 +787,32 @@ struct Sim {
     if (nvac) flags |= F_VAC;
     if (noconv) flags |= F_NOCONV;
 
+    /* indirect gravity (Sect. 2.10): the star is accelerated by the disc,
+     * a_star = G sum_cells m r_vec / |r_vec|^3 (gas and dust mass), and the frame centred on
+     * the star adds -a_star to every fluid element; with A = sum m r cos(theta)/|r|^3 and
+     * B = sum m r sin(theta)/|r|^3 its cylindrical components are
+     * -G (A cos(theta) + B sin(theta), -A sin(theta) + B cos(theta), 0).  G = GM (unit star
+     * mass).  Not part of the empty run: the stationary flow is axisymmetric. */
+    T Aind = 0.0, Bind = 0.0;
+    const bool ind = c.indirect != 0 && !in_empty_run;
+    if (ind) {
+      for (int k = 0; k < nz; ++k)
+        for (int i = 0; i < nr; ++i) {
+          double r = rce(i), z = zc[k];
+          double wgt = V[i] * r / std::pow(r * r + z * z, 1.5);
+          for (int j = 0; j < nth; ++j) {
+            size_t id = idx(k, i, j);
+            double th = (j + 0.5) * dth;
+            T m = U[4 * N + id];
+            for (int s = 0; s < nd && with_dust; ++s) m = m + U[(5 + 4 * s + 3) * N + id];
+            Aind = Aind + m * (wgt * std::cos(th));
+            Bind = Bind + m * (wgt * std::sin(th));
+          }
+        }
+      last_A = val(Aind);
+      last_B = val(Bind);
+    }
+
     /* divergence and sources per cell */
     const double g = c.gamma;
 #pragma omp parallel for collapse(2) schedule(static)
@@ -845,6 +873,21 @@ struct Sim {
             S[2] = S[2] + dragz;
             S[3] = S[3] + (u * dragx + v * dragy + w * dragz);
           }
+          if (ind) {
+            double th = (j + 0.5) * dth;
+            double cs = std::cos(th), sn = std::sin(th);
+            T ar = -c.GM * (Aind * cs + Bind * sn);
+            T at = -c.GM * (Bind * cs - Aind * sn);
+            S[0] = S[0] + rho * ar;
+            S[1] = S[1] + rho * at;
+            S[3] = S[3] + rho * (u * ar + v * at);
+            for (int s = 0; s < nd && with_dust; ++s) {
+              int o = 5 + 4 * s;
+              T rd = U[(o + 3) * N + id];
+              S[o + 0] = S[o + 0] + rd * ar;
+              S[o + 1] = S[o + 1] + rd * at;
+            }
+          }
           for (int f = 0; f < nfl; ++f) {
             T gv = Gc[f] + S[f] * V[i];
             if (subtract_R0 && f < 5) gv = gv - R0[((size_t)k * nr + i) * 5 + f];
@@ -864,7 +907,9 @@ struct Sim {
             U[f * N + idx(k, i, j)] = bg_c[((size_t)k * nr + i) * nf + f];
     std::vector<T> G(nf * N, T(0.0));
     int sf = flags;
+    in_empty_run = true;
     evaluate(U, false, false, G);
+    in_empty_run = false;
     flags = sf;
     for (int k = 0; k < nz; ++k)
       for (int i = 0; i < nr; ++i)
@@ -1142,6 +1187,17 @@ void or_diag(void* h, OrDiag* d) {
   s->masses(d->mass);
   for (int q = 0; q < 5; ++q) d->outflow[q] = s->outflow[q];
   d->dt_last = s->dt_last;
+}
+
+/* indirect-gravity sums A, B of the current state (evaluates the operator once) */
+void or_indirect_sums(void* h, double* A, double* B) {
+  Sim<double>* s = (Sim<double>*)h;
+  std::vector<double> G((size_t)s->nf * s->N);
+  int sf = s->flags;
+  s->evaluate(s->E, s->nd > 0, s->c.balanced != 0, G);
+  s->flags = sf;
+  *A = s->last_A;
+  *B = s->last_B;
 }
 
 double or_core_dust_mass(void* h, double r_lo, double r_hi, double dcore) {

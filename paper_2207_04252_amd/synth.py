@@ -63,6 +63,7 @@ class Config:
     eps_dust: Tuple[float, ...] = ()
     hd_over_h: Tuple[float, ...] = ()
     steps: int = 100
+    indirect: bool = False      # indirect gravity of the star's displacement (Sect. 2.10)
 
     @property
     def n_dust(self) -> int:
