@@ -83,6 +83,11 @@ typedef struct {
   double vortex_amp, vortex_r0, vortex_th0, vortex_sig_r, vortex_sig_a, noise_amp;
   /* dust: Stokes number (t_s = St / Omega_K), dust-to-gas column ratio, H_d / H       */
   double stokes[4], eps_dust[4], hd_over_h[4];
+  /* 1: indirect gravity (Sect. 2.10) -- every fluid element feels minus the star's
+   * acceleration by the disc, G sum m r_vec/|r_vec|^3 over gas and dust (G = GM, unit star
+   * mass); recomputed from each stage's input.  Disc only; not with rb_record.          */
+  int32_t indirect;
+  int32_t reserved;
 } rb_config;
 
 /* Caller-owned device buffers.  Sizes come from rb_query_sizes; pointers must be

@@ -59,6 +59,7 @@ bool validate(const rb_config* c, std::string* why) {
   if (c->init_kind == RB_INIT_DISC && !(c->GM > 0.0)) return bad("disc needs GM > 0");
   if (c->init_kind == RB_INIT_SOD && c->n_dust > 0) return bad("Sod annulus carries no dust");
   if (c->n_dust > 0 && !(c->GM > 0.0)) return bad("dust drag needs GM > 0 (t_s = St/Omega_K)");
+  if (c->indirect && c->init_kind != RB_INIT_DISC) return bad("indirect gravity needs a disc");
   for (int s = 0; s < c->n_dust; ++s)
     if (!(c->stokes[s] > 0.0) || !(c->hd_over_h[s] > 0.0) || !(c->eps_dust[s] >= 0.0))
       return bad("dust parameters must be positive");
@@ -113,6 +114,11 @@ Layout make_layout(const rb_config& c) {
   L.ghz = take(4 * nr * nf);
   L.ghzf = take(2 * nr * 5);
   L.dsc = take(std::max<size_t>(1, (size_t)c.n_dust * nz * nr));
+  L.trig = take(2 * nth);
+  L.indw = take(nz * nr);
+  L.indab = take(2);
+  L.nind = (int)std::min<size_t>((N + 255) / 256, 1024);
+  L.indp = take((size_t)L.nind * 2);
   L.dtlog = take(DTLOG + 2);
   L.cflp = take(std::max((size_t)L.nblocks * 5, (size_t)L.ncfl));
   L.outp = take((size_t)L.nblocks * 5);
@@ -130,6 +136,7 @@ Geo make_geo(const rb_config& c) {
   g.N = (size_t)c.nr * c.ntheta * c.nz;
   g.gamma = c.gamma; g.GM = c.GM; g.cfl = c.cfl;
   g.p32 = c.precision == RB_FP32_PERT;
+  g.indirect = c.indirect != 0;
   for (int s = 0; s < 4; ++s) g.inv_st[s] = s < c.n_dust ? 1.0 / c.stokes[s] : 0.0;
   return g;
 }
@@ -144,6 +151,7 @@ StageArgs base_args(rb_ctx* x) {
   a.t.bgr = w + L.bgr; a.t.bgz = w + L.bgz; a.t.r0 = w + L.r0; a.t.grav = w + L.grav;
   a.t.ghr = w + L.ghr; a.t.ghrf = w + L.ghrf; a.t.ghz = w + L.ghz; a.t.ghzf = w + L.ghzf;
   a.t.dsc = w + L.dsc;
+  a.t.trig = w + L.trig; a.t.indw = w + L.indw; a.t.indab = w + L.indab;
   a.c.ctrl = reinterpret_cast<Ctrl*>(w + L.ctrl);
   a.c.dtlog = w + L.dtlog; a.c.cflp = w + L.cflp; a.c.outp = w + L.outp; a.c.r0w = w + L.r0;
   a.tk = L.tk; a.ntj = L.ntj; a.nti = L.nti; a.nkc = L.nkc;
@@ -223,8 +231,16 @@ void prof_collect(rb_ctx* x) {
   x->ev_used = 0;
 }
 
+// indirect-gravity sums of the stage input (before any group kernel of the stage)
+hipError_t prep_stage(rb_ctx* x, const StageArgs& a) {
+  if (!x->g.indirect || a.mode == MODE_RESID) return hipSuccess;
+  ProfScope ps(x, 2);
+  return launch_indirect(a, a.in, x->work + x->L.indp, x->L.nind, x->work + x->L.indab, x->stream);
+}
+
 hipError_t run_stage(rb_ctx* x, const StageArgs& a) {
-  hipError_t e;
+  hipError_t e = prep_stage(x, a);
+  if (e != hipSuccess) return e;
   {
     ProfScope ps(x, 0);
     e = launch_stage_group(a, x->L.nblocks, 0, x->stream);
@@ -464,6 +480,7 @@ rb_status rb_eval_operator(rb_ctx* x, double* host_out, size_t n_doubles) {
   if (n_doubles != N * x->g.nf) return fail(x, RB_EINVAL, "n_doubles must be nfields * ncells");
   StageArgs a = base_args(x);
   a.in = x->state; a.base = x->state; a.out = x->stage; a.mode = MODE_OPER; a.gas_only = 0;
+  HIPCHK(x, prep_stage(x, a), "indirect sums");
   HIPCHK(x, launch_stage(a, x->L.nblocks, x->stream), "operator");
   if (x->g.p32) {
     // FP32 form: the kernels write FP32; widened at the boundary
@@ -609,6 +626,7 @@ rb_status rb_record(rb_ctx* x, int n, int ckpt_every, const rb_dt_policy* policy
                     void* ws, size_t ws_bytes) {
   if (!x || !policy || !ws || n < 1 || ckpt_every < 1) return RB_EINVAL;
   if (x->g.p32) return fail(x, RB_EINVAL, "the adjoint is FP64 only");
+  if (x->g.indirect) return fail(x, RB_EINVAL, "the adjoint does not cover indirect gravity");
   const int k = std::min(ckpt_every, n);
   const AdjLayout A = adj_layout(x, n, k);
   if (ws_bytes < A.total * sizeof(double)) return fail(x, RB_EINVAL, "workspace too small");

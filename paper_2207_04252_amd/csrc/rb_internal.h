@@ -46,7 +46,8 @@ struct Ctrl {
 // Offsets (in doubles) of the tables inside the work area.
 struct Layout {
   size_t ctrl, rt, ar, rco, rcell, zc, bgc, bgr, bgz, r0, grav, ghr, ghrf, ghz, ghzf;
-  size_t dsc, dtlog, cflp, outp, red, total;
+  size_t dsc, trig, indw, indab, indp, dtlog, cflp, outp, red, total;
+  int nind;      // blocks of the indirect-gravity sums
   int nblocks;   // stage-kernel blocks
   int ntj, nti, nkc, tk;
   int ncfl;      // blocks of the standalone CFL / conversion kernels
@@ -55,6 +56,7 @@ struct Layout {
 struct Geo {
   int nr, nth, nz, twod, nd, nf;
   int p32;       // state stored as FP32 perturbation (gas) / scaled dust
+  int indirect;  // indirect gravity of the displaced star
   size_t N;
   double gamma, GM, cfl;
   double inv_st[4];
@@ -74,6 +76,9 @@ struct Tables {
   const double* ghz;
   const double* ghzf;
   const double* dsc;   // dust storage scale [species][k][i] (FP32 storage)
+  const double* trig;  // cos, sin of the theta cell centres [2][ntheta]
+  const double* indw;  // V r / (r^2 + z^2)^(3/2) per (k, i) (indirect-gravity sums)
+  const double* indab; // the indirect-gravity sums A, B of the current stage input
 };
 
 struct Ctl {
@@ -143,6 +148,9 @@ hipError_t launch_from_full(const StageArgs& a, const double* in, void* state, i
 hipError_t launch_mass(const StageArgs& a, const void* state, double* partials, int f,
                        int blocks, hipStream_t s);
 hipError_t launch_sum(const double* partials, int n, double* out, hipStream_t s);
+// indirect-gravity sums A, B of a state into the table (fixed-order partial sums)
+hipError_t launch_indirect(const StageArgs& a, const void* state, double* partials, int blocks,
+                           double* ab, hipStream_t s);
 // d(initial state)/d(vortex amplitude) contracted with a state cotangent, per cell
 hipError_t launch_amp_grad(const InitArgs& a, const double* lam, double* out, hipStream_t s);
 

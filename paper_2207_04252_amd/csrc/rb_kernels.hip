@@ -322,6 +322,22 @@ __global__ void __launch_bounds__(NT) k_march(StageArgs a, int species) {
       S[2] = rd * gz - fz;
       S[3] = 0.0;
     }
+    // indirect gravity (Sect. 2.10): minus the star's acceleration by the disc
+    if (g.indirect && a.mode != MODE_RESID) {
+      const double A = a.t.indab[0], B = a.t.indab[1];
+      const double cs = a.t.trig[jw], sn = a.t.trig[g.nth + jw];
+      const double ar = -g.GM * (A * cs + B * sn), at = -g.GM * (B * cs - A * sn);
+      if constexpr (GAS) {
+        const double mr = bgc[0] + (double)r0[0], mt = bgc[1] + (double)r0[1];
+        const double rho = bgc[4] + (double)r0[4];
+        S[0] += (T)(rho * ar);
+        S[1] += (T)(rho * at);
+        S[3] += (T)(mr * ar + mt * at);
+      } else {
+        S[0] += r0[3] * ar;
+        S[1] += r0[3] * at;
+      }
+    }
     T Gt[NG];
 #pragma unroll
     for (int f = 0; f < NG; ++f) Gt[f] = fma(S[f], T(Vc), Gd[f]);
@@ -595,6 +611,11 @@ __global__ void __launch_bounds__(256) k_tables_r(InitArgs a) {
   const double dth = 2.0 * M_PI / c.ntheta;
   const double dz = twod ? 1.0 : 2.0 * c.z_half / c.nz;
   for (int i = threadIdx.x; i < nr + 4; i += blockDim.x) w[L.rcell + i] = cell_r(c, i - 2);
+  for (int j = threadIdx.x; j < c.ntheta; j += blockDim.x) {
+    const double th = (j + 0.5) * dth;
+    w[L.trig + j] = cos(th);
+    w[L.trig + c.ntheta + j] = sin(th);
+  }
   for (int i = threadIdx.x; i <= nr; i += blockDim.x) w[L.ar + i] = face_r(c, i) * dth * dz;
   for (int i = threadIdx.x; i < nr; i += blockDim.x) {
     double rm = face_r(c, i), rp = face_r(c, i + 1);
@@ -655,6 +676,13 @@ __global__ void __launch_bounds__(256) k_tables_2d(InitArgs a) {
     const double zc = twod ? 0.0 : (kk + 0.5 - 0.5 * nz) * dz;
     double q[MAXF];
     const bool kin = kk >= 0 && kk < nz, iin = ii >= 0 && ii < nr;
+    if (kin && iin) {
+      // indirect-gravity weight V r / (r^2 + z^2)^(3/2) of the cell
+      const double rm = face_r(c, ii), rp = face_r(c, ii + 1), rc = cell_r(c, ii);
+      const double V = 0.5 * (rp * rp - rm * rm) * (2.0 * M_PI / c.ntheta) * dz;
+      const double s2 = rc * rc + zc * zc;
+      w[L.indw + (size_t)kk * nr + ii] = V * rc / (s2 * sqrt(s2));
+    }
     if (kin && iin) {
       const double r = cell_r(c, ii);
       background_full(a, r, zc, q);
@@ -870,6 +898,49 @@ __global__ void __launch_bounds__(256) k_mass(StageArgs a, const void* state, do
   if (threadIdx.x == 0) part[blockIdx.x] = (s_s[0] + s_s[1]) + (s_s[2] + s_s[3]);
 }
 
+// Indirect-gravity sums A = sum m w cos(theta), B = sum m w sin(theta) over the cells,
+// m = gas + dust density, w = V r / (r^2 + z^2)^(3/2): per-block partials over fixed
+// chunks, then one block adds them in a fixed order (deterministic, FP64).
+template <bool P32>
+__global__ void __launch_bounds__(256) k_indirect(StageArgs a, const void* state, double* part) {
+  __shared__ double s_s[2][4];
+  const Geo& g = a.g;
+  const size_t chunk = (g.N + gridDim.x - 1) / gridDim.x;
+  const size_t c0 = (size_t)blockIdx.x * chunk, c1 = min(g.N, c0 + chunk);
+  double sa = 0.0, sb = 0.0;
+  for (size_t c = c0 + threadIdx.x; c < c1; c += blockDim.x) {
+    const size_t ki = c / g.nth;
+    const int j = (int)(c % g.nth), i = (int)(ki % g.nr), k = (int)(ki / g.nr);
+    double m = a.t.bgc[ki * 5 + 4] + ld_cell<P32>(a, state, 4, k, i, c);
+    for (int s = 0; s < g.nd; ++s) m += ld_cell<P32>(a, state, 5 + 4 * s + 3, k, i, c);
+    const double mw = m * a.t.indw[ki];
+    sa += mw * a.t.trig[j];
+    sb += mw * a.t.trig[g.nth + j];
+  }
+  sa = wave_sum(sa);
+  sb = wave_sum(sb);
+  if ((threadIdx.x & 63) == 0) { s_s[0][threadIdx.x / 64] = sa; s_s[1][threadIdx.x / 64] = sb; }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    part[2 * blockIdx.x] = (s_s[0][0] + s_s[0][1]) + (s_s[0][2] + s_s[0][3]);
+    part[2 * blockIdx.x + 1] = (s_s[1][0] + s_s[1][1]) + (s_s[1][2] + s_s[1][3]);
+  }
+}
+
+__global__ void __launch_bounds__(256) k_indirect_final(const double* part, int n, double* ab) {
+  __shared__ double s_s[2][4];
+  double sa = 0.0, sb = 0.0;
+  for (int b = threadIdx.x; b < n; b += blockDim.x) { sa += part[2 * b]; sb += part[2 * b + 1]; }
+  sa = wave_sum(sa);
+  sb = wave_sum(sb);
+  if ((threadIdx.x & 63) == 0) { s_s[0][threadIdx.x / 64] = sa; s_s[1][threadIdx.x / 64] = sb; }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    ab[0] = (s_s[0][0] + s_s[0][1]) + (s_s[0][2] + s_s[0][3]);
+    ab[1] = (s_s[1][0] + s_s[1][1]) + (s_s[1][2] + s_s[1][3]);
+  }
+}
+
 __global__ void __launch_bounds__(256) k_sum(const double* part, int n, double* out) {
   __shared__ double s_s[4];
   double acc = 0.0;
@@ -996,6 +1067,14 @@ hipError_t launch_mass(const StageArgs& a, const void* state, double* partials, 
 hipError_t launch_amp_grad(const InitArgs& a, const double* lam, double* out, hipStream_t s) {
   const int blocks = (int)std::min<size_t>((a.g.N + 255) / 256, 65536);
   hipLaunchKernelGGL(k_amp_grad, dim3(blocks), dim3(256), 0, s, a, lam, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_indirect(const StageArgs& a, const void* state, double* partials, int blocks,
+                           double* ab, hipStream_t s) {
+  if (a.g.p32) hipLaunchKernelGGL(k_indirect<true>, dim3(blocks), dim3(256), 0, s, a, state, partials);
+  else hipLaunchKernelGGL(k_indirect<false>, dim3(blocks), dim3(256), 0, s, a, state, partials);
+  hipLaunchKernelGGL(k_indirect_final, dim3(1), dim3(256), 0, s, partials, blocks, ab);
   return hipGetLastError();
 }
 

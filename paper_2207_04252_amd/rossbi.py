@@ -44,6 +44,7 @@ class rb_config(ctypes.Structure):
         ("vortex_sig_a", ctypes.c_double), ("noise_amp", ctypes.c_double),
         ("stokes", ctypes.c_double * 4), ("eps_dust", ctypes.c_double * 4),
         ("hd_over_h", ctypes.c_double * 4),
+        ("indirect", ctypes.c_int32), ("reserved", ctypes.c_int32),
     ]
 
 
@@ -140,6 +141,7 @@ def to_config(cfg: synth.Config, precision: int = RB_FP64) -> rb_config:
         c.stokes[q] = cfg.stokes[q]
         c.eps_dust[q] = cfg.eps_dust[q]
         c.hd_over_h[q] = cfg.hd_over_h[q]
+    c.indirect = int(cfg.indirect)
     return c
 
 
