@@ -51,6 +51,9 @@ class OrConfig(ctypes.Structure):
         ("vortex_sig_a", ctypes.c_double), ("noise_amp", ctypes.c_double),
         ("stokes", ctypes.c_double * 4), ("eps_dust", ctypes.c_double * 4),
         ("hd_over_h", ctypes.c_double * 4),
+        ("drag_law", ctypes.c_int32), ("pad1", ctypes.c_int32),
+        ("grain_size", ctypes.c_double * 4), ("grain_density", ctypes.c_double * 4),
+        ("mfp_coef", ctypes.c_double),
     ]
 
 
@@ -86,6 +89,12 @@ def to_struct(cfg: synth.Config) -> OrConfig:
         s.stokes[q] = cfg.stokes[q]
         s.eps_dust[q] = cfg.eps_dust[q]
         s.hd_over_h[q] = cfg.hd_over_h[q]
+    s.drag_law = int(getattr(cfg, "drag_law", 0))
+    if s.drag_law:
+        for q in range(cfg.n_dust):
+            s.grain_size[q] = cfg.grain_size[q]
+            s.grain_density[q] = cfg.grain_density[q]
+        s.mfp_coef = cfg.mfp_coef
     return s
 
 
@@ -112,6 +121,8 @@ def lib() -> ctypes.CDLL:
         L.or_cfl_dt.argtypes = [ctypes.c_void_p]
         L.or_min_stopping_time.restype = ctypes.c_double
         L.or_min_stopping_time.argtypes = [ctypes.c_void_p]
+        L.or_stopping_times.argtypes = [ctypes.c_void_p, _D]
+        L.or_stopping_times.restype = None
         L.or_diag.argtypes = [ctypes.c_void_p, ctypes.POINTER(OrDiag)]
         L.or_core_dust_mass.restype = ctypes.c_double
         L.or_core_dust_mass.argtypes = [ctypes.c_void_p, ctypes.c_double, ctypes.c_double,
@@ -226,6 +237,14 @@ class Oracle:
 
     def min_stopping_time(self) -> float:
         return lib().or_min_stopping_time(self.h)
+
+    def stopping_times(self) -> np.ndarray:
+        """Stopping time of each dust species in each cell of the current state,
+        [species][nz][nr][ntheta] (Sect. 2.9)."""
+        c = self.cfg
+        out = np.zeros((max(c.n_dust, 1), c.nz, c.nr, c.nth))
+        lib().or_stopping_times(self.h, _ptr(out))
+        return out[: c.n_dust]
 
     def mass(self) -> np.ndarray:
         out = np.zeros(5)

@@ -33,7 +33,9 @@
  *   - the empty run evaluates the whole spatial operator once on the gas
  *     equilibrium, without dust, and is subtracted from the gas components in
  *     both stages;
- *   - drag uses a constant Stokes number, t_s = St / Omega_K(r).
+ *   - drag uses a constant Stokes number, t_s = St / Omega_K(r), or (drag_law 1) the
+ *     Epstein / Stokes law of Sect. 2.9 with c_s the isothermal sound speed sqrt(p/rho)
+ *     of the cell's gas (the c_s of App. A) and lambda = mfp_coef / rho_g.
  * Parity unpinned (no external value exists for them): the limiter variant,
  * the dust tie rule, the vortex recipe of the initial state.
  */
@@ -56,6 +58,8 @@ typedef struct {
   double h0, beta_T, rho_mid0, beta_rho;
   double vortex_amp, vortex_r0, vortex_th0, vortex_sig_r, vortex_sig_a, noise_amp;
   double stokes[4], eps_dust[4], hd_over_h[4];
+  int32_t drag_law, pad1;
+  double grain_size[4], grain_density[4], mfp_coef;
 } OrConfig;
 
 typedef struct {
@@ -860,7 +864,7 @@ struct Sim {
                 ud = U[(o + 0) * N + id] / rd; vd = U[(o + 1) * N + id] / rd;
                 wd = U[(o + 2) * N + id] / rd;
               }
-              T ts = stokes[s] / omk;
+              T ts = stopping_time(s, omk, rho, p);
               T fx = rd * (ud - u) / ts, fy = rd * (vd - v) / ts, fz = rd * (wd - w) / ts;
               dragx = dragx + fx; dragy = dragy + fy; dragz = dragz + fz;
               S[o + 0] = rd * vd * vd / r + rd * gr - fx;
@@ -963,13 +967,38 @@ struct Sim {
     return bad;
   }
 
-  double min_stopping_time() const {
+  /* stopping time of species s in a cell (Sect. 2.9).  Law 0: t_s = St / Omega_K.
+   * Law 1: Epstein t = rho_s r_p / (rho_g c_s) while r_p <= 9 lambda / 4, else Stokes
+   * t = (4/9) (r_p / lambda) t^E, with lambda = mfp_coef / rho_g (the mean free path
+   * mu m_u / (sigma_eff rho_g) with its constant folded) and c_s = sqrt(p / rho_g). */
+  T stopping_time(int s, double omk, T rho, T p) const {
+    if (c.drag_law == 0) return stokes[s] / omk;
+    T cs = sqrt_(p / rho);
+    T tE = (c.grain_density[s] * c.grain_size[s]) / (rho * cs);
+    T lam = c.mfp_coef / rho;
+    if (c.grain_size[s] <= 9.0 * val(lam) / 4.0) return tE;
+    return (4.0 / 9.0) * (c.grain_size[s] / lam) * tE;
+  }
+
+  /* smallest stopping time over species and cells of the state U */
+  double min_stopping_time(const std::vector<T>& U) const {
+    const double g = c.gamma;
     double tmin = 1e300;
-    for (int s = 0; s < nd; ++s)
-      for (int i = 0; i < nr; ++i) {
-        double r = rce(i);
-        tmin = std::min(tmin, val(stokes[s]) / std::sqrt(c.GM / (r * r * r)));
-      }
+    if (c.drag_law == 0) {
+      for (int s = 0; s < nd; ++s)
+        for (int i = 0; i < nr; ++i) {
+          double r = rce(i);
+          tmin = std::min(tmin, val(stokes[s]) / std::sqrt(c.GM / (r * r * r)));
+        }
+      return tmin;
+    }
+    for (size_t id = 0; id < N; ++id) {
+      double rho = val(U[4 * N + id]);
+      double m2 = 0.0;
+      for (int q = 0; q < 3; ++q) m2 += val(U[q * N + id]) * val(U[q * N + id]);
+      double p = (g - 1.0) * (val(U[3 * N + id]) - 0.5 * m2 / rho);
+      for (int s = 0; s < nd; ++s) tmin = std::min(tmin, val(stopping_time(s, 1.0, T(rho), T(p))));
+    }
     return tmin;
   }
 
@@ -1072,7 +1101,7 @@ struct Sim {
       else if (dt_kind == 1) dt = dt_fixed;
       else dt = dt_list[q];
       if (!(dt > 0.0)) return OR_EINVAL;
-      if (nd > 0 && dt >= min_stopping_time()) { flags |= F_STIFF; return OR_ESTIFF; }
+      if (nd > 0 && dt >= min_stopping_time(E)) { flags |= F_STIFF; return OR_ESTIFF; }
       if (dt_out) dt_out[q] = dt;
       dt_last = dt;
       int st = one_step(dt);
@@ -1169,7 +1198,28 @@ double or_cfl_dt(void* h) {
   return s->cfl_dt(s->E);
 }
 
-double or_min_stopping_time(void* h) { return ((Sim<double>*)h)->min_stopping_time(); }
+/* stopping time of every dust species in every cell of the current state, [s][cell] */
+void or_stopping_times(void* h, double* out) {
+  Sim<double>* s = (Sim<double>*)h;
+  const size_t N = s->N;
+  const double g = s->c.gamma;
+  for (size_t id = 0; id < N; ++id) {
+    const std::vector<double>& U = s->E;
+    double rho = U[4 * N + id];
+    double m2 = U[0 * N + id] * U[0 * N + id] + U[1 * N + id] * U[1 * N + id] +
+                U[2 * N + id] * U[2 * N + id];
+    double p = (g - 1.0) * (U[3 * N + id] - 0.5 * m2 / rho);
+    int i = (int)((id / s->nth) % s->nr);
+    double r = s->rce(i);
+    double omk = std::sqrt(s->c.GM / (r * r * r));
+    for (int q = 0; q < s->nd; ++q) out[(size_t)q * N + id] = s->stopping_time(q, omk, rho, p);
+  }
+}
+
+double or_min_stopping_time(void* h) {
+  Sim<double>* s = (Sim<double>*)h;
+  return s->min_stopping_time(s->E);
+}
 
 void or_mass(void* h, double* out) { ((Sim<double>*)h)->masses(out); }
 

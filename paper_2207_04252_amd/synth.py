@@ -64,6 +64,13 @@ class Config:
     hd_over_h: Tuple[float, ...] = ()
     steps: int = 100
     indirect: bool = False      # indirect gravity of the star's displacement (Sect. 2.10)
+    # drag law (Sect. 2.9): 0 constant Stokes number (t_s = St / Omega_K); 1 Epstein /
+    # Stokes regimes from the grain radius and material density, with the gas mean free
+    # path lambda = mfp_coef / rho_g (code units)
+    drag_law: int = 0
+    grain_size: Tuple[float, ...] = ()
+    grain_density: Tuple[float, ...] = ()
+    mfp_coef: float = 0.0
 
     @property
     def n_dust(self) -> int:
@@ -108,6 +115,23 @@ C5_ADJOINT = _disc("adjoint_disc_128x256x32", 128, 256, 32, stokes=(0.1,),
                    eps_dust=(0.01,), hd_over_h=(0.3,), steps=200)
 
 CONFIGS = {c.name: c for c in (C1_SOD, C2_DISC, C3_BIFLUID, C4_LARGE, C5_ADJOINT)}
+
+
+def epstein_grains(cfg: Config, rho_switch: float = 0.5, rho_s: float = 1.0) -> Config:
+    """The disc cfg with the Epstein / Stokes drag law (Sect. 2.9) in place of constant
+    Stokes numbers: each species gets the grain radius whose Epstein stopping time at
+    r = 1, z = 0 of the stationary disc is its configured Stokes number (material density
+    rho_s), and the mean-free-path constant puts the regime switch r_p = 9 lambda / 4 of
+    the middle species at gas density rho_switch, so that grains of that size are in the
+    Stokes regime in the dense inner midplane and in the Epstein regime elsewhere."""
+    assert cfg.init_kind == INIT_DISC and cfg.n_dust > 0
+    c1 = cfg.h0 * math.sqrt(cfg.GM)          # isothermal sound speed at r = 1
+    om1 = math.sqrt(cfg.GM)
+    sizes = tuple(st * cfg.rho_mid0 * c1 / (om1 * rho_s) for st in cfg.stokes)
+    mid = sizes[len(sizes) // 2]
+    return cfg.with_(drag_law=1, grain_size=sizes, grain_density=(rho_s,) * len(sizes),
+                     mfp_coef=4.0 * rho_switch * mid / 9.0,
+                     name=cfg.name.replace("_disc", "_epstein_disc", 1))
 
 # vortex core region used by the adjoint objective (dust mass in the core)
 CORE_R = (0.9, 1.1)
