@@ -87,7 +87,16 @@ typedef struct {
    * acceleration by the disc, G sum m r_vec/|r_vec|^3 over gas and dust (G = GM, unit star
    * mass); recomputed from each stage's input.  Disc only; not with rb_record.          */
   int32_t indirect;
-  int32_t reserved;
+  /* drag law (Sect. 2.9).  0: constant Stokes number, t_s = stokes[s] / Omega_K(r).
+   * 1: Epstein / Stokes regimes from the gas state of each cell: with c_s = sqrt(p/rho)
+   * (the isothermal sound speed of App. A) and the mean free path lambda = mfp_coef/rho
+   * (mu m_u / sigma_eff folded into one code-unit constant), t^E = grain_density
+   * grain_size / (rho c_s) while grain_size <= 9 lambda / 4, else (4/9)(grain_size /
+   * lambda) t^E.  The stiffness check (RB_ESTIFF) then takes the minimum over cells of
+   * the state at the start of each step.  stokes[] is unused by law 1; not with
+   * rb_record.                                                                         */
+  int32_t drag_law;
+  double grain_size[4], grain_density[4], mfp_coef;
 } rb_config;
 
 /* Caller-owned device buffers.  Sizes come from rb_query_sizes; pointers must be

@@ -58,10 +58,19 @@ bool validate(const rb_config* c, std::string* why) {
   if (c->init_kind != RB_INIT_SOD && c->init_kind != RB_INIT_DISC) return bad("unknown init_kind");
   if (c->init_kind == RB_INIT_DISC && !(c->GM > 0.0)) return bad("disc needs GM > 0");
   if (c->init_kind == RB_INIT_SOD && c->n_dust > 0) return bad("Sod annulus carries no dust");
-  if (c->n_dust > 0 && !(c->GM > 0.0)) return bad("dust drag needs GM > 0 (t_s = St/Omega_K)");
+  if (c->drag_law != 0 && c->drag_law != 1) return bad("drag_law must be 0 or 1");
+  if (c->n_dust > 0 && c->drag_law == 0 && !(c->GM > 0.0))
+    return bad("dust drag needs GM > 0 (t_s = St/Omega_K)");
+  if (c->n_dust > 0 && c->drag_law == 1) {
+    if (!(c->mfp_coef > 0.0)) return bad("drag law 1 needs mfp_coef > 0");
+    for (int s = 0; s < c->n_dust; ++s)
+      if (!(c->grain_size[s] > 0.0) || !(c->grain_density[s] > 0.0))
+        return bad("drag law 1 needs positive grain sizes and densities");
+  }
   if (c->indirect && c->init_kind != RB_INIT_DISC) return bad("indirect gravity needs a disc");
   for (int s = 0; s < c->n_dust; ++s)
-    if (!(c->stokes[s] > 0.0) || !(c->hd_over_h[s] > 0.0) || !(c->eps_dust[s] >= 0.0))
+    if ((c->drag_law == 0 && !(c->stokes[s] > 0.0)) || !(c->hd_over_h[s] > 0.0) ||
+        !(c->eps_dust[s] >= 0.0))
       return bad("dust parameters must be positive");
   if (c->precision != RB_FP64 && c->precision != RB_FP32_PERT) return bad("unknown precision");
   if (c->precision == RB_FP32_PERT && c->init_kind != RB_INIT_DISC)
@@ -122,6 +131,7 @@ Layout make_layout(const rb_config& c) {
   L.dtlog = take(DTLOG + 2);
   L.cflp = take(std::max((size_t)L.nblocks * 5, (size_t)L.ncfl));
   L.outp = take((size_t)L.nblocks * 5);
+  L.tsp = take(std::max((size_t)L.nblocks, (size_t)L.ncfl));
   L.red = take(2048 + 16);
   L.total = o;
   return L;
@@ -137,7 +147,14 @@ Geo make_geo(const rb_config& c) {
   g.gamma = c.gamma; g.GM = c.GM; g.cfl = c.cfl;
   g.p32 = c.precision == RB_FP32_PERT;
   g.indirect = c.indirect != 0;
-  for (int s = 0; s < 4; ++s) g.inv_st[s] = s < c.n_dust ? 1.0 / c.stokes[s] : 0.0;
+  g.drag_law = c.drag_law;
+  g.mfp = c.drag_law ? c.mfp_coef : 0.0;
+  for (int s = 0; s < 4; ++s) {
+    const bool on = s < c.n_dust;
+    g.inv_st[s] = on && c.drag_law == 0 ? 1.0 / c.stokes[s] : 0.0;
+    g.inv_mp[s] = on && c.drag_law ? 1.0 / (c.grain_density[s] * c.grain_size[s]) : 0.0;
+    g.rp94[s] = on && c.drag_law ? 4.0 * c.grain_size[s] / 9.0 : 0.0;
+  }
   return g;
 }
 
@@ -154,6 +171,7 @@ StageArgs base_args(rb_ctx* x) {
   a.t.trig = w + L.trig; a.t.indw = w + L.indw; a.t.indab = w + L.indab;
   a.c.ctrl = reinterpret_cast<Ctrl*>(w + L.ctrl);
   a.c.dtlog = w + L.dtlog; a.c.cflp = w + L.cflp; a.c.outp = w + L.outp; a.c.r0w = w + L.r0;
+  a.c.tsp = w + L.tsp;
   a.tk = L.tk; a.ntj = L.ntj; a.nti = L.nti; a.nkc = L.nkc;
   a.dt_idx = -1;
   return a;
@@ -210,10 +228,10 @@ struct ProfScope {
     slot = x->ev_used;
     x->ev_used += 2;
     x->ev_kind[slot / 2] = kind;
-    hipEventRecord(x->ev[slot], x->stream);
+    (void)hipEventRecord(x->ev[slot], x->stream);
   }
   ~ProfScope() {
-    if (x->prof && slot + 1 < x->ev.size()) hipEventRecord(x->ev[slot + 1], x->stream);
+    if (x->prof && slot + 1 < x->ev.size()) (void)hipEventRecord(x->ev[slot + 1], x->stream);
   }
 };
 
@@ -627,6 +645,7 @@ rb_status rb_record(rb_ctx* x, int n, int ckpt_every, const rb_dt_policy* policy
   if (!x || !policy || !ws || n < 1 || ckpt_every < 1) return RB_EINVAL;
   if (x->g.p32) return fail(x, RB_EINVAL, "the adjoint is FP64 only");
   if (x->g.indirect) return fail(x, RB_EINVAL, "the adjoint does not cover indirect gravity");
+  if (x->g.drag_law) return fail(x, RB_EINVAL, "the adjoint covers the constant-Stokes drag only");
   const int k = std::min(ckpt_every, n);
   const AdjLayout A = adj_layout(x, n, k);
   if (ws_bytes < A.total * sizeof(double)) return fail(x, RB_EINVAL, "workspace too small");
@@ -767,7 +786,7 @@ const char* rb_last_error(const rb_ctx* x) { return x ? x->err.c_str() : "null c
 
 void rb_destroy(rb_ctx* x) {
   if (!x) return;
-  for (hipEvent_t e : x->ev) hipEventDestroy(e);
+  for (hipEvent_t e : x->ev) (void)hipEventDestroy(e);
   delete x;
 }
 

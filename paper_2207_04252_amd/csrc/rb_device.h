@@ -680,6 +680,17 @@ __device__ __forceinline__ int wave_imax(int v) {
   return v;
 }
 
+// Inverse dust stopping time of species s in a cell whose gas has density rho and
+// pressure p (Sect. 2.9).  Law 0: Omega_K / St.  Law 1: Epstein 1/t = rho c_s / (rho_s r_p)
+// with the isothermal c_s = sqrt(p / rho), i.e. sqrt(p rho) / (rho_s r_p); in the Stokes
+// regime (r_p > 9 lambda / 4, lambda = mfp / rho) the Epstein rate times 9 lambda / (4 r_p).
+__device__ __forceinline__ double inv_tstop(const Geo& g, int s, double omk, double rho, double p) {
+  if (g.drag_law == 0) return omk * g.inv_st[s];
+  const double ie = sqrt(p * rho) * g.inv_mp[s];
+  const double x = g.rp94[s] * rho;
+  return x <= g.mfp ? ie : ie * g.mfp / x;
+}
+
 // XCD-aware tile order: workgroup b is dispatched to XCD b % 8; give every XCD a
 // contiguous range of tiles so that halo re-reads hit its own L2.
 __device__ __forceinline__ int xcd_tile(int b, int nblk) {

@@ -46,7 +46,7 @@ struct Ctrl {
 // Offsets (in doubles) of the tables inside the work area.
 struct Layout {
   size_t ctrl, rt, ar, rco, rcell, zc, bgc, bgr, bgz, r0, grav, ghr, ghrf, ghz, ghzf;
-  size_t dsc, trig, indw, indab, indp, dtlog, cflp, outp, red, total;
+  size_t dsc, trig, indw, indab, indp, dtlog, cflp, outp, tsp, red, total;
   int nind;      // blocks of the indirect-gravity sums
   int nblocks;   // stage-kernel blocks
   int ntj, nti, nkc, tk;
@@ -57,9 +57,13 @@ struct Geo {
   int nr, nth, nz, twod, nd, nf;
   int p32;       // state stored as FP32 perturbation (gas) / scaled dust
   int indirect;  // indirect gravity of the displaced star
+  int drag_law;  // 0 constant Stokes number, 1 Epstein / Stokes regimes
   size_t N;
   double gamma, GM, cfl;
   double inv_st[4];
+  double inv_mp[4];  // 1 / (grain density x grain radius)   (drag law 1)
+  double rp94[4];    // 4 grain radius / 9                    (drag law 1)
+  double mfp;        // mean-free-path constant: lambda = mfp / rho_gas
 };
 
 struct Tables {
@@ -86,6 +90,7 @@ struct Ctl {
   double* dtlog;
   double* cflp;
   double* outp;
+  double* tsp;   // per-block smallest stopping time of a state (drag law 1)
   double* r0w;   // writable residual table (empty run)
 };
 

@@ -31,7 +31,7 @@ __global__ void __launch_bounds__(NT) k_march(StageArgs a, int species) {
   __shared__ T s_pl[NG][TI + 4][TJ + 4];
   __shared__ T s_ft[NG][TI][TJ + 1];
   __shared__ T s_fr[NG][TI + 1][TJ];
-  __shared__ double s_red[NT / 64][2];
+  __shared__ double s_red[NT / 64][3];
 
   const Geo& g = a.g;
   const GasC gc = gas_consts(g.gamma);
@@ -55,6 +55,7 @@ __global__ void __launch_bounds__(NT) k_march(StageArgs a, int species) {
 
   TStat st = {0, 0, 0, 0, 0};
   double dtmin = 1e300;
+  double tsmin = 1e300;  // smallest stopping time of the new state (drag law 1)
   double ledger = 0.0;
 
   const double* rt = a.t.rt + (size_t)igc * RT_N;
@@ -241,6 +242,7 @@ __global__ void __launch_bounds__(NT) k_march(StageArgs a, int species) {
         for (int f = 0; f < 5; ++f) q[f] = bgc[f] + (double)r0[f];
         const double inv = 1.0 / q[4];
         const double u = q[0] * inv, v = q[1] * inv, w2 = q[2] * inv;
+        const double pq = g.drag_law ? gc.gm1 * (q[3] - 0.5 * (q[0] * u + q[1] * v + q[2] * w2)) : 0.0;
         double dx = 0.0, dy = 0.0, dzz = 0.0;
 #pragma unroll
         for (int s2 = 0; s2 < ND; ++s2) {
@@ -253,7 +255,7 @@ __global__ void __launch_bounds__(NT) k_march(StageArgs a, int species) {
             vd = ld_cell<P32>(a, in, o + 1, k, igc, cellw) * id;
             wd = ld_cell<P32>(a, in, o + 2, k, igc, cellw) * id;
           }
-          const double its = omk * g.inv_st[s2];
+          const double its = inv_tstop(g, s2, omk, q[4], pq);
           dx += rd * (ud - u) * its;
           dy += rd * (vd - v) * its;
           dzz += rd * (wd - w2) * its;
@@ -288,7 +290,7 @@ __global__ void __launch_bounds__(NT) k_march(StageArgs a, int species) {
             vd = ld_cell<P32>(a, in, o + 1, k, igc, cellw) * id;
             wd = ld_cell<P32>(a, in, o + 2, k, igc, cellw) * id;
           }
-          const double its = omk * g.inv_st[s2];
+          const double its = inv_tstop(g, s2, omk, q[4], p);
           dx += rd * (ud - u) * its;
           dy += rd * (vd - v) * its;
           dzz += rd * (wd - w) * its;
@@ -312,7 +314,8 @@ __global__ void __launch_bounds__(NT) k_march(StageArgs a, int species) {
         for (int f = 0; f < 5; ++f) q[f] = bgc[f] + ld_cell<P32>(a, in, f, k, igc, cellw);
         const double inv = 1.0 / q[4];
         const double u = q[0] * inv, v = q[1] * inv, w = q[2] * inv;
-        const double its = omk * g.inv_st[species];
+        const double pq = g.drag_law ? gc.gm1 * (q[3] - 0.5 * (q[0] * u + q[1] * v + q[2] * w)) : 0.0;
+        const double its = inv_tstop(g, species, omk, q[4], pq);
         fx = rd * (ud - u) * its;
         fy = rd * (vd - v) * its;
         fz = rd * (wd - w) * its;
@@ -392,6 +395,10 @@ __global__ void __launch_bounds__(NT) k_march(StageArgs a, int species) {
         } else if (a.second) {
           double spd = sqrt(un * un + vn * vn + wn * wn) + sqrt(gc.g * pn * in2);
           dtmin = fmin(dtmin, g.cfl * Vc / (spd * maxA));
+          if (g.drag_law) {
+#pragma unroll
+            for (int s2 = 0; s2 < ND; ++s2) tsmin = fmin(tsmin, 1.0 / inv_tstop(g, s2, omk, qn[4], pn));
+          }
         }
       } else if (a.second && nvd[3] > 0.0) {
         double id = 1.0 / nvd[3];
@@ -421,16 +428,19 @@ __global__ void __launch_bounds__(NT) k_march(StageArgs a, int species) {
   if (a.second && a.mode == MODE_UPDATE) {
     double m = wave_min(dtmin);
     double ls = wave_sum(ledger);
-    if (ln == 0) { s_red[wv][0] = m; s_red[wv][1] = ls; }
+    double tm = (GAS && ND > 0) ? wave_min(tsmin) : 1e300;
+    if (ln == 0) { s_red[wv][0] = m; s_red[wv][1] = ls; s_red[wv][2] = tm; }
     __syncthreads();
     if (tid == 0) {
-      double mm = s_red[0][0], lsum = s_red[0][1];
+      double mm = s_red[0][0], lsum = s_red[0][1], tmm = s_red[0][2];
       for (int w2 = 1; w2 < NT / 64; ++w2) {
         mm = fmin(mm, s_red[w2][0]);
         lsum += s_red[w2][1];
+        tmm = fmin(tmm, s_red[w2][2]);
       }
       a.c.cflp[(size_t)blockIdx.x * 5 + slot] = mm;
       a.c.outp[(size_t)blockIdx.x * 5 + slot] = lsum;
+      if (GAS && g.drag_law) a.c.tsp[blockIdx.x] = tmm;
     }
   }
 }
@@ -441,8 +451,9 @@ __global__ void __launch_bounds__(NT) k_march(StageArgs a, int species) {
 template <int ND, bool P32>
 __global__ void __launch_bounds__(256) k_cfl(StageArgs a, const void* state) {
   __shared__ double s_m[4];
+  __shared__ double s_t[4];
   const Geo& g = a.g;
-  double dtmin = 1e300;
+  double dtmin = 1e300, tsmin = 1e300;
   const double gm1 = g.gamma - 1.0;
   for (size_t c = (size_t)blockIdx.x * blockDim.x + threadIdx.x; c < g.N;
        c += (size_t)gridDim.x * blockDim.x) {
@@ -477,13 +488,19 @@ __global__ void __launch_bounds__(256) k_cfl(StageArgs a, const void* state) {
     }
     const double* rt = a.t.rt + (size_t)i * RT_N;
     dtmin = fmin(dtmin, g.cfl * rt[RT_V] / (spd * rt[RT_MAXA]));
+    if (g.drag_law) {
+#pragma unroll
+      for (int s = 0; s < ND; ++s) tsmin = fmin(tsmin, 1.0 / inv_tstop(g, s, rt[RT_OMK], q[4], p));
+    }
   }
   double m = wave_min(dtmin);
-  if ((threadIdx.x & 63) == 0) s_m[threadIdx.x / 64] = m;
+  double tm = wave_min(tsmin);
+  if ((threadIdx.x & 63) == 0) { s_m[threadIdx.x / 64] = m; s_t[threadIdx.x / 64] = tm; }
   __syncthreads();
   if (threadIdx.x == 0) {
     double mm = fmin(fmin(s_m[0], s_m[1]), fmin(s_m[2], s_m[3]));
     a.c.cflp[blockIdx.x] = mm;
+    if (g.drag_law) a.c.tsp[blockIdx.x] = fmin(fmin(s_t[0], s_t[1]), fmin(s_t[2], s_t[3]));
   }
 }
 
@@ -491,17 +508,20 @@ __global__ void __launch_bounds__(256) k_cfl(StageArgs a, const void* state) {
 __global__ void __launch_bounds__(256) k_reduce(StageArgs a, int nparts, int dt_next, int want_dt,
                                                 int want_ledger) {
   __shared__ double s_m[4];
+  __shared__ double s_ts[4];
   __shared__ double s_l[4][5];
   __shared__ int s_stop;
   if (threadIdx.x == 0) s_stop = __atomic_load_n(&a.c.ctrl->status, __ATOMIC_RELAXED);
   __syncthreads();
   if (s_stop & FL_HARD) return;
-  double m = 1e300;
+  double m = 1e300, tsm = 1e300;
   double l[5] = {0, 0, 0, 0, 0};
+  const bool dyn_ts = a.g.drag_law && a.g.nd > 0;
   // fixed partition and order: deterministic sums
   // stage partials: [nparts][5] (gas, dust species); standalone CFL: [nparts]
   const int per = want_ledger ? 1 + a.g.nd : 1;
   for (int b = threadIdx.x; b < nparts; b += blockDim.x) {
+    if (dyn_ts) tsm = fmin(tsm, a.c.tsp[b]);
     if (want_dt)
       for (int s = 0; s < per; ++s) m = fmin(m, a.c.cflp[want_ledger ? (size_t)b * 5 + s : b]);
     if (want_ledger)
@@ -509,10 +529,12 @@ __global__ void __launch_bounds__(256) k_reduce(StageArgs a, int nparts, int dt_
       for (int s = 0; s < 5; ++s) l[s] += a.c.outp[(size_t)b * 5 + s];
   }
   m = wave_min(m);
+  tsm = wave_min(tsm);
 #pragma unroll
   for (int s = 0; s < 5; ++s) l[s] = wave_sum(l[s]);
   if ((threadIdx.x & 63) == 0) {
     s_m[threadIdx.x / 64] = m;
+    s_ts[threadIdx.x / 64] = tsm;
 #pragma unroll
     for (int s = 0; s < 5; ++s) s_l[threadIdx.x / 64][s] = l[s];
   }
@@ -527,9 +549,14 @@ __global__ void __launch_bounds__(256) k_reduce(StageArgs a, int nparts, int dt_
       for (int s = 0; s < 5; ++s)
         a.c.ctrl->outflow[s] = ((s_l[0][s] + s_l[1][s]) + (s_l[2][s] + s_l[3][s]));
     double dtn = a.c.dtlog[dt_next];
-    if (a.g.nd > 0 && dtn >= a.c.ctrl->min_ts) {
+    // stiffness: dt against the smallest stopping time (constant law: from the tables;
+    // law 1: over the cells of the state the step starts from)
+    const double tsmin = dyn_ts ? fmin(fmin(s_ts[0], s_ts[1]), fmin(s_ts[2], s_ts[3]))
+                                : a.c.ctrl->min_ts;
+    if (a.g.nd > 0 && dtn >= tsmin) {
       atomicOr(&a.c.ctrl->status, FL_STIFF);
-      atomicCAS(&a.c.ctrl->bad_step, -1, a.step + 1);
+      // dt_next 0: the first step of the call (a.step); else the step after a.step
+      atomicCAS(&a.c.ctrl->bad_step, -1, dt_next == 0 ? a.step : a.step + 1);
     }
   }
 }
@@ -653,7 +680,7 @@ __global__ void __launch_bounds__(256) k_tables_r(InitArgs a) {
   if (threadIdx.x == 0) {
     Ctrl* ct = reinterpret_cast<Ctrl*>(w + L.ctrl);
     double mts = 1e300;
-    for (int s = 0; s < c.n_dust; ++s)
+    for (int s = 0; s < c.n_dust && c.drag_law == 0; ++s)
       for (int i = 0; i < nr; ++i) {
         double rc = cell_r(c, i);
         mts = fmin(mts, c.stokes[s] / sqrt(c.GM / (rc * rc * rc)));

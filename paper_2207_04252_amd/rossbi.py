@@ -44,7 +44,9 @@ class rb_config(ctypes.Structure):
         ("vortex_sig_a", ctypes.c_double), ("noise_amp", ctypes.c_double),
         ("stokes", ctypes.c_double * 4), ("eps_dust", ctypes.c_double * 4),
         ("hd_over_h", ctypes.c_double * 4),
-        ("indirect", ctypes.c_int32), ("reserved", ctypes.c_int32),
+        ("indirect", ctypes.c_int32), ("drag_law", ctypes.c_int32),
+        ("grain_size", ctypes.c_double * 4), ("grain_density", ctypes.c_double * 4),
+        ("mfp_coef", ctypes.c_double),
     ]
 
 
@@ -142,6 +144,12 @@ def to_config(cfg: synth.Config, precision: int = RB_FP64) -> rb_config:
         c.eps_dust[q] = cfg.eps_dust[q]
         c.hd_over_h[q] = cfg.hd_over_h[q]
     c.indirect = int(cfg.indirect)
+    c.drag_law = int(cfg.drag_law)
+    if cfg.drag_law:
+        for q in range(cfg.n_dust):
+            c.grain_size[q] = cfg.grain_size[q]
+            c.grain_density[q] = cfg.grain_density[q]
+        c.mfp_coef = cfg.mfp_coef
     return c
 
 

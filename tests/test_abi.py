@@ -36,9 +36,29 @@ def test_library_exports_every_declared_symbol(lib):
 
 
 def test_struct_sizes_match_header_layout():
-    # rb_config: 8 int32 + 6 + 1 + 3 + 3 + 4 + 6 + 12 doubles
-    assert ctypes.sizeof(rossbi.rb_config) == 8 * 4 + (6 + 1 + 3 + 3 + 4 + 6 + 12) * 8 + 2 * 4
+    # rb_config: 8 int32 + 6 + 1 + 3 + 3 + 4 + 6 + 12 doubles, 2 int32, 9 doubles
+    assert ctypes.sizeof(rossbi.rb_config) == 8 * 4 + (6 + 1 + 3 + 3 + 4 + 6 + 12) * 8 + 2 * 4 + 9 * 8
     assert ctypes.sizeof(rossbi.rb_diag) == 8 + 8 + 4 + 4 + 8 + 8 + 8 + 4 + 4 + 5 * 8 + 5 * 8 + 8 + 8
+
+
+def test_struct_layout_matches_c_compiler(tmp_path):
+    """The header compiled by the host C compiler gives the binding's sizes and offsets."""
+    import os
+    import subprocess
+    inc = os.path.join(os.path.dirname(__file__), "..", "include")
+    fields = [f[0] for f in rossbi.rb_config._fields_]
+    src = tmp_path / "layout.c"
+    body = "".join(f'  printf("%zu\\n", offsetof(rb_config, {f}));\n' for f in fields)
+    src.write_text("#include <stddef.h>\n#include <stdio.h>\n#include \"rossbi_mi355x.h\"\n"
+                   "int main(void) {\n" + body +
+                   '  printf("%zu\\n%zu\\n", sizeof(rb_config), sizeof(rb_diag));\n  return 0;\n}\n')
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c11", "-I", inc, "-o", str(exe), str(src)], check=True)
+    got = [int(v) for v in subprocess.run([str(exe)], check=True, capture_output=True,
+                                          text=True).stdout.split()]
+    want = [getattr(rossbi.rb_config, f).offset for f in fields]
+    assert got[:-2] == want
+    assert got[-2:] == [ctypes.sizeof(rossbi.rb_config), ctypes.sizeof(rossbi.rb_diag)]
 
 
 @pytest.mark.parametrize("name", list(synth.CONFIGS))

@@ -284,8 +284,13 @@ def test_stiff_error(rb):
     cfg = synth.C3_BIFLUID.scaled(12, 64, 8).with_(stokes=(1e-4,))
     say("[stiff] " + cfg.name)
     sim = rb.Sim(cfg)
+    s0 = sim.fields()
     st, _ = sim.step(1)
     assert st == rb.RB_ESTIFF
+    # refused before the step: no step counted, no time advanced, state unchanged
+    d = sim.diagnostics()
+    assert d.step == 0 and d.t == 0.0 and d.first_bad_step == 0
+    assert np.array_equal(sim.fields(), s0)
 
 
 @pytest.mark.parametrize("cfg", [synth.C2_DISC, synth.C3_BIFLUID], ids=["gas_disc_full", "bifluid_full"])

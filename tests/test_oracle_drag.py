@@ -157,3 +157,16 @@ def test_stiffness_uses_cell_stopping_time(oracle_mod):
     st, _ = o.step(1, dt=0.5 * tmin)
     assert st == 0
     o.close()
+
+
+def test_workload_spans_both_regimes(oracle_mod):
+    """The Epstein-law disc of the parity tests holds cells of each regime for the middle
+    species."""
+    cfg = synth.epstein_grains(synth.C4_LARGE.scaled(96, 64, 16))
+    o = oracle_mod.Oracle(cfg, noise=synth.noise(cfg))
+    s = o.state()
+    rho = s[4]
+    rsw = 9.0 * cfg.mfp_coef / (4.0 * cfg.grain_size[1])
+    frac = float(np.mean(rho > rsw))
+    assert 0.05 < frac < 0.95, frac
+    o.close()
