@@ -90,7 +90,8 @@ def timed_rate(rossbi, torch, cfg, precision, steps, warmup):
     sim.close()
     return {"zone_updates_per_s": cfg.n_cells * steps / wall, "ms_per_step": 1e3 * wall / steps,
             "gas_kernel_ms": round(float(ms[0]) / max(int(nl[0]), 1), 4),
-            "dust_kernel_ms": round(float(ms[1]) / max(int(nl[1]), 1), 4) if nl[1] else None}
+            "dust_kernel_ms": round(float(ms[1]) / max(int(nl[1]), 1), 4) if nl[1] else None,
+            "other_kernels_ms_per_step": round(float(ms[2]) / steps, 4)}
 
 
 def precision_forms(rossbi, torch, steps):
@@ -108,6 +109,24 @@ def precision_forms(rossbi, torch, steps):
     out["fp32p_accuracy"] = ("one step from oracle states, relative per cell: density and "
                              "pressure <= 1e-5 everywhere (measured ~1e-10); dust density "
                              "<= 1e-5 off the midplane layers and on midplane two-cell sums")
+    return out
+
+
+def extensions(rossbi, torch, steps):
+    """Cost of the physics beyond the base step on the one-dust disc (FP64, CFL steps):
+    indirect gravity (two disc sums per stage) and the Epstein / Stokes drag law
+    (per-cell stopping times and stiffness partials), each against the base run."""
+    base = synth.C3_BIFLUID
+    runs = {"base": base, "indirect_gravity": base.with_(indirect=True),
+            "epstein_stokes_drag": synth.epstein_grains(base)}
+    out = {"workload": base.name, "steps": steps}
+    r0 = None
+    for name, cfg in runs.items():
+        log(f"extensions: {name}, {steps} steps")
+        r = timed_rate(rossbi, torch, cfg, rossbi.RB_FP64, steps, 3)
+        r0 = r0 or r
+        r["cost_vs_base"] = round(r["ms_per_step"] / r0["ms_per_step"], 4)
+        out[name] = r
     return out
 
 
@@ -186,6 +205,9 @@ def main():
                     help="skip the FP64 / FP32-perturbation comparison on the dust discs")
     ap.add_argument("--forms-steps", type=int, default=40)
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint cost measurement")
+    ap.add_argument("--no-extensions", action="store_true",
+                    help="skip the indirect-gravity and drag-law cost measurement")
+    ap.add_argument("--extensions-steps", type=int, default=40)
     ap.add_argument("--adjoint-steps", type=int, default=200)
     ap.add_argument("--calib", action="store_true",
                     help="first copy 256 MiB device to device 3 times (counter calibration)")
@@ -260,6 +282,8 @@ def main():
         out["precision_forms"] = precision_forms(rossbi, torch, args.forms_steps)
     if not args.no_adjoint:
         out["adjoint"] = adjoint_cost(rossbi, torch, args.adjoint_steps, 20)
+    if not args.no_extensions:
+        out["extensions"] = extensions(rossbi, torch, args.extensions_steps)
     if not args.no_cpu:
         log("cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(cfg, xi, args.cpu_seconds)
