@@ -54,6 +54,9 @@ class OrConfig(ctypes.Structure):
         ("drag_law", ctypes.c_int32), ("pad1", ctypes.c_int32),
         ("grain_size", ctypes.c_double * 4), ("grain_density", ctypes.c_double * 4),
         ("mfp_coef", ctypes.c_double),
+        ("bc_r", ctypes.c_int32), ("bc_z", ctypes.c_int32),
+        ("damp_r_in", ctypes.c_double), ("damp_r_out", ctypes.c_double),
+        ("damp_z", ctypes.c_double), ("damp_tau", ctypes.c_double),
     ]
 
 
@@ -95,6 +98,9 @@ def to_struct(cfg: synth.Config) -> OrConfig:
             s.grain_size[q] = cfg.grain_size[q]
             s.grain_density[q] = cfg.grain_density[q]
         s.mfp_coef = cfg.mfp_coef
+    s.bc_r, s.bc_z = int(getattr(cfg, "bc_r", 0)), int(getattr(cfg, "bc_z", 0))
+    s.damp_r_in, s.damp_r_out = cfg.damp_r_in, cfg.damp_r_out
+    s.damp_z, s.damp_tau = cfg.damp_z, cfg.damp_tau
     return s
 
 

@@ -33,6 +33,16 @@
  *   - the empty run evaluates the whole spatial operator once on the gas
  *     equilibrium, without dust, and is subtracted from the gas components in
  *     both stages;
+ *   - boundary conditions (Sect. 2.4 names them without formulas): bc_r 1 adds
+ *     wave-killing zones next to the radial boundaries and bc_z 2 sheared damped zones
+ *     next to the vertical ones, both relaxing the gas deviation from the stationary
+ *     flow to zero at the rate R / tau (R a quadratic ramp from 0 at the zone's edge to 1
+ *     at the boundary, tau = damp_tau orbital periods at the boundary radius, or at the
+ *     cell's radius for the vertical zones; the form of de Val-Borro et al. 2006); bc_z 1
+ *     is the outflow condition: z ghosts carry the boundary cell's gas deviation scaled
+ *     by the ratio of the stationary densities (zero gradient of E'/rho0, so that the
+ *     ghost keeps the boundary cell's relative perturbation) and repeat its dust
+ *     variables;
  *   - drag uses a constant Stokes number, t_s = St / Omega_K(r), or (drag_law 1) the
  *     Epstein / Stokes law of Sect. 2.9 with c_s the isothermal sound speed sqrt(p/rho)
  *     of the cell's gas (the c_s of App. A) and lambda = mfp_coef / rho_g.
@@ -60,6 +70,8 @@ typedef struct {
   double stokes[4], eps_dust[4], hd_over_h[4];
   int32_t drag_law, pad1;
   double grain_size[4], grain_density[4], mfp_coef;
+  int32_t bc_r, bc_z;
+  double damp_r_in, damp_r_out, damp_z, damp_tau;
 } OrConfig;
 
 typedef struct {
@@ -421,6 +433,11 @@ struct Sim {
     nr = c.nr; nth = c.nth; nz = c.nz; nd = c.n_dust;
     if (nr < 3 || nth < 1 || nz < 1 || nd < 0 || nd > 4) return false;
     if (c.gamma <= 1.0) return false;
+    if (c.bc_r < 0 || c.bc_r > 1 || c.bc_z < 0 || c.bc_z > 2) return false;
+    if ((c.bc_r == 1 || c.bc_z == 2) &&
+        (!(c.GM > 0.0) || !(c.damp_tau > 0.0) || !(c.damp_r_in > 1.0) ||
+         !(c.damp_r_out > 0.0 && c.damp_r_out < 1.0) || !(c.damp_z > 0.0 && c.damp_z < 1.0)))
+      return false;
     nf = 5 + 4 * nd;
     twod = (nz == 1);
     N = (size_t)nr * nth * nz;
@@ -593,6 +610,34 @@ struct Sim {
 
   double ghost_z(int k) const { return twod ? 0.0 : (k + 0.5 - 0.5 * nz) * dz; }
 
+  /* relaxation rate R / tau of the boundary damping zones at a cell centre (0 outside) */
+  double damp_rate(double r, double z) const {
+    const double two_pi = 6.283185307179586;
+    double rate = 0.0;
+    if (c.bc_r == 1) {
+      double ri = c.damp_r_in * c.r_in, ro = c.damp_r_out * c.r_out;
+      if (r < ri) {
+        double x = (ri - r) / (ri - c.r_in);
+        double tau = c.damp_tau * two_pi / std::sqrt(c.GM / (c.r_in * c.r_in * c.r_in));
+        rate += x * x / tau;
+      }
+      if (r > ro) {
+        double x = (r - ro) / (c.r_out - ro);
+        double tau = c.damp_tau * two_pi / std::sqrt(c.GM / (c.r_out * c.r_out * c.r_out));
+        rate += x * x / tau;
+      }
+    }
+    if (c.bc_z == 2 && !twod) {
+      double zd = c.damp_z * c.z_half, az = std::fabs(z);
+      if (az > zd) {
+        double x = (az - zd) / (c.z_half - zd);
+        double tau = c.damp_tau * two_pi / std::sqrt(c.GM / (r * r * r));
+        rate += x * x / tau;
+      }
+    }
+    return rate;
+  }
+
   /* Reconstructed variable of any cell, interior or ghost: E' for the gas, the whole
    * conservative variable for the dust.  Ghost cells (Sect. 2.4) hold the stationary
    * flow (gas E' = 0) and the initial dust layer; for the Sod annulus they keep the
@@ -600,6 +645,17 @@ struct Sim {
   T dev(int f, int k, int i, int j) const {
     bool ghost = i < 0 || i >= nr || k < 0 || k >= nz;
     if (!ghost) return Ep[f * N + idx(k, i, wrapi(j, nth))];
+    if (c.bc_z == 1 && (k < 0 || k >= nz) && i >= 0 && i < nr) {
+      const int kb = k < 0 ? 0 : nz - 1;
+      const T e = Ep[f * N + idx(kb, i, wrapi(j, nth))];
+      if (f >= 5) return e;
+      /* outflow: the boundary cell's gas deviation relative to the stationary density
+       * carried into the ghost (zero gradient of E'/rho0) */
+      double bg[24], bb[24];
+      background(rce(i), ghost_z(k), bg);
+      background(rce(i), zc[kb], bb);
+      return e * (bg[4] / bb[4]);
+    }
     if (f >= 5) {
       double b[24];
       background(rce(i), ghost_z(k), b);
@@ -624,7 +680,7 @@ struct Sim {
     double b[24];
     background(rce(i), ghost_z(k), b);
     for (int f = 0; f < 5; ++f) out[f] = b[f] + dev(f, k, i, j);
-    for (int f = 5; f < nf; ++f) out[f] = b[f];
+    for (int f = 5; f < nf; ++f) out[f] = dev(f, k, i, j);
   }
 
   const T* cur = nullptr; /* state whose operator is being evaluated */
@@ -891,6 +947,11 @@ struct Sim {
               S[o + 0] = S[o + 0] + rd * ar;
               S[o + 1] = S[o + 1] + rd * at;
             }
+          }
+          /* boundary damping zones: the gas deviation relaxes to the stationary flow */
+          if (c.bc_r == 1 || c.bc_z == 2) {
+            double kd = damp_rate(r, z);
+            for (int f = 0; f < 5; ++f) S[f] = S[f] - kd * Ep[f * N + id];
           }
           for (int f = 0; f < nfl; ++f) {
             T gv = Gc[f] + S[f] * V[i];

@@ -71,6 +71,18 @@ class Config:
     grain_size: Tuple[float, ...] = ()
     grain_density: Tuple[float, ...] = ()
     mfp_coef: float = 0.0
+    # boundary conditions (Sect. 2.4).  bc_r: 0 ghosts hold the stationary (sheared) flow;
+    # 1 adds wave-killing zones r < damp_r_in r_in and r > damp_r_out r_out.  bc_z: 0
+    # stationary ghosts; 1 outflow (ghosts repeat the boundary cell's deviation); 2 sheared
+    # damped zones |z| > damp_z z_half.  Damping relaxes the gas deviation at rate R / tau,
+    # R rising quadratically from 0 at the zone edge to 1 at the boundary, tau = damp_tau
+    # orbital periods (at the boundary radius; at the cell radius for the z zones).
+    bc_r: int = 0
+    bc_z: int = 0
+    damp_r_in: float = 1.25
+    damp_r_out: float = 0.84
+    damp_z: float = 0.8
+    damp_tau: float = 1.0
 
     @property
     def n_dust(self) -> int:
