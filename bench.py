@@ -114,11 +114,14 @@ def precision_forms(rossbi, torch, steps):
 
 def extensions(rossbi, torch, steps):
     """Cost of the physics beyond the base step on the one-dust disc (FP64, CFL steps):
-    indirect gravity (two disc sums per stage) and the Epstein / Stokes drag law
-    (per-cell stopping times and stiffness partials), each against the base run."""
+    indirect gravity (two disc sums per stage), the Epstein / Stokes drag law (per-cell
+    stopping times and stiffness partials), the boundary damping zones and the outflow
+    z ghosts, each against the base run."""
     base = synth.C3_BIFLUID
     runs = {"base": base, "indirect_gravity": base.with_(indirect=True),
-            "epstein_stokes_drag": synth.epstein_grains(base)}
+            "epstein_stokes_drag": synth.epstein_grains(base),
+            "damping_zones_r_z": base.with_(bc_r=1, bc_z=2),
+            "outflow_z": base.with_(bc_z=1)}
     out = {"workload": base.name, "steps": steps}
     r0 = None
     for name, cfg in runs.items():

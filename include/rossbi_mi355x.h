@@ -97,6 +97,18 @@ typedef struct {
    * rb_record.                                                                         */
   int32_t drag_law;
   double grain_size[4], grain_density[4], mfp_coef;
+  /* boundary conditions (Sect. 2.4; disc only).  bc_r 0: r ghosts hold the stationary
+   * sheared flow; 1: in addition, wave-killing zones r < damp_r_in r_in and
+   * r > damp_r_out r_out.  bc_z 0: z ghosts hold the stationary flow; 1: outflow, the
+   * two z ghosts carry the boundary cell's gas deviation scaled by the ratio of the
+   * stationary densities (zero gradient of E'/rho0) and repeat its dust variables; 2:
+   * sheared damped zones |z| > damp_z z_half.  A damping zone relaxes the gas deviation from the
+   * stationary flow at the rate R / tau added to the operator (V dE'/dt = ... - V R E'/tau),
+   * R = x^2 with x rising linearly from 0 at the zone edge to 1 at the boundary and
+   * tau = damp_tau orbital periods 2 pi / Omega_K at the boundary radius (radial zones)
+   * or at the cell radius (vertical zones).  Not with rb_record.                       */
+  int32_t bc_r, bc_z;
+  double damp_r_in, damp_r_out, damp_z, damp_tau;
 } rb_config;
 
 /* Caller-owned device buffers.  Sizes come from rb_query_sizes; pointers must be

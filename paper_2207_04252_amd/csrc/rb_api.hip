@@ -68,6 +68,12 @@ bool validate(const rb_config* c, std::string* why) {
         return bad("drag law 1 needs positive grain sizes and densities");
   }
   if (c->indirect && c->init_kind != RB_INIT_DISC) return bad("indirect gravity needs a disc");
+  if (c->bc_r < 0 || c->bc_r > 1 || c->bc_z < 0 || c->bc_z > 2) return bad("bc_r must be 0..1, bc_z 0..2");
+  if ((c->bc_r || c->bc_z) && c->init_kind != RB_INIT_DISC) return bad("boundary options need a disc");
+  if ((c->bc_r == 1 || c->bc_z == 2) &&
+      (!(c->damp_tau > 0.0) || !(c->damp_r_in > 1.0) || !(c->damp_r_out > 0.0 && c->damp_r_out < 1.0) ||
+       !(c->damp_z > 0.0 && c->damp_z < 1.0)))
+    return bad("damping zones need damp_tau > 0, damp_r_in > 1, 0 < damp_r_out < 1, 0 < damp_z < 1");
   for (int s = 0; s < c->n_dust; ++s)
     if ((c->drag_law == 0 && !(c->stokes[s] > 0.0)) || !(c->hd_over_h[s] > 0.0) ||
         !(c->eps_dust[s] >= 0.0))
@@ -128,6 +134,8 @@ Layout make_layout(const rb_config& c) {
   L.indab = take(2);
   L.nind = (int)std::min<size_t>((N + 255) / 256, 1024);
   L.indp = take((size_t)L.nind * 2);
+  L.damp = take(nz * nr);
+  L.ozr = take(4 * nr);
   L.dtlog = take(DTLOG + 2);
   L.cflp = take(std::max((size_t)L.nblocks * 5, (size_t)L.ncfl));
   L.outp = take((size_t)L.nblocks * 5);
@@ -148,6 +156,8 @@ Geo make_geo(const rb_config& c) {
   g.p32 = c.precision == RB_FP32_PERT;
   g.indirect = c.indirect != 0;
   g.drag_law = c.drag_law;
+  g.bc_z = c.nz > 1 ? c.bc_z : 0;
+  g.damp = c.bc_r == 1 || (c.bc_z == 2 && c.nz > 1);
   g.mfp = c.drag_law ? c.mfp_coef : 0.0;
   for (int s = 0; s < 4; ++s) {
     const bool on = s < c.n_dust;
@@ -169,6 +179,8 @@ StageArgs base_args(rb_ctx* x) {
   a.t.ghr = w + L.ghr; a.t.ghrf = w + L.ghrf; a.t.ghz = w + L.ghz; a.t.ghzf = w + L.ghzf;
   a.t.dsc = w + L.dsc;
   a.t.trig = w + L.trig; a.t.indw = w + L.indw; a.t.indab = w + L.indab;
+  a.t.damp = w + L.damp;
+  a.t.ozr = w + L.ozr;
   a.c.ctrl = reinterpret_cast<Ctrl*>(w + L.ctrl);
   a.c.dtlog = w + L.dtlog; a.c.cflp = w + L.cflp; a.c.outp = w + L.outp; a.c.r0w = w + L.r0;
   a.c.tsp = w + L.tsp;
@@ -646,6 +658,7 @@ rb_status rb_record(rb_ctx* x, int n, int ckpt_every, const rb_dt_policy* policy
   if (x->g.p32) return fail(x, RB_EINVAL, "the adjoint is FP64 only");
   if (x->g.indirect) return fail(x, RB_EINVAL, "the adjoint does not cover indirect gravity");
   if (x->g.drag_law) return fail(x, RB_EINVAL, "the adjoint covers the constant-Stokes drag only");
+  if (x->g.bc_z || x->g.damp) return fail(x, RB_EINVAL, "the adjoint covers the stationary ghosts only");
   const int k = std::min(ckpt_every, n);
   const AdjLayout A = adj_layout(x, n, k);
   if (ws_bytes < A.total * sizeof(double)) return fail(x, RB_EINVAL, "workspace too small");

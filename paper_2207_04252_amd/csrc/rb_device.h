@@ -619,14 +619,23 @@ __device__ __forceinline__ void st_cell(const StageArgs& a, void* st, int f, int
   }
 }
 
-template <bool P32>
+// EXT: the optional physics and boundary options (outflow ghosts here) may be active; the
+// base instantiation compiles them out.
+template <bool P32, bool EXT = false>
 __device__ __forceinline__ double fetch(const StageArgs& a, const void* st, int f, int k, int i,
                                         int j) {
   const Geo& g = a.g;
   if (k < 0 || k >= g.nz) {
+    int ii = min(max(i, 0), g.nr - 1);
     int side = k < 0 ? 0 : 1;
     int layer = min(k < 0 ? -1 - k : k - g.nz, 1);
-    int ii = min(max(i, 0), g.nr - 1);
+    if (EXT && g.bc_z == 1) {
+      // outflow: the boundary cell's dust variables, and its gas deviation carried at the
+      // same fraction of the stationary density
+      const int kb = k < 0 ? 0 : g.nz - 1;
+      const double v = ld_cell<P32>(a, st, f, kb, ii, ((size_t)kb * g.nr + ii) * g.nth + j);
+      return f < 5 ? v * a.t.ozr[(size_t)(side * 2 + layer) * g.nr + ii] : v;
+    }
     return a.t.ghz[((size_t)(side * 2 + layer) * g.nr + ii) * g.nf + f];
   }
   if (i < 0 || i >= g.nr) {
@@ -637,12 +646,13 @@ __device__ __forceinline__ double fetch(const StageArgs& a, const void* st, int 
   return ld_cell<P32>(a, st, f, k, i, ((size_t)k * g.nr + i) * g.nth + j);
 }
 
-// centre state used by the gas fallback: E0(centre) + E' for interior cells (scale 1),
-// the ghost's full state (scale 0) otherwise
+// centre state used by the gas fallback: E0(centre) + E' for interior cells and outflow
+// z ghosts (scale 1), the ghost's full state (scale 0) otherwise
+template <bool EXT = false>
 __device__ __forceinline__ const double* centre_ptr(const StageArgs& a, int k, int i, double& s) {
   const Geo& g = a.g;
   if (k < 0 || k >= g.nz) {
-    s = 0.0;
+    s = (EXT && g.bc_z == 1) ? 1.0 : 0.0;
     int ii = min(max(i, 0), g.nr - 1);
     return a.t.ghzf + ((size_t)(k < 0 ? 0 : 1) * g.nr + ii) * 5;
   }
@@ -684,8 +694,9 @@ __device__ __forceinline__ int wave_imax(int v) {
 // pressure p (Sect. 2.9).  Law 0: Omega_K / St.  Law 1: Epstein 1/t = rho c_s / (rho_s r_p)
 // with the isothermal c_s = sqrt(p / rho), i.e. sqrt(p rho) / (rho_s r_p); in the Stokes
 // regime (r_p > 9 lambda / 4, lambda = mfp / rho) the Epstein rate times 9 lambda / (4 r_p).
+template <bool EXT = true>
 __device__ __forceinline__ double inv_tstop(const Geo& g, int s, double omk, double rho, double p) {
-  if (g.drag_law == 0) return omk * g.inv_st[s];
+  if (!EXT || g.drag_law == 0) return omk * g.inv_st[s];
   const double ie = sqrt(p * rho) * g.inv_mp[s];
   const double x = g.rp94[s] * rho;
   return x <= g.mfp ? ie : ie * g.mfp / x;

@@ -46,7 +46,7 @@ struct Ctrl {
 // Offsets (in doubles) of the tables inside the work area.
 struct Layout {
   size_t ctrl, rt, ar, rco, rcell, zc, bgc, bgr, bgz, r0, grav, ghr, ghrf, ghz, ghzf;
-  size_t dsc, trig, indw, indab, indp, dtlog, cflp, outp, tsp, red, total;
+  size_t dsc, trig, indw, indab, indp, damp, ozr, dtlog, cflp, outp, tsp, red, total;
   int nind;      // blocks of the indirect-gravity sums
   int nblocks;   // stage-kernel blocks
   int ntj, nti, nkc, tk;
@@ -58,6 +58,8 @@ struct Geo {
   int p32;       // state stored as FP32 perturbation (gas) / scaled dust
   int indirect;  // indirect gravity of the displaced star
   int drag_law;  // 0 constant Stokes number, 1 Epstein / Stokes regimes
+  int bc_z;      // 0 stationary z ghosts, 1 outflow (ghosts repeat the boundary cell), 2 damped
+  int damp;      // boundary damping zones present (rate table)
   size_t N;
   double gamma, GM, cfl;
   double inv_st[4];
@@ -83,6 +85,8 @@ struct Tables {
   const double* trig;  // cos, sin of the theta cell centres [2][ntheta]
   const double* indw;  // V r / (r^2 + z^2)^(3/2) per (k, i) (indirect-gravity sums)
   const double* indab; // the indirect-gravity sums A, B of the current stage input
+  const double* damp;  // boundary-zone relaxation rate R / tau per (k, i), 0 outside
+  const double* ozr;   // outflow z ghosts: rho0(ghost) / rho0(boundary cell) [side][layer][i]
 };
 
 struct Ctl {

@@ -17,7 +17,7 @@ namespace rb {
 // groups interact only through the cell-local drag, which each kernel evaluates from
 // the other group's centre state of the same stage input.
 
-template <bool GAS, int ND, bool G75, bool P32>
+template <bool GAS, int ND, bool G75, bool P32, bool EXT>
 __global__ void __launch_bounds__(NT) k_march(StageArgs a, int species) {
   constexpr int NG = GAS ? 5 : 4;
   constexpr bool PG = GAS && P32;  // gas in the FP32 perturbation form
@@ -83,14 +83,14 @@ __global__ void __launch_bounds__(NT) k_march(StageArgs a, int species) {
     T e2[NG];
 #pragma unroll
     for (int f = 0; f < NG; ++f) {
-      e2[f] = (T)fetch<P32>(a, in, F0 + f, k0 - 2, ig, jw);
-      rm[f] = (T)fetch<P32>(a, in, F0 + f, k0 - 1, ig, jw);
-      r0[f] = (T)fetch<P32>(a, in, F0 + f, k0, ig, jw);
-      rp[f] = (T)fetch<P32>(a, in, F0 + f, k0 + 1, ig, jw);
+      e2[f] = (T)fetch<P32, EXT>(a, in, F0 + f, k0 - 2, ig, jw);
+      rm[f] = (T)fetch<P32, EXT>(a, in, F0 + f, k0 - 1, ig, jw);
+      r0[f] = (T)fetch<P32, EXT>(a, in, F0 + f, k0, ig, jw);
+      rp[f] = (T)fetch<P32, EXT>(a, in, F0 + f, k0 + 1, ig, jw);
     }
     double sB = 1.0, sC = 1.0;
-    const double* cB = GAS ? centre_ptr(a, k0 - 1, igc, sB) : nullptr;
-    const double* cC = GAS ? centre_ptr(a, k0, igc, sC) : nullptr;
+    const double* cB = GAS ? centre_ptr<EXT>(a, k0 - 1, igc, sB) : nullptr;
+    const double* cC = GAS ? centre_ptr<EXT>(a, k0, igc, sC) : nullptr;
     const double* bgf = a.t.bgz + ((size_t)k0 * g.nr + igc) * 5;
     face(DZ(), e2, rm, r0, rp, nullptr, nullptr, bgf, cB, sB, cC, sC, fzlo);
     if (a.second && k0 == 0 && act) {
@@ -101,7 +101,7 @@ __global__ void __launch_bounds__(NT) k_march(StageArgs a, int species) {
   } else {
 #pragma unroll
     for (int f = 0; f < NG; ++f) {
-      r0[f] = (T)fetch<P32>(a, in, F0 + f, 0, ig, jw);
+      r0[f] = (T)fetch<P32, EXT>(a, in, F0 + f, 0, ig, jw);
       rm[f] = T(0); rp[f] = T(0); rn[f] = T(0); fzlo[f] = T(0); fzhi[f] = T(0);
     }
   }
@@ -109,7 +109,7 @@ __global__ void __launch_bounds__(NT) k_march(StageArgs a, int species) {
   for (int k = k0; k < k1; ++k) {
     if (!twod) {
 #pragma unroll
-      for (int f = 0; f < NG; ++f) rn[f] = (T)fetch<P32>(a, in, F0 + f, k + 2, ig, jw);
+      for (int f = 0; f < NG; ++f) rn[f] = (T)fetch<P32, EXT>(a, in, F0 + f, k + 2, ig, jw);
     }
     // ---- stage the plane (with halo) in LDS
 #pragma unroll
@@ -120,7 +120,7 @@ __global__ void __launch_bounds__(NT) k_march(StageArgs a, int species) {
       int ii = i0 + rr - 2;
       int jj = (j0 + cc - 2 + g.nth) % g.nth;
 #pragma unroll
-      for (int f = 0; f < NG; ++f) s_pl[f][rr][cc] = (T)fetch<P32>(a, in, F0 + f, k, ii, jj);
+      for (int f = 0; f < NG; ++f) s_pl[f][rr][cc] = (T)fetch<P32, EXT>(a, in, F0 + f, k, ii, jj);
     }
     __syncthreads();
     // ---- theta face j+1/2 and r face i+1/2 of this cell
@@ -146,8 +146,8 @@ __global__ void __launch_bounds__(NT) k_march(StageArgs a, int species) {
         const int ifc = min(ig + 1, g.nr);
         const double* bgf = a.t.bgr + ((size_t)k * (g.nr + 1) + ifc) * 5;
         double sB = 1.0, sC = 1.0;
-        const double* cB = GAS ? centre_ptr(a, k, min(ig, g.nr), sB) : nullptr;
-        const double* cC = GAS ? centre_ptr(a, k, min(ig + 1, g.nr), sC) : nullptr;
+        const double* cB = GAS ? centre_ptr<EXT>(a, k, min(ig, g.nr), sB) : nullptr;
+        const double* cC = GAS ? centre_ptr<EXT>(a, k, min(ig + 1, g.nr), sC) : nullptr;
         face(DR(), eA, eB, eC, eD, rco_ptr(a, ig), rco_ptr(a, ig + 1), bgf, cB, sB, cC, sC, F);
         if (a.second && act && ig == g.nr - 1) {
           double fm = (double)F[NG - 1];
@@ -170,8 +170,8 @@ __global__ void __launch_bounds__(NT) k_march(StageArgs a, int species) {
       }
       const double* bgf = a.t.bgr + ((size_t)k * (g.nr + 1) + i0) * 5;
       double sB = 1.0, sC = 1.0;
-      const double* cB = GAS ? centre_ptr(a, k, i0 - 1, sB) : nullptr;
-      const double* cC = GAS ? centre_ptr(a, k, i0, sC) : nullptr;
+      const double* cB = GAS ? centre_ptr<EXT>(a, k, i0 - 1, sB) : nullptr;
+      const double* cC = GAS ? centre_ptr<EXT>(a, k, i0, sC) : nullptr;
       face(DR(), eA, eB, eC, eD, rco_ptr(a, i0 - 1), rco_ptr(a, i0), bgf, cB, sB, cC, sC, F);
 #pragma unroll
       for (int f = 0; f < NG; ++f) s_fr[f][0][col] = F[f];
@@ -197,8 +197,8 @@ __global__ void __launch_bounds__(NT) k_march(StageArgs a, int species) {
     // ---- z face k+1/2 from the register ring
     if (!twod) {
       double sB = 1.0, sC = 1.0;
-      const double* cB = GAS ? centre_ptr(a, k, igc, sB) : nullptr;
-      const double* cC = GAS ? centre_ptr(a, k + 1, igc, sC) : nullptr;
+      const double* cB = GAS ? centre_ptr<EXT>(a, k, igc, sB) : nullptr;
+      const double* cC = GAS ? centre_ptr<EXT>(a, k + 1, igc, sC) : nullptr;
       const double* bgf = a.t.bgz + ((size_t)(k + 1) * g.nr + igc) * 5;
       face(DZ(), rm, r0, rp, rn, nullptr, nullptr, bgf, cB, sB, cC, sC, fzhi);
       if (a.second && act && k == g.nz - 1) {
@@ -242,7 +242,7 @@ __global__ void __launch_bounds__(NT) k_march(StageArgs a, int species) {
         for (int f = 0; f < 5; ++f) q[f] = bgc[f] + (double)r0[f];
         const double inv = 1.0 / q[4];
         const double u = q[0] * inv, v = q[1] * inv, w2 = q[2] * inv;
-        const double pq = g.drag_law ? gc.gm1 * (q[3] - 0.5 * (q[0] * u + q[1] * v + q[2] * w2)) : 0.0;
+        const double pq = (EXT && g.drag_law) ? gc.gm1 * (q[3] - 0.5 * (q[0] * u + q[1] * v + q[2] * w2)) : 0.0;
         double dx = 0.0, dy = 0.0, dzz = 0.0;
 #pragma unroll
         for (int s2 = 0; s2 < ND; ++s2) {
@@ -255,7 +255,7 @@ __global__ void __launch_bounds__(NT) k_march(StageArgs a, int species) {
             vd = ld_cell<P32>(a, in, o + 1, k, igc, cellw) * id;
             wd = ld_cell<P32>(a, in, o + 2, k, igc, cellw) * id;
           }
-          const double its = inv_tstop(g, s2, omk, q[4], pq);
+          const double its = inv_tstop<EXT>(g, s2, omk, q[4], pq);
           dx += rd * (ud - u) * its;
           dy += rd * (vd - v) * its;
           dzz += rd * (wd - w2) * its;
@@ -290,7 +290,7 @@ __global__ void __launch_bounds__(NT) k_march(StageArgs a, int species) {
             vd = ld_cell<P32>(a, in, o + 1, k, igc, cellw) * id;
             wd = ld_cell<P32>(a, in, o + 2, k, igc, cellw) * id;
           }
-          const double its = inv_tstop(g, s2, omk, q[4], p);
+          const double its = inv_tstop<EXT>(g, s2, omk, q[4], p);
           dx += rd * (ud - u) * its;
           dy += rd * (vd - v) * its;
           dzz += rd * (wd - w) * its;
@@ -314,8 +314,8 @@ __global__ void __launch_bounds__(NT) k_march(StageArgs a, int species) {
         for (int f = 0; f < 5; ++f) q[f] = bgc[f] + ld_cell<P32>(a, in, f, k, igc, cellw);
         const double inv = 1.0 / q[4];
         const double u = q[0] * inv, v = q[1] * inv, w = q[2] * inv;
-        const double pq = g.drag_law ? gc.gm1 * (q[3] - 0.5 * (q[0] * u + q[1] * v + q[2] * w)) : 0.0;
-        const double its = inv_tstop(g, species, omk, q[4], pq);
+        const double pq = (EXT && g.drag_law) ? gc.gm1 * (q[3] - 0.5 * (q[0] * u + q[1] * v + q[2] * w)) : 0.0;
+        const double its = inv_tstop<EXT>(g, species, omk, q[4], pq);
         fx = rd * (ud - u) * its;
         fy = rd * (vd - v) * its;
         fz = rd * (wd - w) * its;
@@ -326,7 +326,7 @@ __global__ void __launch_bounds__(NT) k_march(StageArgs a, int species) {
       S[3] = 0.0;
     }
     // indirect gravity (Sect. 2.10): minus the star's acceleration by the disc
-    if (g.indirect && a.mode != MODE_RESID) {
+    if (EXT && g.indirect && a.mode != MODE_RESID) {
       const double A = a.t.indab[0], B = a.t.indab[1];
       const double cs = a.t.trig[jw], sn = a.t.trig[g.nth + jw];
       const double ar = -g.GM * (A * cs + B * sn), at = -g.GM * (B * cs - A * sn);
@@ -340,6 +340,12 @@ __global__ void __launch_bounds__(NT) k_march(StageArgs a, int species) {
         S[0] += r0[3] * ar;
         S[1] += r0[3] * at;
       }
+    }
+    // boundary damping zones (Sect. 2.4): the gas deviation relaxes to the stationary flow
+    if (EXT && GAS && g.damp) {
+      const T kd = (T)a.t.damp[(size_t)k * g.nr + igc];
+#pragma unroll
+      for (int f = 0; f < NG; ++f) S[f] -= kd * r0[f];
     }
     T Gt[NG];
 #pragma unroll
@@ -395,9 +401,9 @@ __global__ void __launch_bounds__(NT) k_march(StageArgs a, int species) {
         } else if (a.second) {
           double spd = sqrt(un * un + vn * vn + wn * wn) + sqrt(gc.g * pn * in2);
           dtmin = fmin(dtmin, g.cfl * Vc / (spd * maxA));
-          if (g.drag_law) {
+          if (EXT && g.drag_law) {
 #pragma unroll
-            for (int s2 = 0; s2 < ND; ++s2) tsmin = fmin(tsmin, 1.0 / inv_tstop(g, s2, omk, qn[4], pn));
+            for (int s2 = 0; s2 < ND; ++s2) tsmin = fmin(tsmin, 1.0 / inv_tstop<EXT>(g, s2, omk, qn[4], pn));
           }
         }
       } else if (a.second && nvd[3] > 0.0) {
@@ -428,7 +434,7 @@ __global__ void __launch_bounds__(NT) k_march(StageArgs a, int species) {
   if (a.second && a.mode == MODE_UPDATE) {
     double m = wave_min(dtmin);
     double ls = wave_sum(ledger);
-    double tm = (GAS && ND > 0) ? wave_min(tsmin) : 1e300;
+    double tm = (EXT && GAS && ND > 0) ? wave_min(tsmin) : 1e300;
     if (ln == 0) { s_red[wv][0] = m; s_red[wv][1] = ls; s_red[wv][2] = tm; }
     __syncthreads();
     if (tid == 0) {
@@ -440,7 +446,7 @@ __global__ void __launch_bounds__(NT) k_march(StageArgs a, int species) {
       }
       a.c.cflp[(size_t)blockIdx.x * 5 + slot] = mm;
       a.c.outp[(size_t)blockIdx.x * 5 + slot] = lsum;
-      if (GAS && g.drag_law) a.c.tsp[blockIdx.x] = tmm;
+      if (EXT && GAS && g.drag_law) a.c.tsp[blockIdx.x] = tmm;
     }
   }
 }
@@ -709,6 +715,28 @@ __global__ void __launch_bounds__(256) k_tables_2d(InitArgs a) {
       const double V = 0.5 * (rp * rp - rm * rm) * (2.0 * M_PI / c.ntheta) * dz;
       const double s2 = rc * rc + zc * zc;
       w[L.indw + (size_t)kk * nr + ii] = V * rc / (s2 * sqrt(s2));
+      // boundary damping zones: rate R / tau, R the squared fraction of the way from the
+      // zone edge to the boundary, tau = damp_tau orbital periods
+      double rate = 0.0;
+      if (c.bc_r == 1) {
+        const double e_in = c.damp_r_in * c.r_in, e_out = c.damp_r_out * c.r_out;
+        if (rc < e_in) {
+          const double x = (e_in - rc) / (e_in - c.r_in);
+          rate += x * x * sqrt(c.GM / (c.r_in * c.r_in * c.r_in)) / (2.0 * M_PI * c.damp_tau);
+        }
+        if (rc > e_out) {
+          const double x = (rc - e_out) / (c.r_out - e_out);
+          rate += x * x * sqrt(c.GM / (c.r_out * c.r_out * c.r_out)) / (2.0 * M_PI * c.damp_tau);
+        }
+      }
+      if (c.bc_z == 2 && !twod) {
+        const double e_z = c.damp_z * c.z_half, az = fabs(zc);
+        if (az > e_z) {
+          const double x = (az - e_z) / (c.z_half - e_z);
+          rate += x * x * sqrt(c.GM / (rc * rc * rc)) / (2.0 * M_PI * c.damp_tau);
+        }
+      }
+      w[L.damp + (size_t)kk * nr + ii] = rate;
     }
     if (kin && iin) {
       const double r = cell_r(c, ii);
@@ -752,6 +780,10 @@ __global__ void __launch_bounds__(256) k_tables_2d(InitArgs a) {
         ge[f] = (f < 5 && c.init_kind == RB_INIT_DISC) ? 0.0 : q[f];
       if (layer == 0)
         for (int f = 0; f < 5; ++f) w[L.ghzf + ((size_t)side * nr + ii) * 5 + f] = q[f];
+      // outflow ghosts: stationary density of the ghost over that of the boundary cell
+      const double rho_g = q[4];
+      background_full(a, cell_r(c, ii), (side == 0 ? 0.5 - 0.5 * nz : nz - 0.5 - 0.5 * nz) * dz, q);
+      w[L.ozr + (size_t)(side * 2 + layer) * nr + ii] = rho_g / q[4];
     }
   }
 }
@@ -995,16 +1027,27 @@ hipError_t launch_init_state(const InitArgs& a, hipStream_t s) {
   return hipGetLastError();
 }
 
-template <int ND, bool P32>
-static void group_nd2(const StageArgs& a, int blocks, int group, hipStream_t s) {
+template <int ND, bool P32, bool EXT>
+static void group_nd3(const StageArgs& a, int blocks, int group, hipStream_t s) {
   if (group == 0) {
     if (a.g.gamma == 1.4)
-      hipLaunchKernelGGL((k_march<true, ND, true, P32>), dim3(blocks), dim3(NT), 0, s, a, 0);
+      hipLaunchKernelGGL((k_march<true, ND, true, P32, EXT>), dim3(blocks), dim3(NT), 0, s, a, 0);
     else
-      hipLaunchKernelGGL((k_march<true, ND, false, P32>), dim3(blocks), dim3(NT), 0, s, a, 0);
+      hipLaunchKernelGGL((k_march<true, ND, false, P32, EXT>), dim3(blocks), dim3(NT), 0, s, a, 0);
   } else {
-    hipLaunchKernelGGL((k_march<false, ND, true, P32>), dim3(blocks), dim3(NT), 0, s, a, group - 1);
+    hipLaunchKernelGGL((k_march<false, ND, true, P32, EXT>), dim3(blocks), dim3(NT), 0, s, a,
+                       group - 1);
   }
+}
+
+// the optional physics (indirect gravity, drag law 1) and boundary options (damping zones,
+// outflow ghosts) run in their own instantiation; the base one compiles them out
+static bool uses_ext(const Geo& g) { return g.indirect || g.damp || g.bc_z == 1 || g.drag_law; }
+
+template <int ND, bool P32>
+static void group_nd2(const StageArgs& a, int blocks, int group, hipStream_t s) {
+  if (uses_ext(a.g)) group_nd3<ND, P32, true>(a, blocks, group, s);
+  else group_nd3<ND, P32, false>(a, blocks, group, s);
 }
 
 template <int ND>

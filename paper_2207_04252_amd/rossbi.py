@@ -47,6 +47,9 @@ class rb_config(ctypes.Structure):
         ("indirect", ctypes.c_int32), ("drag_law", ctypes.c_int32),
         ("grain_size", ctypes.c_double * 4), ("grain_density", ctypes.c_double * 4),
         ("mfp_coef", ctypes.c_double),
+        ("bc_r", ctypes.c_int32), ("bc_z", ctypes.c_int32),
+        ("damp_r_in", ctypes.c_double), ("damp_r_out", ctypes.c_double),
+        ("damp_z", ctypes.c_double), ("damp_tau", ctypes.c_double),
     ]
 
 
@@ -150,6 +153,9 @@ def to_config(cfg: synth.Config, precision: int = RB_FP64) -> rb_config:
             c.grain_size[q] = cfg.grain_size[q]
             c.grain_density[q] = cfg.grain_density[q]
         c.mfp_coef = cfg.mfp_coef
+    c.bc_r, c.bc_z = int(cfg.bc_r), int(cfg.bc_z)
+    c.damp_r_in, c.damp_r_out, c.damp_z, c.damp_tau = (cfg.damp_r_in, cfg.damp_r_out,
+                                                       cfg.damp_z, cfg.damp_tau)
     return c
 
 
