@@ -14,11 +14,23 @@ namespace rb {
 // ------------------------------------------------------------------------------------
 // small helpers
 
+// minmod of three: when all three share a sign, the one of smallest magnitude, else zero.
+// Branch-free: the sign test on the sign bits, the magnitude from two minima (a zero
+// argument gives a zero magnitude, so only the sign of that zero can differ).
+__device__ __forceinline__ bool same_sign3(double x, double y, double z) {
+  const unsigned bx = (unsigned)(__double_as_longlong(x) >> 32);
+  const unsigned by = (unsigned)(__double_as_longlong(y) >> 32);
+  const unsigned bz = (unsigned)(__double_as_longlong(z) >> 32);
+  return (int)((bx ^ by) | (bx ^ bz)) >= 0;
+}
+__device__ __forceinline__ bool same_sign3(float x, float y, float z) {
+  const unsigned bx = __float_as_uint(x), by = __float_as_uint(y), bz = __float_as_uint(z);
+  return (int)((bx ^ by) | (bx ^ bz)) >= 0;
+}
 template <class T>
 __device__ __forceinline__ T minmod3(T x, T y, T z) {
-  if (x > T(0) && y > T(0) && z > T(0)) return fmin(x, fmin(y, z));
-  if (x < T(0) && y < T(0) && z < T(0)) return fmax(x, fmax(y, z));
-  return T(0);
+  const T m = fmin(fabs(x), fmin(fabs(y), fabs(z)));
+  return same_sign3(x, y, z) ? copysign(m, x) : T(0);
 }
 
 // Uniform direction (index coordinates): the three-point parabola gives the upper-face

@@ -32,6 +32,12 @@ __global__ void __launch_bounds__(NT) k_march(StageArgs a, int species) {
   __shared__ T s_ft[NG][TI][TJ + 1];
   __shared__ T s_fr[NG][TI + 1][TJ];
   __shared__ double s_red[NT / 64][3];
+  // FP64 gas: per-thread slots (no sharing) for the column's cell below the current plane
+  // and the flux of the z face below, kept in LDS between their uses (without them the
+  // face solves spill registers); the other kernels keep both in registers
+  constexpr bool LR = GAS && !P32;
+  __shared__ T s_rm[LR ? NG : 1][LR ? NT : 1];
+  __shared__ T s_fz[LR ? NG : 1][LR ? NT : 1];
 
   const Geo& g = a.g;
   const GasC gc = gas_consts(g.gamma);
@@ -78,6 +84,7 @@ __global__ void __launch_bounds__(NT) k_march(StageArgs a, int species) {
 
   // z ring of the thread's column: e_{k-1}, e_k, e_{k+1}, e_{k+2}; fluxes below/above k
   T rm[NG], r0[NG], rp[NG], rn[NG], fzlo[NG], fzhi[NG];
+  const int tslot = threadIdx.x;
   const bool twod = g.twod != 0;
   if (!twod) {
     T e2[NG];
@@ -97,6 +104,10 @@ __global__ void __launch_bounds__(NT) k_march(StageArgs a, int species) {
       double fm = (double)fzlo[NG - 1];
       if (PG) fm += bgf[2];  // background normal mass flux rho0 w0
       ledger -= Az * fm;
+    }
+    if constexpr (LR) {
+#pragma unroll
+      for (int f = 0; f < NG; ++f) { s_rm[f][tslot] = rm[f]; s_fz[f][tslot] = fzlo[f]; }
     }
   } else {
 #pragma unroll
@@ -196,6 +207,10 @@ __global__ void __launch_bounds__(NT) k_march(StageArgs a, int species) {
     }
     // ---- z face k+1/2 from the register ring
     if (!twod) {
+      if constexpr (LR) {
+#pragma unroll
+        for (int f = 0; f < NG; ++f) rm[f] = s_rm[f][tslot];
+      }
       double sB = 1.0, sC = 1.0;
       const double* cB = GAS ? centre_ptr<EXT>(a, k, igc, sB) : nullptr;
       const double* cC = GAS ? centre_ptr<EXT>(a, k + 1, igc, sC) : nullptr;
@@ -214,7 +229,7 @@ __global__ void __launch_bounds__(NT) k_march(StageArgs a, int species) {
     for (int f = 0; f < NG; ++f) {
       T dr = T(Arhi) * s_fr[f][ti + 1][tj] - T(Arlo) * s_fr[f][ti][tj];
       T dth = T(Ath) * (s_ft[f][ti][tj + 1] - s_ft[f][ti][tj]);
-      T dz = twod ? T(0) : T(Az) * (fzhi[f] - fzlo[f]);
+      T dz = twod ? T(0) : T(Az) * (fzhi[f] - (LR ? s_fz[f][tslot] : fzlo[f]));
       Gd[f] = -((dr + dth) + dz);
     }
     const size_t cell = ((size_t)k * g.nr + ig) * g.nth + jg;
@@ -416,7 +431,12 @@ __global__ void __launch_bounds__(NT) k_march(StageArgs a, int species) {
     // ---- shift the ring
 #pragma unroll
     for (int f = 0; f < NG; ++f) {
-      rm[f] = r0[f]; r0[f] = rp[f]; rp[f] = rn[f]; fzlo[f] = fzhi[f];
+      if constexpr (LR) {
+        s_rm[f][tslot] = r0[f]; s_fz[f][tslot] = fzhi[f];
+      } else {
+        rm[f] = r0[f]; fzlo[f] = fzhi[f];
+      }
+      r0[f] = rp[f]; rp[f] = rn[f];
     }
   }
 
