@@ -100,10 +100,18 @@ Layout make_layout(const rb_config& c) {
     if (env && std::atoi(env) > 0) {
       tk = std::atoi(env);
     } else {
-      const int cand[4] = {16, 8, 4, 2};
-      for (int q = 0; q < 4; ++q) {
-        size_t blocks = (size_t)L.ntj * L.nti * ((nz + cand[q] - 1) / cand[q]);
-        if (blocks >= 512 || cand[q] == 2) { tk = cand[q]; break; }
+      // One 512-thread workgroup fills a CU (256 VGPRs: two waves per SIMD), so a launch
+      // runs in ceil(blocks / 256) rounds on the 256 CUs of an MI355X; a block marches tk
+      // planes plus about 1.5 planes of set-up (initial ring, first z face).  Take the
+      // chunk length with the fewest plane-times.
+      const size_t tiles = (size_t)L.ntj * L.nti;
+      const int cand[7] = {128, 64, 32, 16, 8, 4, 2};
+      double best = 1e300;
+      for (int q = 0; q < 7; ++q) {
+        const size_t c = std::min<size_t>(cand[q], nz);
+        const size_t blocks = tiles * ((nz + c - 1) / c);
+        const double t = (double)((blocks + 255) / 256) * ((double)c + 1.5);
+        if (t < best) { best = t; tk = (int)c; }
       }
     }
     L.tk = (int)std::min<size_t>(tk, nz);
