@@ -61,16 +61,17 @@ __device__ __forceinline__ T inc_lo_c(T em, T e0, T ep, const double* co) {
                     T(co[RC_LMP]) * dp);
 }
 
-// x^(-1/7) for x > 0: FP32 hardware log2/exp2 seed, then Newton on z^-7 = x written as
-// z <- z + (z/7)(1 - x z^7) (quadratic convergence, three steps reach FP64 accuracy;
-// x = 1 is a fixed point).
+// x^(-1/7) for x > 0: FP32 hardware log2/exp2 seed (relative error ~1e-7 for x in the
+// clamped range), then Newton on z^-7 = x written as z <- z + (z/7)(1 - x z^7), whose error
+// goes e -> 4 e^2: two steps reach FP64 rounding (4 (4e-14)^2 ~ 1e-26); x = 1 is a fixed
+// point.
 __device__ __forceinline__ double inv_root7(double x) {
   if (x == 1.0) return 1.0;
   float xf = fminf(fmaxf((float)x, 1e-30f), 1e30f);
   double z = (double)__builtin_amdgcn_exp2f(-0.142857142857142857f * __builtin_amdgcn_logf(xf));
   const double k7 = 1.0 / 7.0;
 #pragma unroll
-  for (int it = 0; it < 3; ++it) {
+  for (int it = 0; it < 2; ++it) {
     double z2 = z * z;
     double z3 = z2 * z;
     double z7 = z3 * z3 * z;
@@ -89,8 +90,18 @@ __device__ __forceinline__ double frcp(double x) {
   return fma(r, e, r);
 }
 
+// 1/sqrt(x) for normal positive x: hardware estimate and two Newton steps
+// r <- r (3/2 - x r^2 / 2) (error e -> 3/2 e^2; within an ulp or two of the rounded value).
+__device__ __forceinline__ double frsq(double x) {
+  double r = __builtin_amdgcn_rsq(x);
+  const double h = 0.5 * x;
+  r = r * fma(-h * r, r, 1.5);
+  r = r * fma(-h * r, r, 1.5);
+  return r;
+}
+
 struct GasC {
-  double g, gm1, inv_gm1, g2m1, gm1_2g, gp1_2g, kshock, a2, half_gm1, inv_g, inv_gp1_2g;
+  double g, gm1, inv_gm1, g2m1, gm1_2g, gp1_2g, kshock, a2, half_gm1, inv_g, inv_gp1_2g, inv_a2;
 };
 
 __device__ __forceinline__ GasC gas_consts(double g) {
@@ -106,6 +117,7 @@ __device__ __forceinline__ GasC gas_consts(double g) {
   c.half_gm1 = 0.5 * (g - 1.0);
   c.inv_g = 1.0 / g;
   c.inv_gp1_2g = (2.0 * g) / (g + 1.0);
+  c.inv_a2 = 0.5 * (g + 1.0);
   return c;
 }
 
@@ -144,17 +156,19 @@ __device__ __forceinline__ double ipow_fan_p(double ratio, const GasC& c) {
 // Per-side constants of the pressure function: A = 2/((g+1) rho), B = (g-1)/(g+1) p,
 // 1/p and 1/(rho c).
 struct Side {
-  double r, u, p, c, A, B, ip, irc;
+  double r, u, p, c, A, B, ip, irc, iA;
 };
 
+// c and 1/c of the side come in as c2 * rs and rs, rs = 1/sqrt(c2)
 __device__ __forceinline__ Side make_side(double r, double ir, double u, double p, double c,
-                                          const GasC& g) {
+                                          double rs, const GasC& g) {
   Side s;
   s.r = r; s.u = u; s.p = p; s.c = c;
   s.A = g.a2 * ir;
   s.B = g.kshock * p;
   s.ip = frcp(p);
-  s.irc = ir * frcp(c);
+  s.irc = ir * rs;
+  s.iA = r * g.inv_a2;
   return s;
 }
 
@@ -162,8 +176,9 @@ template <bool G75>
 __device__ __forceinline__ void pfun(double p, const Side& K, const GasC& c, double& f,
                                      double& df) {
   if (p > K.p) {
-    double ipb = frcp(p + K.B);
-    double q = sqrt(K.A * ipb);
+    // q = sqrt(A / (p + B)) = 1/sqrt((p + B)/A) and 1/(p + B) = q^2 / A
+    const double q = frsq((p + K.B) * K.iA);
+    const double ipb = q * q * K.iA;
     f = (p - K.p) * q;
     df = q * (1.0 - 0.5 * (p - K.p) * ipb);
   } else {
@@ -257,8 +272,9 @@ __device__ void gas_riemann(const GasC& c, double rL, double irL, double uL, dou
       }
     }
   }
-  const double cL = sqrt(c2L);
-  const double cR = sqrt(c2R);
+  const double rsL = frsq(c2L), rsR = frsq(c2R);
+  const double cL = c2L * rsL;
+  const double cR = c2R * rsR;
   double rho, un, t1, t2, p;
   if (c.g2m1 * (cL + cR) <= du) {
     // vacuum between two rarefactions
@@ -280,8 +296,8 @@ __device__ void gas_riemann(const GasC& c, double rL, double irL, double uL, dou
     } else { rho = rR; un = uR; t1 = aR; t2 = bR; p = pR; br = GR_RIGHT; }
     if constexpr (REC) rec->branch = br;
   } else {
-    const Side L = make_side(rL, irL, uL, pL, cL, c);
-    const Side R = make_side(rR, irR, uR, pR, cR, c);
+    const Side L = make_side(rL, irL, uL, pL, cL, rsL, c);
+    const Side R = make_side(rR, irR, uR, pR, cR, rsR, c);
     double ppv = 0.5 * (pL + pR) - 0.125 * du * (rL + rR) * (cL + cR);
     double ps = fmax(ppv, 1e-8 * fmin(pL, pR));
     int it = 0;
