@@ -137,6 +137,7 @@ Layout make_layout(const rb_config& c) {
   L.ghz = take(4 * nr * nf);
   L.ghzf = take(2 * nr * 5);
   L.dsc = take(std::max<size_t>(1, (size_t)c.n_dust * nz * nr));
+  L.idsc = take(std::max<size_t>(1, (size_t)c.n_dust * nz * nr));
   L.trig = take(2 * nth);
   L.indw = take(nz * nr);
   L.indab = take(2);
@@ -186,6 +187,7 @@ StageArgs base_args(rb_ctx* x) {
   a.t.bgr = w + L.bgr; a.t.bgz = w + L.bgz; a.t.r0 = w + L.r0; a.t.grav = w + L.grav;
   a.t.ghr = w + L.ghr; a.t.ghrf = w + L.ghrf; a.t.ghz = w + L.ghz; a.t.ghzf = w + L.ghzf;
   a.t.dsc = w + L.dsc;
+  a.t.idsc = w + L.idsc;
   a.t.trig = w + L.trig; a.t.indw = w + L.indw; a.t.indab = w + L.indab;
   a.t.damp = w + L.damp;
   a.t.ozr = w + L.ozr;

@@ -640,7 +640,7 @@ __device__ __forceinline__ void st_cell(const StageArgs& a, void* st, int f, int
     if (f < 5) { ((float*)st)[(size_t)f * g.N + cell] = (float)v; return; }
     const int sp = (f - 5) >> 2, c = (f - 5) & 3;
     if (c == 3) { ((double*)st)[p32_f64_base(g) + (size_t)sp * g.N + cell] = v; return; }
-    v /= a.t.dsc[((size_t)sp * g.nz + k) * g.nr + i];
+    v *= a.t.idsc[((size_t)sp * g.nz + k) * g.nr + i];
     ((float*)st)[(size_t)(5 + 3 * sp + c) * g.N + cell] = (float)v;
   } else {
     ((double*)st)[(size_t)f * g.N + cell] = v;

@@ -770,6 +770,7 @@ __global__ void __launch_bounds__(256) k_tables_2d(InitArgs a) {
       for (int sp = 0; sp < c.n_dust; ++sp) {
         double rd = q[5 + 4 * sp + 3];
         w[L.dsc + ((size_t)sp * nz + kk) * nr + ii] = rd > 1e-300 ? rd : 1.0;
+        w[L.idsc + ((size_t)sp * nz + kk) * nr + ii] = rd > 1e-300 ? 1.0 / rd : 1.0;
       }
     }
     if (kin && ii >= 0 && ii <= nr) {

@@ -19,14 +19,15 @@ struct BgW {
 template <int DIR>
 __device__ __forceinline__ BgW bg_prims(const double* q, double g) {
   BgW b;
-  const double ir = 1.0 / q[4];
+  const double ir = frcp(q[4]);
   const double vel[3] = {q[0] * ir, q[1] * ir, q[2] * ir};
   b.rho = q[4];
   b.un = vel[Dirs<DIR>::n];
   b.t1 = vel[Dirs<DIR>::t1];
   b.t2 = vel[Dirs<DIR>::t2];
   b.p = (g - 1.0) * (q[3] - 0.5 * (q[0] * vel[0] + q[1] * vel[1] + q[2] * vel[2]));
-  b.c = sqrt(g * b.p * ir);
+  const double c2 = g * b.p * ir;
+  b.c = c2 * frsq(c2);
   b.h = q[3] + b.p;
   return b;
 }
