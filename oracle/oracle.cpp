@@ -43,6 +43,9 @@
  *     by the ratio of the stationary densities (zero gradient of E'/rho0, so that the
  *     ghost keeps the boundary cell's relative perturbation) and repeat its dust
  *     variables;
+ *   - the Rossby-wave-instability initial state (Sect. 4.3) keeps the temperature of the
+ *     stationary flow under the density bump and rebalances v_theta radially (the
+ *     bump's amplitude, width and centre are configuration values);
  *   - drag uses a constant Stokes number, t_s = St / Omega_K(r), or (drag_law 1) the
  *     Epstein / Stokes law of Sect. 2.9 with c_s the isothermal sound speed sqrt(p/rho)
  *     of the cell's gas (the c_s of App. A) and lambda = mfp_coef / rho_g.
@@ -72,6 +75,8 @@ typedef struct {
   double grain_size[4], grain_density[4], mfp_coef;
   int32_t bc_r, bc_z;
   double damp_r_in, damp_r_out, damp_z, damp_tau;
+  int32_t rwi_m, pad2;
+  double rwi_delta, rwi_dr, rwi_r0, rwi_eps;
 } OrConfig;
 
 typedef struct {
@@ -591,12 +596,26 @@ struct Sim {
                            std::exp(-X * X / (2.0 * sr * sr) - Y * Y / (2.0 * sa * sa));
           double dvr_hat = -psi_hat * rv * Y / (r * sa * sa);
           double dvt_hat = psi_hat * X / (sr * sr);
-          T u = A * dvr_hat;
-          T v = vth0 + A * dvt_hat;
+          /* Rossby-wave-instability seed (Sect. 4.3): a Gaussian overdensity bump
+           * B = 1 + delta exp(-(r - r0)^2 / (2 dr^2)) on the density and, at unchanged
+           * temperature, on the pressure; the azimuthal velocity rebalanced radially,
+           * v^2 = v0^2 + (r/rho) dP/dr - (r/rho0) dP0/dr = v0^2 + r c_iso^2 B'/B; and the
+           * radial velocity eps v0 sin(m theta) exp(-(r - r0)^2 / (2 dr^2)). */
+          double bump = 1.0, vrw = 0.0, vth = vth0;
+          if (c.rwi_delta != 0.0 || c.rwi_eps != 0.0) {
+            double x = r - c.rwi_r0;
+            double gx = std::exp(-x * x / (2.0 * c.rwi_dr * c.rwi_dr));
+            bump = 1.0 + c.rwi_delta * gx;
+            double dbump = -c.rwi_delta * x / (c.rwi_dr * c.rwi_dr) * gx;
+            vth = std::sqrt(vth0 * vth0 + r * (P0 / rho0) * dbump / bump);
+            vrw = c.rwi_eps * vth0 * std::sin(c.rwi_m * th) * gx;
+          }
+          T u = A * dvr_hat + vrw;
+          T v = vth + A * dvt_hat;
           double xi = noise ? noise[id] : 0.0;
-          double rho = rho0 * (1.0 + c.noise_amp * xi);
+          double rho = rho0 * bump * (1.0 + c.noise_amp * xi);
           T q[5];
-          gas_conservative(rho, u, v, P0, q);
+          gas_conservative(rho, u, v, P0 * bump, q);
           for (int f = 0; f < 5; ++f) E[f * N + id] = q[f];
           for (int s = 0; s < nd; ++s) {
             double rd = dust_density(s, r, z);

@@ -83,6 +83,14 @@ class Config:
     damp_r_out: float = 0.84
     damp_z: float = 0.8
     damp_tau: float = 1.0
+    # Rossby-wave-instability seed (Sect. 4.3): density bump 1 + rwi_delta exp(-(r -
+    # rwi_r0)^2 / (2 rwi_dr^2)) at unchanged temperature with v_theta rebalanced, and a
+    # radial velocity rwi_eps v_theta0 sin(rwi_m theta) with the same Gaussian profile
+    rwi_m: int = 0
+    rwi_delta: float = 0.0
+    rwi_dr: float = 0.05
+    rwi_r0: float = 1.0
+    rwi_eps: float = 0.0
 
     @property
     def n_dust(self) -> int:
@@ -126,7 +134,13 @@ C4_LARGE = _disc("bifluid3_disc_512x1024x128", 512, 1024, 128, vortex_amp=1e-2,
 C5_ADJOINT = _disc("adjoint_disc_128x256x32", 128, 256, 32, stokes=(0.1,),
                    eps_dust=(0.01,), hd_over_h=(0.3,), steps=200)
 
-CONFIGS = {c.name: c for c in (C1_SOD, C2_DISC, C3_BIFLUID, C4_LARGE, C5_ADJOINT)}
+# Rossby-wave-instability test (Sect. 4.3): gas disc of the second workload with a density
+# bump (amplitude 0.2 and width 0.05 at r = 1: readings, the paper gives neither) and the
+# m = 4 radial-velocity seed of amplitude 1e-4; no vortex
+C6_RWI = _disc("rwi_disc_128x256x64", 128, 256, 64, vortex_amp=0.0, rwi_m=4, rwi_delta=0.2,
+               rwi_dr=0.05, rwi_r0=1.0, rwi_eps=1e-4, steps=200)
+
+CONFIGS = {c.name: c for c in (C1_SOD, C2_DISC, C3_BIFLUID, C4_LARGE, C5_ADJOINT, C6_RWI)}
 
 
 def epstein_grains(cfg: Config, rho_switch: float = 0.5, rho_s: float = 1.0) -> Config:
