@@ -109,6 +109,13 @@ typedef struct {
    * or at the cell radius (vertical zones).  Not with rb_record.                       */
   int32_t bc_r, bc_z;
   double damp_r_in, damp_r_out, damp_z, damp_tau;
+  /* Rossby-wave-instability seed of the initial disc (Sect. 4.3; 0 amplitudes: none):
+   * density and pressure times B = 1 + rwi_delta exp(-(r - rwi_r0)^2 / (2 rwi_dr^2))
+   * (temperature unchanged), v_theta^2 = v_theta0^2 + r c_iso^2 B'/B (radial balance), and
+   * v_r = rwi_eps v_theta0 sin(rwi_m theta) exp(-(r - rwi_r0)^2 / (2 rwi_dr^2)).
+   * rb_amp_gradient refuses a seeded disc.                                              */
+  int32_t rwi_m, reserved2;
+  double rwi_delta, rwi_dr, rwi_r0, rwi_eps;
 } rb_config;
 
 /* Caller-owned device buffers.  Sizes come from rb_query_sizes; pointers must be

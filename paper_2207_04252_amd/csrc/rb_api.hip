@@ -69,6 +69,9 @@ bool validate(const rb_config* c, std::string* why) {
   }
   if (c->indirect && c->init_kind != RB_INIT_DISC) return bad("indirect gravity needs a disc");
   if (c->bc_r < 0 || c->bc_r > 1 || c->bc_z < 0 || c->bc_z > 2) return bad("bc_r must be 0..1, bc_z 0..2");
+  if ((c->rwi_delta != 0.0 || c->rwi_eps != 0.0) &&
+      (c->init_kind != RB_INIT_DISC || !(c->rwi_dr > 0.0) || !(c->rwi_delta > -1.0) || c->rwi_m < 0))
+    return bad("the RWI seed needs a disc, rwi_dr > 0, rwi_delta > -1 and rwi_m >= 0");
   if ((c->bc_r || c->bc_z) && c->init_kind != RB_INIT_DISC) return bad("boundary options need a disc");
   if ((c->bc_r == 1 || c->bc_z == 2) &&
       (!(c->damp_tau > 0.0) || !(c->damp_r_in > 1.0) || !(c->damp_r_out > 0.0 && c->damp_r_out < 1.0) ||
@@ -782,6 +785,8 @@ rb_status rb_amp_gradient(rb_ctx* x, const double* noise, const double* amp, con
                           void* out) {
   if (!x || !lam || !out) return RB_EINVAL;
   if (x->cfg.init_kind != RB_INIT_DISC) return fail(x, RB_EINVAL, "no vortex in this initial state");
+  if (x->cfg.rwi_delta != 0.0 || x->cfg.rwi_eps != 0.0)
+    return fail(x, RB_EINVAL, "the amplitude gradient covers the vortex-only initial state");
   const size_t N = x->g.N;
   InitArgs ia;
   std::memset(&ia, 0, sizeof(ia));

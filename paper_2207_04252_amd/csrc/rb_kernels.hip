@@ -861,11 +861,22 @@ __global__ void __launch_bounds__(256) k_init_state(InitArgs a) {
     const double Om = sqrt(c.GM / (rv * rv * rv));
     const double psi = -2.0 * Om / (1.0 / (sr * sr) + 1.0 / (sa * sa)) *
                        exp(-X * X / (2.0 * sr * sr) - Y * Y / (2.0 * sa * sa));
-    const double u = A * (-psi * rv * Y / (r * sa * sa));
-    const double v = e.v + A * (psi * X / (sr * sr));
+    // Rossby-wave-instability seed (Sect. 4.3): density bump B at unchanged temperature,
+    // rotation from the radial balance with the bump's pressure gradient
+    // (v^2 = v0^2 + r c_iso^2 B'/B, c_iso^2 = P0/rho0), m-mode radial velocity
+    double B = 1.0, vr = 0.0, vt = e.v;
+    if (c.rwi_delta != 0.0 || c.rwi_eps != 0.0) {
+      const double x = r - c.rwi_r0, w2 = c.rwi_dr * c.rwi_dr;
+      const double gx = exp(-0.5 * x * x / w2);
+      B = 1.0 + c.rwi_delta * gx;
+      vt = sqrt(e.v * e.v - r * (e.P / e.rho) * (c.rwi_delta * gx * x / w2) / B);
+      vr = c.rwi_eps * e.v * sin(c.rwi_m * ((j + 0.5) * dth)) * gx;
+    }
+    const double u = A * (-psi * rv * Y / (r * sa * sa)) + vr;
+    const double v = vt + A * (psi * X / (sr * sr));
     const double xi = a.noise ? a.noise[cl] : 0.0;
-    const double rho = e.rho * (1.0 + c.noise_amp * xi);
-    gas_cons(c.gamma, rho, u, v, e.P, q);
+    const double rho = e.rho * B * (1.0 + c.noise_amp * xi);
+    gas_cons(c.gamma, rho, u, v, e.P * B, q);
     for (int f = 0; f < 5; ++f) store_init(a, f, k, i, cl, q[f] - q0[f]);
     for (int s = 0; s < c.n_dust; ++s) {
       const double rd = dust_layer(c, s, r, z);

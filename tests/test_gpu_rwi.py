@@ -1,0 +1,105 @@
+"""Rossby-wave-instability disc (Sect. 4.3) on the GPU against the FP64 oracle: the
+seeded initial state (density bump, rebalanced rotation, m = 4 radial-velocity seed) and
+the step map along an oracle trajectory, FP64 and FP32-perturbation forms.  Short
+horizon: the growth of the instability itself is a long-run measurement."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2207_04252_amd import synth
+from tests.parity import field_errors, worst
+
+pytestmark = pytest.mark.gpu
+
+CFG = synth.C6_RWI.scaled(48, 64, 16)
+
+
+@pytest.fixture(scope="module")
+def rb():
+    import torch
+    assert torch.cuda.is_available(), "GPU test on a machine without a GPU"
+    from paper_2207_04252_amd import rossbi
+    rossbi.load()
+    return rossbi
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32p"])
+def test_rwi_initial_state(rb, precision):
+    cfg = CFG
+    say(f"[rwi init] {cfg.name} {precision}")
+    xi = synth.noise(cfg)
+    prec = rb.RB_FP64 if precision == "fp64" else rb.RB_FP32_PERT
+    sim = rb.Sim(cfg, precision=prec, noise=xi)
+    gpu = sim.fields()
+    ref = oracle.Oracle(cfg, noise=xi).state()
+    tol = 1e-12 if precision == "fp64" else 1e-6
+    for f in range(5):
+        if f == 2:   # the seeded disc has w = 0
+            assert np.all(gpu[f] == 0.0) or np.abs(gpu[f]).max() <= tol * np.abs(ref[1]).max()
+            continue
+        scale = np.abs(ref[f]).max() if f == 0 else np.abs(ref[f])
+        err = np.max(np.abs(gpu[f] - ref[f]) / scale)
+        assert err <= tol, (f, err)
+    sim.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32p"])
+def test_rwi_step_parity(rb, precision):
+    """One step from oracle states along an oracle trajectory.  The limiter (reading of
+    Sect. 2.7) switches near its thresholds on the bump's flanks, where the step map
+    amplifies rounding-size input changes by up to ~1e5; each checkpoint's FP64 gate is
+    therefore max(1e-10, 30 x the oracle's own change under a 1e-15 relative input
+    perturbation)."""
+    cfg = CFG
+    say(f"[rwi step] {cfg.name} {precision}")
+    xi = synth.noise(cfg)
+    o = oracle.Oracle(cfg, noise=xi)
+    prec = rb.RB_FP64 if precision == "fp64" else rb.RB_FP32_PERT
+    sim = rb.Sim(cfg, precision=prec, noise=xi)
+    done = 0
+    for c in (0, 15, 30):
+        if c > done:
+            assert o.step(c - done)[0] == 0
+            done = c
+        sim_in = o.state()
+        sim.set_fields(sim_in)
+        dt = o.cfl_dt()
+        st, _ = sim.step(1, dt=dt)
+        assert st == rb.RB_OK, sim.error()
+        assert o.step(1, dt=dt)[0] == 0
+        done += 1
+        gpu, ref = sim.fields(), o.state()
+        if precision == "fp64":
+            x0 = sim_in
+            o2 = oracle.Oracle(cfg)
+            o2.set_state(x0 * (1 + 1e-15 * np.random.default_rng(c).standard_normal(x0.shape)))
+            assert o2.step(1, dt=dt)[0] == 0
+            sens = worst(field_errors(o2.state(), ref, cfg.gamma, cfg.n_dust))[1]
+            o2.close()
+            errs = field_errors(gpu, ref, cfg.gamma, cfg.n_dust)
+            gate = max(1e-10, 30 * sens)
+            say(f"[rwi step] checkpoint {c}: worst {worst(errs)}, oracle self-change {sens:.2e}")
+            for k, v in errs.items():
+                assert v <= gate, (c, k, v, gate)
+        else:
+            rel = np.abs(gpu[4] - ref[4]) / ref[4]
+            say(f"[rwi step] checkpoint {c}: rho {rel.max():.2e}")
+            assert rel.max() <= 1e-5
+    sim.close()
+    o.close()
+
+
+def test_rwi_amp_gradient_refused(rb):
+    cfg = CFG.scaled(12, 64, 8)
+    sim = rb.Sim(cfg, noise=synth.noise(cfg))
+    lam = np.zeros(sim.shape)
+    with pytest.raises(rb.RbError):
+        sim.amp_gradient(lam)
+    sim.close()
