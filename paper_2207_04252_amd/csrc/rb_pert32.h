@@ -11,6 +11,11 @@
 
 namespace rb {
 
+// FP32 reciprocal and square root from the hardware instructions (within an ulp or two;
+// the perturbation form's accuracy target is 1e-5 relative)
+__device__ __forceinline__ float rcp32(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ float sqrt32(float x) { return __builtin_amdgcn_sqrtf(x); }
+
 // background primitives at a face in the face frame (FP64)
 struct BgW {
   double rho, un, t1, t2, p, c, h;  // h = E + p per volume
@@ -44,7 +49,7 @@ __device__ __forceinline__ PW pert_prims(const BgW& b, const float* e, float gm1
   PW w;
   w.rho = e[4];
   const float rho = (float)(b.rho + (double)e[4]);
-  const float ir = __frcp_rn(rho);
+  const float ir = rcp32(rho);
   const float un0 = (float)b.un, t10 = (float)b.t1, t20 = (float)b.t2;
   w.un = (e[Dirs<DIR>::n] - un0 * w.rho) * ir;
   w.t1 = (e[Dirs<DIR>::t1] - t10 * w.rho) * ir;
@@ -90,11 +95,11 @@ __device__ __forceinline__ SideP make_side_p(const BgW& b, const PW& w, const Ga
   s.pp = w.p;
   s.p = (float)(b.p + (double)w.p);
   s.rho = (float)(b.rho + (double)w.rho);
-  s.c = sqrtf((float)g.g * s.p / s.rho);
-  s.A = (float)g.a2 / s.rho;
+  s.c = sqrt32((float)g.g * s.p * rcp32(s.rho));
+  s.A = (float)g.a2 * rcp32(s.rho);
   s.B = (float)g.kshock * s.p;
-  s.irc = __frcp_rn(s.rho * s.c);
-  s.ip = __frcp_rn(s.p);
+  s.irc = rcp32(s.rho * s.c);
+  s.ip = rcp32(s.p);
   s.up = w.un;
   s.u = (float)b.un + w.un;
   return s;
@@ -106,11 +111,11 @@ __device__ __forceinline__ void root7p(float x, float& y, float& ym1) {
   const float a = 1.0f + x;
   y = __builtin_amdgcn_exp2f(0.142857142857f * __builtin_amdgcn_logf(a));
   float y2 = y * y, y3 = y2 * y, y6 = y3 * y3;
-  y = y - (y6 * y - a) * __frcp_rn(7.0f * y6);
+  y = y - (y6 * y - a) * rcp32(7.0f * y6);
   y2 = y * y;
   y3 = y2 * y;
   const float s = 1.0f + y + y2 + y3 + y3 * y + y3 * y2 + y3 * y3;
-  ym1 = x * __frcp_rn(s);
+  ym1 = x * rcp32(s);
 }
 
 // pressure function of one side at p* = p0 + q (gamma = 7/5): value and derivative
@@ -118,8 +123,8 @@ __device__ __forceinline__ void pfun_p(float q, const SideP& K, float& f, float&
   const float d = q - K.pp;  // p* - p_K
   if (d > 0.0f) {
     const float ps = K.p + d;
-    const float ipb = __frcp_rn(ps + K.B);
-    const float qs = sqrtf(K.A * ipb);
+    const float ipb = rcp32(ps + K.B);
+    const float qs = sqrt32(K.A * ipb);
     f = d * qs;
     df = qs * (1.0f - 0.5f * d * ipb);
   } else {
@@ -127,7 +132,7 @@ __device__ __forceinline__ void pfun_p(float q, const SideP& K, float& f, float&
     root7p(d * K.ip, y, ym1);
     f = 5.0f * K.c * ym1;
     const float y2 = y * y, y3 = y2 * y, y6 = y3 * y3;
-    df = __frcp_rn(y6) * K.irc;
+    df = rcp32(y6) * K.irc;
   }
 }
 
@@ -146,8 +151,8 @@ __device__ __forceinline__ bool riemann_pert(const BgW& b, const PW& WL, const P
   // supersonic faces: the left (right) state is the solution when f(p_hi) >= 0 and the
   // contact moves the same way (same argument as the FP64 solver, with margins)
   if (L.u >= L.c) {
-    const float m = L.u / L.c;
-    const float phi = L.p * (m * m - (float)g.gm1_2g) / (float)g.gp1_2g;
+    const float m = L.u * rcp32(L.c);
+    const float phi = L.p * (m * m - (float)g.gm1_2g) * (float)g.inv_gp1_2g;
     float fL, dL, fR, dR;
     pfun_p(phi - p0, L, fL, dL);
     pfun_p(phi - p0, R, fR, dR);
@@ -156,8 +161,8 @@ __device__ __forceinline__ bool riemann_pert(const BgW& b, const PW& WL, const P
       return true;
     }
   } else if (R.u <= -R.c) {
-    const float m = -R.u / R.c;
-    const float phi = R.p * (m * m - (float)g.gm1_2g) / (float)g.gp1_2g;
+    const float m = -R.u * rcp32(R.c);
+    const float phi = R.p * (m * m - (float)g.gm1_2g) * (float)g.inv_gp1_2g;
     float fL, dL, fR, dR;
     pfun_p(phi - p0, L, fL, dL);
     pfun_p(phi - p0, R, fR, dR);
@@ -177,7 +182,7 @@ __device__ __forceinline__ bool riemann_pert(const BgW& b, const PW& WL, const P
     ++it;
     pfun_p(q, L, fL, dL);
     pfun_p(q, R, fR, dR);
-    float qn = q - (fL + fR + du) / (dL + dR);
+    float qn = q - (fL + fR + du) * rcp32(dL + dR);
     qn = fmaxf(qn, 1e-8f * (p0 + q) - p0);
     dq = qn - q;
     q = qn;
@@ -191,9 +196,9 @@ __device__ __forceinline__ bool riemann_pert(const BgW& b, const PW& WL, const P
   if (0.0f <= usfull) {
     if (q > WL.p) {
       const float x = (q - WL.p) * L.ip;
-      const float sL = L.u - L.c * sqrtf((float)g.gp1_2g * (1.0f + x) + (float)g.gm1_2g);
+      const float sL = L.u - L.c * sqrt32((float)g.gp1_2g * (1.0f + x) + (float)g.gm1_2g);
       if (0.0f <= sL) { W = WL; return true; }
-      const float rm1 = x * (1.0f - kk) * __frcp_rn(kk * (1.0f + x) + 1.0f);
+      const float rm1 = x * (1.0f - kk) * rcp32(kk * (1.0f + x) + 1.0f);
       W.rho = WL.rho + L.rho * rm1;
     } else {
       if (0.0f <= L.u - L.c) { W = WL; return true; }
@@ -208,9 +213,9 @@ __device__ __forceinline__ bool riemann_pert(const BgW& b, const PW& WL, const P
   }
   if (q > WR.p) {
     const float x = (q - WR.p) * R.ip;
-    const float sR = R.u + R.c * sqrtf((float)g.gp1_2g * (1.0f + x) + (float)g.gm1_2g);
+    const float sR = R.u + R.c * sqrt32((float)g.gp1_2g * (1.0f + x) + (float)g.gm1_2g);
     if (0.0f >= sR) { W = WR; return true; }
-    const float rm1 = x * (1.0f - kk) * __frcp_rn(kk * (1.0f + x) + 1.0f);
+    const float rm1 = x * (1.0f - kk) * rcp32(kk * (1.0f + x) + 1.0f);
     W.rho = WR.rho + R.rho * rm1;
   } else {
     if (0.0f >= R.u + R.c) { W = WR; return true; }
