@@ -121,9 +121,9 @@ typedef struct {
 /* Caller-owned device buffers.  Sizes come from rb_query_sizes; pointers must be
  * 256-byte aligned device addresses that stay valid until rb_destroy. */
 /* State layout.  FP64: all fields in FP64, field-major.  FP32-perturbation: the gas
- * deviation E' (5 fields) and the dust momenta divided by each species' initial-layer
- * density (3 per species) in FP32, padded to a multiple of 64 floats, then the dust
- * densities in FP64.  rb_get_fields / rb_set_fields always exchange FP64 full values. */
+ * deviation E' (5 fields) and the dust velocities, momentum / density (3 per species), in
+ * FP32, padded to a multiple of 64 floats, then the dust densities in FP64.
+ * rb_get_fields / rb_set_fields always exchange FP64 full values. */
 typedef struct {
   void* state;   /* the state (layout above)                                          */
   void* stage;   /* midpoint state of the RK2 step, same layout and type             */

@@ -139,8 +139,6 @@ Layout make_layout(const rb_config& c) {
   L.ghrf = take(2 * nz * 5);
   L.ghz = take(4 * nr * nf);
   L.ghzf = take(2 * nr * 5);
-  L.dsc = take(std::max<size_t>(1, (size_t)c.n_dust * nz * nr));
-  L.idsc = take(std::max<size_t>(1, (size_t)c.n_dust * nz * nr));
   L.trig = take(2 * nth);
   L.indw = take(nz * nr);
   L.indab = take(2);
@@ -189,8 +187,6 @@ StageArgs base_args(rb_ctx* x) {
   a.t.rt = w + L.rt; a.t.ar = w + L.ar; a.t.rco = w + L.rco; a.t.bgc = w + L.bgc;
   a.t.bgr = w + L.bgr; a.t.bgz = w + L.bgz; a.t.r0 = w + L.r0; a.t.grav = w + L.grav;
   a.t.ghr = w + L.ghr; a.t.ghrf = w + L.ghrf; a.t.ghz = w + L.ghz; a.t.ghzf = w + L.ghzf;
-  a.t.dsc = w + L.dsc;
-  a.t.idsc = w + L.idsc;
   a.t.trig = w + L.trig; a.t.indw = w + L.indw; a.t.indab = w + L.indab;
   a.t.damp = w + L.damp;
   a.t.ozr = w + L.ozr;
@@ -507,7 +503,12 @@ rb_status rb_set_fields(rb_ctx* x, const double* host_in, size_t n_doubles) {
   const size_t N = x->g.N;
   if (n_doubles != N * x->g.nf) return fail(x, RB_EINVAL, "n_doubles must be nfields * ncells");
   StageArgs a = base_args(x);
-  for (int f = 0; f < x->g.nf; ++f) {
+  // each dust density before its momenta (the FP32 layout stores velocities against it)
+  std::vector<int> order;
+  for (int f = 0; f < 5; ++f) order.push_back(f);
+  for (int s = 0; s < x->g.nd; ++s)
+    for (int c : {3, 0, 1, 2}) order.push_back(5 + 4 * s + c);
+  for (int f : order) {
     HIPCHK(x, hipMemcpyAsync(x->stage, host_in + (size_t)f * N, N * sizeof(double),
                              hipMemcpyHostToDevice, x->stream), "copy in");
     HIPCHK(x, launch_from_full(a, (const double*)x->stage, x->state, f, x->stream), "from_full");

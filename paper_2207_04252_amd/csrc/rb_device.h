@@ -610,9 +610,11 @@ __device__ __forceinline__ void gas_face_p32(const GasC& c, const float* eA, con
 // ------------------------------------------------------------------------------------
 // state access with ghost cells (Sect. 2.4): r and z ghosts come from tables, theta wraps
 
-// FP32-perturbation storage layout: the gas deviation (5 fields) and the dust momenta
-// (3 per species, divided by the species' initial-layer density) in FP32, then the dust
-// densities in FP64 (mass is accumulated in FP64).  f64_base: first double of that part.
+// FP32-perturbation storage layout: the gas deviation (5 fields) and the dust velocities
+// (momentum / density, 3 per species) in FP32, then the dust densities in FP64 (mass is
+// accumulated in FP64).  f64_base: first double of that part.  A dust momentum is read as
+// density x velocity; it is stored as momentum / density after the cell's new density,
+// which must therefore be written first (zero velocity where the density is below 1e-300).
 __device__ __forceinline__ size_t p32_f64_base(const Geo& g) {
   return (((size_t)(5 + 3 * g.nd) * g.N + 63) / 64 * 64) / 2;
 }
@@ -625,9 +627,9 @@ __device__ __forceinline__ double ld_cell(const StageArgs& a, const void* st, in
   if (P32) {
     if (f < 5) return (double)((const float*)st)[(size_t)f * g.N + cell];
     const int sp = (f - 5) >> 2, c = (f - 5) & 3;
-    if (c == 3) return ((const double*)st)[p32_f64_base(g) + (size_t)sp * g.N + cell];
-    const double v = (double)((const float*)st)[(size_t)(5 + 3 * sp + c) * g.N + cell];
-    return v * a.t.dsc[((size_t)sp * g.nz + k) * g.nr + i];
+    const double rd = ((const double*)st)[p32_f64_base(g) + (size_t)sp * g.N + cell];
+    if (c == 3) return rd;
+    return rd * (double)((const float*)st)[(size_t)(5 + 3 * sp + c) * g.N + cell];
   }
   return ((const double*)st)[(size_t)f * g.N + cell];
 }
@@ -639,9 +641,10 @@ __device__ __forceinline__ void st_cell(const StageArgs& a, void* st, int f, int
   if (P32) {
     if (f < 5) { ((float*)st)[(size_t)f * g.N + cell] = (float)v; return; }
     const int sp = (f - 5) >> 2, c = (f - 5) & 3;
-    if (c == 3) { ((double*)st)[p32_f64_base(g) + (size_t)sp * g.N + cell] = v; return; }
-    v *= a.t.idsc[((size_t)sp * g.nz + k) * g.nr + i];
-    ((float*)st)[(size_t)(5 + 3 * sp + c) * g.N + cell] = (float)v;
+    double* dens = (double*)st + p32_f64_base(g) + (size_t)sp * g.N + cell;
+    if (c == 3) { *dens = v; return; }
+    const double rd = *dens;  // the new density, written before the momenta
+    ((float*)st)[(size_t)(5 + 3 * sp + c) * g.N + cell] = rd > 1e-300 ? (float)(v * frcp(rd)) : 0.0f;
   } else {
     ((double*)st)[(size_t)f * g.N + cell] = v;
   }

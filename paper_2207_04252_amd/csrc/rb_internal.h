@@ -46,7 +46,7 @@ struct Ctrl {
 // Offsets (in doubles) of the tables inside the work area.
 struct Layout {
   size_t ctrl, rt, ar, rco, rcell, zc, bgc, bgr, bgz, r0, grav, ghr, ghrf, ghz, ghzf;
-  size_t dsc, idsc, trig, indw, indab, indp, damp, ozr, dtlog, cflp, outp, tsp, red, total;
+  size_t trig, indw, indab, indp, damp, ozr, dtlog, cflp, outp, tsp, red, total;
   int nind;      // blocks of the indirect-gravity sums
   int nblocks;   // stage-kernel blocks
   int ntj, nti, nkc, tk;
@@ -81,8 +81,6 @@ struct Tables {
   const double* ghrf;
   const double* ghz;
   const double* ghzf;
-  const double* dsc;   // dust storage scale [species][k][i] (FP32 storage)
-  const double* idsc;  // its reciprocal
   const double* trig;  // cos, sin of the theta cell centres [2][ntheta]
   const double* indw;  // V r / (r^2 + z^2)^(3/2) per (k, i) (indirect-gravity sums)
   const double* indab; // the indirect-gravity sums A, B of the current stage input

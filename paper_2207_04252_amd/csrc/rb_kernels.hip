@@ -396,9 +396,17 @@ __global__ void __launch_bounds__(NT) k_march(StageArgs a, int species) {
       } else {
         const double cdt = a.coef * dt * invV;
 #pragma unroll
-        for (int f = 0; f < NG; ++f) {
+        for (int f = 0; f < NG; ++f)
           nvd[f] = fma(cdt, (double)Gt[f], ld_cell<P32>(a, a.base, F0 + f, k, ig, cell));
-          st_cell<P32>(a, a.out, F0 + f, k, ig, cell, nvd[f]);
+        if (!P32 || GAS) {
+#pragma unroll
+          for (int f = 0; f < NG; ++f) st_cell<P32>(a, a.out, F0 + f, k, ig, cell, nvd[f]);
+        } else {
+          // FP32 dust velocities are stored against the new density: density first (all
+          // values above were read before any store, the update may be in place)
+          st_cell<P32>(a, a.out, F0 + 3, k, ig, cell, nvd[3]);
+#pragma unroll
+          for (int f = 0; f < 3; ++f) st_cell<P32>(a, a.out, F0 + f, k, ig, cell, nvd[f]);
         }
       }
       if (GAS) {
@@ -766,12 +774,6 @@ __global__ void __launch_bounds__(256) k_tables_2d(InitArgs a) {
       double s3 = pow(r * r + zc * zc, 1.5);
       w[L.grav + ((size_t)kk * nr + ii) * 2 + 0] = -c.GM * r / s3;
       w[L.grav + ((size_t)kk * nr + ii) * 2 + 1] = -c.GM * zc / s3;
-      // storage scale of each dust species (FP32 form): its initial layer density
-      for (int sp = 0; sp < c.n_dust; ++sp) {
-        double rd = q[5 + 4 * sp + 3];
-        w[L.dsc + ((size_t)sp * nz + kk) * nr + ii] = rd > 1e-300 ? rd : 1.0;
-        w[L.idsc + ((size_t)sp * nz + kk) * nr + ii] = rd > 1e-300 ? 1.0 / rd : 1.0;
-      }
     }
     if (kin && ii >= 0 && ii <= nr) {
       background_full(a, face_r(c, ii), zc, q);
@@ -809,16 +811,16 @@ __global__ void __launch_bounds__(256) k_tables_2d(InitArgs a) {
   }
 }
 
-// store of the initial state: FP64, or FP32 with the dust scaled by its initial layer
+// store of the initial state: FP64, or the FP32 layout (dust velocity components given
+// directly through dust_vel)
 __device__ __forceinline__ void store_init(const InitArgs& a, int f, int k, int i, size_t cl,
-                                           double v) {
+                                           double v, double dust_vel = 0.0) {
   const Geo& g = a.g;
   if (g.p32) {
     if (f < 5) { ((float*)a.state)[(size_t)f * g.N + cl] = (float)v; return; }
     const int sp = (f - 5) >> 2, c = (f - 5) & 3;
     if (c == 3) { ((double*)a.state)[p32_f64_base(g) + (size_t)sp * g.N + cl] = v; return; }
-    v /= a.work[a.L.dsc + ((size_t)sp * g.nz + k) * g.nr + i];
-    ((float*)a.state)[(size_t)(5 + 3 * sp + c) * g.N + cl] = (float)v;
+    ((float*)a.state)[(size_t)(5 + 3 * sp + c) * g.N + cl] = (float)dust_vel;
   } else {
     ((double*)a.state)[(size_t)f * g.N + cl] = v;
   }
@@ -881,9 +883,9 @@ __global__ void __launch_bounds__(256) k_init_state(InitArgs a) {
     for (int s = 0; s < c.n_dust; ++s) {
       const double rd = dust_layer(c, s, r, z);
       const int o = 5 + 4 * s;
-      store_init(a, o + 0, k, i, cl, rd * u);
-      store_init(a, o + 1, k, i, cl, rd * v);
-      store_init(a, o + 2, k, i, cl, 0.0);
+      store_init(a, o + 0, k, i, cl, rd * u, u);
+      store_init(a, o + 1, k, i, cl, rd * v, v);
+      store_init(a, o + 2, k, i, cl, 0.0, 0.0);
       store_init(a, o + 3, k, i, cl, rd);
     }
   }
