@@ -387,11 +387,14 @@ __global__ void __launch_bounds__(NT) k_march(StageArgs a, int species) {
       double nvd[NG];
       if constexpr (PG) {
         const float cdt = (float)(a.coef * dt * invV);
+        float nv[NG];
+        // all loads before any store: the second stage updates in place
+#pragma unroll
+        for (int f = 0; f < NG; ++f) nv[f] = fma(cdt, Gt[f], ((const float*)a.base)[(size_t)f * g.N + cell]);
 #pragma unroll
         for (int f = 0; f < NG; ++f) {
-          float nv = fma(cdt, Gt[f], ((const float*)a.base)[(size_t)f * g.N + cell]);
-          ((float*)a.out)[(size_t)f * g.N + cell] = nv;
-          nvd[f] = (double)nv;
+          ((float*)a.out)[(size_t)f * g.N + cell] = nv[f];
+          nvd[f] = (double)nv[f];
         }
       } else {
         const double cdt = a.coef * dt * invV;
