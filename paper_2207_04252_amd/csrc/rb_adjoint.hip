@@ -707,14 +707,17 @@ __global__ void __launch_bounds__(NT) k_adj_plane(AdjArgs A, int species) {
       cur[3] -= its * dotU;
       stb -= dotD / st;
     }
+    // all loads before any store (out may be one of the bases)
+    double v[NG];
 #pragma unroll
     for (int f = 0; f < NG; ++f) {
       const size_t o = (size_t)(F0 + f) * N + cell;
-      double v = cur[f];
-      if (A.base1) v += A.base1[o];
-      if (A.base2) v += A.base2[o];
-      A.out[o] = v;
+      v[f] = cur[f];
+      if (A.base1) v[f] += A.base1[o];
+      if (A.base2) v[f] += A.base2[o];
     }
+#pragma unroll
+    for (int f = 0; f < NG; ++f) A.out[(size_t)(F0 + f) * N + cell] = v[f];
   }
   // ---- Stokes-number partial of the block (dust)
   if constexpr (!GAS) {
@@ -771,8 +774,11 @@ __global__ void __launch_bounds__(256) k_adj_z(AdjArgs A, int species, int tkz) 
   auto real = [&](int kf) { return kf >= -1 && kf <= g.nz - 1; };
   auto add_out = [&](int k, const double* v) {
     const size_t cell = ((size_t)k * g.nr + ig) * g.nth + jg;
+    double o[NG];
 #pragma unroll
-    for (int f = 0; f < NG; ++f) A.out[(size_t)(F0 + f) * g.N + cell] += v[f];
+    for (int f = 0; f < NG; ++f) o[f] = A.out[(size_t)(F0 + f) * g.N + cell] + v[f];
+#pragma unroll
+    for (int f = 0; f < NG; ++f) A.out[(size_t)(F0 + f) * g.N + cell] = o[f];
   };
 
   // contributions of the faces below cell k to cells k (zb) and k+1 (zc); za = cell k-1
