@@ -677,6 +677,29 @@ __device__ __forceinline__ double fetch(const StageArgs& a, const void* st, int 
   return ld_cell<P32>(a, st, f, k, i, ((size_t)k * g.nr + i) * g.nth + j);
 }
 
+// All NG reconstructed fields of a group at one cell.  A dust group in the FP32 layout
+// reads its density once for the three momenta (density x stored velocity).
+template <bool P32, bool EXT, int NG, class T>
+__device__ __forceinline__ void fetch_all(const StageArgs& a, const void* st, int F0, int k, int i,
+                                          int j, T* out) {
+  const Geo& g = a.g;
+  if constexpr (P32 && NG == 4) {
+    if (k >= 0 && k < g.nz && i >= 0 && i < g.nr) {
+      const size_t cell = ((size_t)k * g.nr + i) * g.nth + j;
+      const int sp = (F0 - 5) >> 2;
+      const double rd = ((const double*)st)[p32_f64_base(g) + (size_t)sp * g.N + cell];
+      const float* vel = (const float*)st + (size_t)(5 + 3 * sp) * g.N + cell;
+      out[0] = (T)(rd * (double)vel[0]);
+      out[1] = (T)(rd * (double)vel[g.N]);
+      out[2] = (T)(rd * (double)vel[2 * g.N]);
+      out[3] = (T)rd;
+      return;
+    }
+  }
+#pragma unroll
+  for (int f = 0; f < NG; ++f) out[f] = (T)fetch<P32, EXT>(a, st, F0 + f, k, i, j);
+}
+
 // centre state used by the gas fallback: E0(centre) + E' for interior cells and outflow
 // z ghosts (scale 1), the ghost's full state (scale 0) otherwise
 template <bool EXT = false>

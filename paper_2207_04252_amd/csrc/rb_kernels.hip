@@ -88,13 +88,10 @@ __global__ void __launch_bounds__(NT) k_march(StageArgs a, int species) {
   const bool twod = g.twod != 0;
   if (!twod) {
     T e2[NG];
-#pragma unroll
-    for (int f = 0; f < NG; ++f) {
-      e2[f] = (T)fetch<P32, EXT>(a, in, F0 + f, k0 - 2, ig, jw);
-      rm[f] = (T)fetch<P32, EXT>(a, in, F0 + f, k0 - 1, ig, jw);
-      r0[f] = (T)fetch<P32, EXT>(a, in, F0 + f, k0, ig, jw);
-      rp[f] = (T)fetch<P32, EXT>(a, in, F0 + f, k0 + 1, ig, jw);
-    }
+    fetch_all<P32, EXT, NG>(a, in, F0, k0 - 2, ig, jw, e2);
+    fetch_all<P32, EXT, NG>(a, in, F0, k0 - 1, ig, jw, rm);
+    fetch_all<P32, EXT, NG>(a, in, F0, k0, ig, jw, r0);
+    fetch_all<P32, EXT, NG>(a, in, F0, k0 + 1, ig, jw, rp);
     double sB = 1.0, sC = 1.0;
     const double* cB = GAS ? centre_ptr<EXT>(a, k0 - 1, igc, sB) : nullptr;
     const double* cC = GAS ? centre_ptr<EXT>(a, k0, igc, sC) : nullptr;
@@ -110,17 +107,16 @@ __global__ void __launch_bounds__(NT) k_march(StageArgs a, int species) {
       for (int f = 0; f < NG; ++f) { s_rm[f][tslot] = rm[f]; s_fz[f][tslot] = fzlo[f]; }
     }
   } else {
+    fetch_all<P32, EXT, NG>(a, in, F0, 0, ig, jw, r0);
 #pragma unroll
     for (int f = 0; f < NG; ++f) {
-      r0[f] = (T)fetch<P32, EXT>(a, in, F0 + f, 0, ig, jw);
       rm[f] = T(0); rp[f] = T(0); rn[f] = T(0); fzlo[f] = T(0); fzhi[f] = T(0);
     }
   }
 
   for (int k = k0; k < k1; ++k) {
     if (!twod) {
-#pragma unroll
-      for (int f = 0; f < NG; ++f) rn[f] = (T)fetch<P32, EXT>(a, in, F0 + f, k + 2, ig, jw);
+      fetch_all<P32, EXT, NG>(a, in, F0, k + 2, ig, jw, rn);
     }
     // ---- stage the plane (with halo) in LDS
 #pragma unroll
@@ -130,8 +126,10 @@ __global__ void __launch_bounds__(NT) k_march(StageArgs a, int species) {
       if (rr >= 2 && rr < TI + 2 && cc >= 2 && cc < TJ + 2) continue;
       int ii = i0 + rr - 2;
       int jj = (j0 + cc - 2 + g.nth) % g.nth;
+      T hv[NG];
+      fetch_all<P32, EXT, NG>(a, in, F0, k, ii, jj, hv);
 #pragma unroll
-      for (int f = 0; f < NG; ++f) s_pl[f][rr][cc] = (T)fetch<P32, EXT>(a, in, F0 + f, k, ii, jj);
+      for (int f = 0; f < NG; ++f) s_pl[f][rr][cc] = hv[f];
     }
     __syncthreads();
     // ---- theta face j+1/2 and r face i+1/2 of this cell
@@ -398,9 +396,10 @@ __global__ void __launch_bounds__(NT) k_march(StageArgs a, int species) {
         }
       } else {
         const double cdt = a.coef * dt * invV;
+        double bv[NG];
+        fetch_all<P32, EXT, NG>(a, a.base, F0, k, ig, jg, bv);
 #pragma unroll
-        for (int f = 0; f < NG; ++f)
-          nvd[f] = fma(cdt, (double)Gt[f], ld_cell<P32>(a, a.base, F0 + f, k, ig, cell));
+        for (int f = 0; f < NG; ++f) nvd[f] = fma(cdt, (double)Gt[f], bv[f]);
         if (!P32 || GAS) {
 #pragma unroll
           for (int f = 0; f < NG; ++f) st_cell<P32>(a, a.out, F0 + f, k, ig, cell, nvd[f]);
