@@ -121,11 +121,17 @@ __global__ void __launch_bounds__(NT) k_march(StageArgs a, int species) {
     // ---- stage the plane (with halo) in LDS
 #pragma unroll
     for (int f = 0; f < NG; ++f) s_pl[f][ti + 2][tj + 2] = r0[f];
-    for (int h = tid; h < (TI + 4) * (TJ + 4); h += NT) {
-      int rr = h / (TJ + 4), cc = h % (TJ + 4);
-      if (rr >= 2 && rr < TI + 2 && cc >= 2 && cc < TJ + 2) continue;
-      int ii = i0 + rr - 2;
-      int jj = (j0 + cc - 2 + g.nth) % g.nth;
+    // the halo ring, one cell per thread: two rows below and above the tile, then two
+    // columns on each side of its rows
+    constexpr int HW = TJ + 4, NHALO = 4 * HW + 4 * TI;
+    static_assert(NHALO <= NT, "one halo cell per thread");
+    if (tid < NHALO) {
+      int rr, cc;
+      if (tid < 2 * HW) { rr = tid / HW; cc = tid % HW; }
+      else if (tid < 4 * HW) { rr = TI + 2 + (tid - 2 * HW) / HW; cc = (tid - 2 * HW) % HW; }
+      else { const int e = tid - 4 * HW; rr = 2 + e / 4; cc = (e & 3) < 2 ? (e & 3) : TJ + (e & 3); }
+      const int ii = i0 + rr - 2;
+      const int jj = (j0 + cc - 2 + g.nth) % g.nth;
       T hv[NG];
       fetch_all<P32, EXT, NG>(a, in, F0, k, ii, jj, hv);
 #pragma unroll
