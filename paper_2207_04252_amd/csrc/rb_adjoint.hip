@@ -550,12 +550,20 @@ __global__ void __launch_bounds__(NT) k_adj_plane(AdjArgs A, int species) {
   double stb = 0.0;  // Stokes-number partial (dust)
   for (int k = k0; k < k1; ++k) {
     // ---- stage the plane with a three-cell halo; clear the tile accumulators
-    for (int h = tid; h < (TI + 2 * H) * (TJ + 2 * H); h += NT) {
-      const int rr = h / (TJ + 2 * H), cc = h % (TJ + 2 * H);
-      const int ii = i0 + rr - H;
-      const int jj = X.jwrap(j0 + cc - H);
+    {
+      // at most two cells per thread; both cells' loads issued before the stores
+      constexpr int W = TJ + 2 * H, NC = (TI + 2 * H) * W;
+      static_assert(NC <= 2 * NT, "two staged cells per thread");
+      const int h0 = tid, h1 = tid + NT;
+      double v0[NG], v1[NG];
+      fetch_all<false, false, NG>(a, E, F0, k, i0 + h0 / W - H, X.jwrap(j0 + h0 % W - H), v0);
+      if (h1 < NC) fetch_all<false, false, NG>(a, E, F0, k, i0 + h1 / W - H, X.jwrap(j0 + h1 % W - H), v1);
 #pragma unroll
-      for (int f = 0; f < NG; ++f) s_e[f][rr][cc] = fetch<false>(a, E, F0 + f, k, ii, jj);
+      for (int f = 0; f < NG; ++f) s_e[f][h0 / W][h0 % W] = v0[f];
+      if (h1 < NC) {
+#pragma unroll
+        for (int f = 0; f < NG; ++f) s_e[f][h1 / W][h1 % W] = v1[f];
+      }
     }
 #pragma unroll
     for (int f = 0; f < NG; ++f) { s_at[f][ti][tj] = 0.0; s_ar[f][ti][tj] = 0.0; }
