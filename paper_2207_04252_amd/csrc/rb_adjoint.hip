@@ -491,7 +491,10 @@ __global__ void __launch_bounds__(NT) k_adj_plane(AdjArgs A, int species) {
   const int tjb = tile % a.ntj;
   const int tib = (tile / a.ntj) % a.nti;
   const int kcb = tile / (a.ntj * a.nti);
-  const int tid = threadIdx.x, tj = tid & (TJ - 1), ti = tid / TJ;
+  // the row index is wavefront-uniform (one 64-lane wavefront per row of a 1D workgroup):
+  // per-row tables go to scalar registers
+  const int tid = threadIdx.x, tj = tid & (TJ - 1);
+  const int ti = __builtin_amdgcn_readfirstlane(tid / TJ);
   const int j0 = tjb * TJ, i0 = tib * TI;
   const int k0 = kcb * A.tk, k1 = min(g.nz, k0 + A.tk);
   const int jg = j0 + tj;

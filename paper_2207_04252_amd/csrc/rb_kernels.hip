@@ -47,7 +47,11 @@ __global__ void __launch_bounds__(NT) k_march(StageArgs a, int species) {
   const int tjb = tile % a.ntj;
   const int tib = (tile / a.ntj) % a.nti;
   const int kcb = tile / (a.ntj * a.nti);
-  const int tid = threadIdx.x, tj = tid & (TJ - 1), ti = tid / TJ;
+  // one wavefront per radial row (TJ = 64 lanes of a 1D workgroup): the row index is
+  // wavefront-uniform, and saying so puts the per-row tables in scalar registers and
+  // scalar loads (without it the FP64 gas kernel spills)
+  const int tid = threadIdx.x, tj = tid & (TJ - 1);
+  const int ti = __builtin_amdgcn_readfirstlane(tid / TJ);
   const int j0 = tjb * TJ, i0 = tib * TI;
   const int k0 = kcb * a.tk, k1 = min(g.nz, k0 + a.tk);
   const int jg = j0 + tj;
@@ -114,6 +118,23 @@ __global__ void __launch_bounds__(NT) k_march(StageArgs a, int species) {
     }
   }
 
+  // the halo ring of the LDS plane, one cell per thread: two rows below and above the
+  // tile, then two columns on each side of its rows.  PF: each plane's halo is loaded one
+  // plane ahead, so that its latency hides behind the previous plane's face solves (not in
+  // the FP32-perturbation gas kernel, where the held registers cost more than they hide).
+  constexpr int HW = TJ + 4, NHALO = 4 * HW + 4 * TI;
+  static_assert(NHALO <= NT, "one halo cell per thread");
+  const bool halo_t = tid < NHALO;
+  int h_rr = 0, h_cc = 0;
+  if (tid < 2 * HW) { h_rr = tid / HW; h_cc = tid % HW; }
+  else if (tid < 4 * HW) { h_rr = TI + 2 + (tid - 2 * HW) / HW; h_cc = (tid - 2 * HW) % HW; }
+  else if (halo_t) { const int e = tid - 4 * HW; h_rr = 2 + e / 4; h_cc = (e & 3) < 2 ? (e & 3) : TJ + (e & 3); }
+  const int h_ii = i0 + h_rr - 2;
+  const int h_jj = (j0 + h_cc - 2 + g.nth) % g.nth;
+  constexpr bool PF = !PG;
+  T hv[NG];
+  if (PF && halo_t) fetch_all<P32, EXT, NG>(a, in, F0, k0, h_ii, h_jj, hv);
+
   for (int k = k0; k < k1; ++k) {
     if (!twod) {
       fetch_all<P32, EXT, NG>(a, in, F0, k + 2, ig, jw, rn);
@@ -121,21 +142,11 @@ __global__ void __launch_bounds__(NT) k_march(StageArgs a, int species) {
     // ---- stage the plane (with halo) in LDS
 #pragma unroll
     for (int f = 0; f < NG; ++f) s_pl[f][ti + 2][tj + 2] = r0[f];
-    // the halo ring, one cell per thread: two rows below and above the tile, then two
-    // columns on each side of its rows
-    constexpr int HW = TJ + 4, NHALO = 4 * HW + 4 * TI;
-    static_assert(NHALO <= NT, "one halo cell per thread");
-    if (tid < NHALO) {
-      int rr, cc;
-      if (tid < 2 * HW) { rr = tid / HW; cc = tid % HW; }
-      else if (tid < 4 * HW) { rr = TI + 2 + (tid - 2 * HW) / HW; cc = (tid - 2 * HW) % HW; }
-      else { const int e = tid - 4 * HW; rr = 2 + e / 4; cc = (e & 3) < 2 ? (e & 3) : TJ + (e & 3); }
-      const int ii = i0 + rr - 2;
-      const int jj = (j0 + cc - 2 + g.nth) % g.nth;
-      T hv[NG];
-      fetch_all<P32, EXT, NG>(a, in, F0, k, ii, jj, hv);
+    if (halo_t) {
+      if (!PF) fetch_all<P32, EXT, NG>(a, in, F0, k, h_ii, h_jj, hv);
 #pragma unroll
-      for (int f = 0; f < NG; ++f) s_pl[f][rr][cc] = hv[f];
+      for (int f = 0; f < NG; ++f) s_pl[f][h_rr][h_cc] = hv[f];
+      if (PF && k + 1 < k1) fetch_all<P32, EXT, NG>(a, in, F0, k + 1, h_ii, h_jj, hv);
     }
     __syncthreads();
     // ---- theta face j+1/2 and r face i+1/2 of this cell
