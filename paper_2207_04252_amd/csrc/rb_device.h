@@ -650,6 +650,19 @@ __device__ __forceinline__ void st_cell(const StageArgs& a, void* st, int f, int
   }
 }
 
+// A whole dust cell (momenta r, theta, z, density) into the FP32 layout from registers: the
+// density, then the velocities formed with it (the same values st_cell stores field by field,
+// without reading the density back)
+__device__ __forceinline__ void st_dust32(const StageArgs& a, void* st, int sp, size_t cell,
+                                          const double v[4]) {
+  const Geo& g = a.g;
+  ((double*)st)[p32_f64_base(g) + (size_t)sp * g.N + cell] = v[3];
+  const double ir = v[3] > 1e-300 ? frcp(v[3]) : 0.0;
+  float* vel = (float*)st + (size_t)(5 + 3 * sp) * g.N + cell;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) vel[(size_t)c * g.N] = v[3] > 1e-300 ? (float)(v[c] * ir) : 0.0f;
+}
+
 // EXT: the optional physics and boundary options (outflow ghosts here) may be active; the
 // base instantiation compiles them out.
 template <bool P32, bool EXT = false>

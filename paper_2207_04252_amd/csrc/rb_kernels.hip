@@ -277,14 +277,10 @@ __global__ void __launch_bounds__(NT) k_march(StageArgs a, int species) {
 #pragma unroll
         for (int s2 = 0; s2 < ND; ++s2) {
           const int o = 5 + 4 * s2;
+          // the FP32 layout stores the dust velocities themselves
           const double rd = ld_cell<P32>(a, in, o + 3, k, igc, cellw);
-          double ud = 0.0, vd = 0.0, wd = 0.0;
-          if (rd > 0.0) {
-            double id = 1.0 / rd;
-            ud = ld_cell<P32>(a, in, o, k, igc, cellw) * id;
-            vd = ld_cell<P32>(a, in, o + 1, k, igc, cellw) * id;
-            wd = ld_cell<P32>(a, in, o + 2, k, igc, cellw) * id;
-          }
+          const float* vel = (const float*)in + (size_t)(5 + 3 * s2) * g.N + cellw;
+          const double ud = vel[0], vd = vel[g.N], wd = vel[2 * (size_t)g.N];
           const double its = inv_tstop<EXT>(g, s2, omk, q[4], pq);
           dx += rd * (ud - u) * its;
           dy += rd * (vd - v) * its;
@@ -421,11 +417,9 @@ __global__ void __launch_bounds__(NT) k_march(StageArgs a, int species) {
 #pragma unroll
           for (int f = 0; f < NG; ++f) st_cell<P32>(a, a.out, F0 + f, k, ig, cell, nvd[f]);
         } else {
-          // FP32 dust velocities are stored against the new density: density first (all
-          // values above were read before any store, the update may be in place)
-          st_cell<P32>(a, a.out, F0 + 3, k, ig, cell, nvd[3]);
-#pragma unroll
-          for (int f = 0; f < 3; ++f) st_cell<P32>(a, a.out, F0 + f, k, ig, cell, nvd[f]);
+          // FP32 dust velocities are formed with the new density (all values above were
+          // read before any store, the update may be in place)
+          st_dust32(a, a.out, species, cell, nvd);
         }
       }
       if (GAS) {
