@@ -55,7 +55,7 @@ struct Layout {
 
 struct Geo {
   int nr, nth, nz, twod, nd, nf;
-  int p32;       // state stored as FP32 perturbation (gas) / scaled dust
+  int p32;       // state stored as FP32 perturbation (gas) / FP32 dust velocities
   int indirect;  // indirect gravity of the displaced star
   int drag_law;  // 0 constant Stokes number, 1 Epstein / Stokes regimes
   int bc_z;      // 0 stationary z ghosts, 1 outflow (ghosts repeat the boundary cell), 2 damped

@@ -958,7 +958,7 @@ __global__ void k_fill(double* p, size_t n, double v) {
     p[q] = v;
 }
 
-// field f of the state -> full FP64 values (gas: E0 + E'; dust: unscaled)
+// field f of the state -> full FP64 values (gas: E0 + E'; dust: momenta, densities)
 template <bool P32>
 __global__ void k_to_full(StageArgs a, const void* state, double* out, int f) {
   const Geo& g = a.g;
