@@ -24,6 +24,13 @@
  *   - the exact solver is the standard two-rarefaction/two-shock pressure
  *     function solved by Newton from the primitive-variable guess, relative
  *     change <= 1e-12, at most 50 iterations, sampled at x/t = 0;
+ *   - the parabola of Sect. 2.7 is taken on the primitive form of the Euler
+ *     variables: velocity, pressure and density of the gas as deviations from the
+ *     stationary flow's (W' = W(E) - W(E0)), and velocity and density of each dust
+ *     fluid whole; the face states are W0(face) + W'(i) + increment, and only
+ *     F* = F(E*) is formed from them.  Limiting the conservative variables one by one
+ *     was measured to be unstable at the disc's Mach numbers (a clipped increment of
+ *     one of rho u, E, rho is a pressure error times Mach^2);
  *   - the MinMod limiter acts on the parabolic face increment, bounded by
  *     twice the one-sided slopes times the face distance (continuous form);
  *   - a face state with rho <= 0 or p <= 0 (dust: rho_d < 0) is replaced by
@@ -688,6 +695,54 @@ struct Sim {
     return T(0.0);
   }
 
+  /* primitive gas variables of a conservative state, in the slots of the fields:
+   * (u_r, v_theta, w_z, P, rho) from (rho u, rho v, rho w, E, rho) with
+   * E = rho |V|^2 / 2 + P / (gamma - 1) (Sect. 2.1, App. B) */
+  template <class S>
+  void gas_primitives(const S* q, S* w) const {
+    w[0] = q[0] / q[4];
+    w[1] = q[1] / q[4];
+    w[2] = q[2] / q[4];
+    w[3] = (c.gamma - 1.0) * (q[3] - 0.5 * (q[0] * w[0] + q[1] * w[1] + q[2] * w[2]));
+    w[4] = q[4];
+  }
+  /* primitive dust variables (u, v, w, rho_d) of (rho_d u, rho_d v, rho_d w, rho_d);
+   * the velocity of an empty cell is zero */
+  template <class S>
+  void dust_primitives(const S* q, S* w) const {
+    bool full = val(q[3]) > 0.0;
+    for (int a = 0; a < 3; ++a) w[a] = full ? q[a] / q[3] : S(0.0);
+    w[3] = q[3];
+  }
+  /* primitive variables of the stationary flow from its conservative form (zero where
+   * the split has no reference: the Sod annulus) */
+  void reference_primitives(const double* q0, double* w0) const {
+    if (c.init_kind != INIT_DISC) {
+      for (int f = 0; f < 5; ++f) w0[f] = 0.0;
+      return;
+    }
+    gas_primitives(q0, w0);
+  }
+  /* reconstructed variables of a full conservative state at a point whose stationary
+   * flow is q0: gas W(E) - W(E0), dust whole primitives */
+  void recon_vars(const T* q, const double* q0, T* w, int nfl) const {
+    double w0[5];
+    reference_primitives(q0, w0);
+    gas_primitives(q, w);
+    for (int f = 0; f < 5; ++f) w[f] = w[f] - w0[f];
+    for (int o = 5; o < nfl; o += 4) dust_primitives(q + o, w + o);
+  }
+  /* reconstructed variable f of any cell, interior or ghost */
+  T recon(int f, int k, int i, int j) const {
+    if (i >= 0 && i < nr && k >= 0 && k < nz) return Wr[f * N + idx(k, i, wrapi(j, nth))];
+    T q[24], w[24];
+    double b[24];
+    centre_state(k, i, j, q);
+    background(rce(i), ghost_z(k), b);
+    recon_vars(q, b, w, nf);
+    return w[f];
+  }
+
   /* full state at the centre of any cell, interior or ghost (used by the face-state
    * positivity fallback) */
   void centre_state(int k, int i, int j, T* out) const {
@@ -703,64 +758,62 @@ struct Sim {
   }
 
   const T* cur = nullptr; /* state whose operator is being evaluated */
+  std::vector<T> Wr;      /* reconstructed variables of its interior cells */
   bool in_empty_run = false;
   double last_A = 0.0, last_B = 0.0; /* indirect-gravity sums of the last evaluation */
 
-  /* gas conservative -> primitive in the frame of direction d (0 r, 1 theta, 2 z) */
-  Prim<T> to_prim_gas(const T* q, int d) const {
+  /* primitive state in the frame of direction d (0 r, 1 theta, 2 z) from field-slot
+   * primitives: gas (u, v, w, P, rho), dust (u, v, w, rho_d) */
+  Prim<T> frame_gas(const T* w, int d) const {
     int t1 = d == 0 ? 1 : 0, t2 = d == 2 ? 1 : 2;
     Prim<T> W;
-    W.rho = q[4];
-    W.un = q[d] / q[4];
-    W.ut1 = q[t1] / q[4];
-    W.ut2 = q[t2] / q[4];
-    T u = q[0] / q[4], v = q[1] / q[4], w = q[2] / q[4];
-    W.p = (c.gamma - 1.0) * (q[3] - 0.5 * (q[0] * u + q[1] * v + q[2] * w));
+    W.rho = w[4]; W.un = w[d]; W.ut1 = w[t1]; W.ut2 = w[t2]; W.p = w[3];
     return W;
   }
-  Prim<T> to_prim_dust(const T* q, int d) const {
+  Prim<T> frame_dust(const T* w, int d) const {
     int t1 = d == 0 ? 1 : 0, t2 = d == 2 ? 1 : 2;
     Prim<T> W;
-    W.rho = q[3];
-    if (val(q[3]) > 0.0) {
-      W.un = q[d] / q[3]; W.ut1 = q[t1] / q[3]; W.ut2 = q[t2] / q[3];
-    } else {
-      W.un = 0.0; W.ut1 = 0.0; W.ut2 = 0.0;
-    }
-    W.p = 0.0;
+    W.rho = w[3]; W.un = w[d]; W.ut1 = w[t1]; W.ut2 = w[t2]; W.p = 0.0;
     return W;
   }
 
   /* Numerical flux at one face (Sect. 2.6, steps 1-3): parabolic face states of the two
    * adjacent cells, exact Riemann problem, F* = F(E*).  Cells a, b, cR, d are the four
-   * cells along the direction (a, b left of the face; cR, d right), x their coordinates,
-   * xf the face coordinate; bgf is E0 at the face; kb/ib/jb and kc/ic/jc locate b and cR. */
+   * cells along the direction (a, b left of the face; cR, d right), given by their
+   * reconstructed variables (gas W', dust primitives); x their coordinates, xf the face
+   * coordinate; bgf is E0 at the face; kb/ib/jb and kc/ic/jc locate b and cR.  The face
+   * state is W0(face) + W'(b) + increment (Sect. 2.7 on the primitive variables); a gas
+   * face state with rho <= 0 or P <= 0 (a dust face state with rho_d < 0) is replaced by
+   * the cell-centre state. */
   void face_flux(int dir, const T* va, const T* vb, const T* vc, const T* vd, const double x[4],
                  double xf, const double* bgf, int kb, int ib, int jb, int kc, int ic, int jc,
                  bool with_dust, T* F, long& nfall, long& nvac, int& maxit, int& noconv) const {
     const double g = c.gamma;
     int nfl = with_dust ? nf : 5;
+    double wf[5];
+    reference_primitives(bgf, wf);
     T qL[24], qR[24];
     for (int f = 0; f < nfl; ++f) {
       T incL = parabola_increment(va[f], vb[f], vc[f], x[0], x[1], x[2], xf);
       T incR = parabola_increment(vb[f], vc[f], vd[f], x[1], x[2], x[3], xf);
-      qL[f] = bgf[f] + (vb[f] + incL);
-      qR[f] = bgf[f] + (vc[f] + incR);
+      double ref = f < 5 ? wf[f] : 0.0;
+      qL[f] = ref + (vb[f] + incL);
+      qR[f] = ref + (vc[f] + incR);
     }
     /* positivity of the reconstructed states: fall back to the cell-centre state */
-    T centL[24], centR[24];
+    T centL[24], centR[24], wc[24];
     bool haveL = false, haveR = false;
-    Prim<T> WL = to_prim_gas(qL, dir), WR = to_prim_gas(qR, dir);
+    Prim<T> WL = frame_gas(qL, dir), WR = frame_gas(qR, dir);
     if (!(val(WL.rho) > 0.0 && val(WL.p) > 0.0)) {
       centre_state(kb, ib, jb, centL); haveL = true;
-      for (int f = 0; f < 5; ++f) qL[f] = centL[f];
-      WL = to_prim_gas(qL, dir);
+      gas_primitives(centL, wc);
+      WL = frame_gas(wc, dir);
       ++nfall;
     }
     if (!(val(WR.rho) > 0.0 && val(WR.p) > 0.0)) {
       centre_state(kc, ic, jc, centR); haveR = true;
-      for (int f = 0; f < 5; ++f) qR[f] = centR[f];
-      WR = to_prim_gas(qR, dir);
+      gas_primitives(centR, wc);
+      WR = frame_gas(wc, dir);
       ++nfall;
     }
     RiemannInfo info;
@@ -781,15 +834,15 @@ struct Sim {
       int o = 5 + 4 * s;
       if (val(qL[o + 3]) < 0.0) {
         if (!haveL) { centre_state(kb, ib, jb, centL); haveL = true; }
-        for (int q = 0; q < 4; ++q) qL[o + q] = centL[o + q];
+        dust_primitives(&centL[o], &qL[o]);
         ++nfall;
       }
       if (val(qR[o + 3]) < 0.0) {
         if (!haveR) { centre_state(kc, ic, jc, centR); haveR = true; }
-        for (int q = 0; q < 4; ++q) qR[o + q] = centR[o + q];
+        dust_primitives(&centR[o], &qR[o]);
         ++nfall;
       }
-      Prim<T> DL = to_prim_dust(&qL[o], dir), DR = to_prim_dust(&qR[o], dir);
+      Prim<T> DL = frame_dust(&qL[o], dir), DR = frame_dust(&qR[o], dir);
       T fd[4];
       riemann_dust(DL, DR, fd);
       F[o + 3] = fd[0];
@@ -811,6 +864,19 @@ struct Sim {
             size_t id = idx(k, i, j);
             Ep[f * N + id] = U[f * N + id] - bg_c[((size_t)k * nr + i) * nf + f];
           }
+    /* the variables the parabola is taken on (gas W' about the stationary flow, dust
+     * primitives), for the interior cells */
+    Wr.assign((size_t)nf * N, T(0.0));
+#pragma omp parallel for collapse(2) schedule(static)
+    for (int k = 0; k < nz; ++k)
+      for (int i = 0; i < nr; ++i)
+        for (int j = 0; j < nth; ++j) {
+          size_t id = idx(k, i, j);
+          T q[24], w[24];
+          for (int f = 0; f < nfl; ++f) q[f] = U[f * N + id];
+          recon_vars(q, &bg_c[((size_t)k * nr + i) * nf], w, nfl);
+          for (int f = 0; f < nfl; ++f) Wr[f * N + id] = w[f];
+        }
     long nfall = 0, nvac = 0;
     int maxit = 0, noconv = 0;
     /* r faces: face fi at rf[fi], between cells fi-1 and fi */
@@ -820,8 +886,8 @@ struct Sim {
         for (int j = 0; j < nth; ++j) {
           T va[24], vb[24], vc[24], vd[24], F[24];
           for (int f = 0; f < nfl; ++f) {
-            va[f] = dev(f, k, fi - 2, j); vb[f] = dev(f, k, fi - 1, j);
-            vc[f] = dev(f, k, fi, j);     vd[f] = dev(f, k, fi + 1, j);
+            va[f] = recon(f, k, fi - 2, j); vb[f] = recon(f, k, fi - 1, j);
+            vc[f] = recon(f, k, fi, j);     vd[f] = recon(f, k, fi + 1, j);
           }
           double x[4] = {rce(fi - 2), rce(fi - 1), rce(fi), rce(fi + 1)};
           face_flux(0, va, vb, vc, vd, x, rfa(fi), &bg_r[((size_t)k * (nr + 1) + fi) * nf], k,
@@ -835,8 +901,8 @@ struct Sim {
         for (int j = 0; j < nth; ++j) {
           T va[24], vb[24], vc[24], vd[24], F[24];
           for (int f = 0; f < nfl; ++f) {
-            va[f] = dev(f, k, i, j - 1); vb[f] = dev(f, k, i, j);
-            vc[f] = dev(f, k, i, j + 1); vd[f] = dev(f, k, i, j + 2);
+            va[f] = recon(f, k, i, j - 1); vb[f] = recon(f, k, i, j);
+            vc[f] = recon(f, k, i, j + 1); vd[f] = recon(f, k, i, j + 2);
           }
           double x[4] = {(double)(j - 1), (double)j, (double)(j + 1), (double)(j + 2)};
           face_flux(1, va, vb, vc, vd, x, j + 0.5, &bg_c[((size_t)k * nr + i) * nf], k, i, j, k, i,
@@ -851,8 +917,8 @@ struct Sim {
           for (int j = 0; j < nth; ++j) {
             T va[24], vb[24], vc[24], vd[24], F[24];
             for (int f = 0; f < nfl; ++f) {
-              va[f] = dev(f, fk - 2, i, j); vb[f] = dev(f, fk - 1, i, j);
-              vc[f] = dev(f, fk, i, j);     vd[f] = dev(f, fk + 1, i, j);
+              va[f] = recon(f, fk - 2, i, j); vb[f] = recon(f, fk - 1, i, j);
+              vc[f] = recon(f, fk, i, j);     vd[f] = recon(f, fk + 1, i, j);
             }
             double x[4] = {(double)(fk - 2), (double)(fk - 1), (double)fk, (double)(fk + 1)};
             face_flux(2, va, vb, vc, vd, x, fk - 0.5, &bg_z[((size_t)fk * nr + i) * nf], fk - 1, i,

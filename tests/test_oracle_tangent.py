@@ -7,16 +7,23 @@ adjoint is checked against.
 The limited reconstruction and the pressureless dust solver are only piecewise smooth.
 Finite differences measure the derivative only away from their kinks, so the pins use
 directions and states that stay clear of them: smooth perturbation patterns, a vortex
-centred off the mesh's faces (a centre on a face makes one-sided differences exactly
-zero there), and scalar functionals rather than per-cell values."""
+centred off the mesh's faces (a centre on a face makes one-sided differences of the
+velocities exactly zero there), and scalar functionals rather than per-cell values.
+Two kinks of the primitive-variable reconstruction sit on the initial disc itself and are
+avoided explicitly: the pressure deviation of the initial state is zero up to rounding
+(the vortex and the density noise leave the pressure unchanged), so the gas pin starts
+from a state ten steps into the run of a noise-free disc; and the settling dust layer is
+mirror-symmetric about the midplane, where it meets in a standing delta shock whose
+flux switches side with the sign of its speed (Sect. 2.9 solver), so amplitude directions
+are taken mirror-symmetric too."""
 import numpy as np
 import pytest
 
 import oracle
 from paper_2207_04252_amd import synth
 
-GAS = synth.C2_DISC.scaled(10, 24, 8).with_(vortex_r0=1.0137, vortex_th0=3.1829)
-DUST = synth.C5_ADJOINT.scaled(10, 24, 8)
+GAS = synth.C2_DISC.scaled(10, 24, 8).with_(vortex_r0=1.0137, vortex_th0=3.1829, noise_amp=0.0)
+DUST = synth.C5_ADJOINT.scaled(10, 24, 8).with_(vortex_r0=1.0137, vortex_th0=3.1829)
 
 
 def smooth_direction(cfg, x0, rng):
@@ -37,11 +44,11 @@ def smooth_direction(cfg, x0, rng):
 
 def test_tangent_state_matches_finite_differences():
     cfg = GAS
-    xi = synth.noise(cfg)
-    o = oracle.Oracle(cfg, noise=xi)
+    o = oracle.Oracle(cfg)
+    assert o.step(10)[0] == 0
+    x0 = o.state()
     st, dts = o.step(3)
     assert st == 0
-    x0 = oracle.Oracle(cfg, noise=xi).state()
     rng = np.random.default_rng(11)
     v = smooth_direction(cfg, x0, rng)
     status, xn, dxn = oracle.tangent_state(cfg, x0, v, None, dts)
@@ -80,10 +87,11 @@ def test_tangent_vortex_amplitude_matches_fd():
     st, dts = o.step(4)
     assert st == 0
     d = synth.random_direction(cfg, seed=3) * cfg.vortex_amp
+    d = 0.5 * (d + d[::-1])  # mirror-symmetric about the midplane
     status, J, dJ = oracle.tangent(cfg, xi, amp, d, None, dts)
     assert status == 0
     assert J == pytest.approx(o.core_dust_mass(), rel=1e-14)
-    assert dJ == pytest.approx(core_mass_fd(cfg, xi, amp, dts, d_amp=d), rel=1e-6)
+    assert dJ == pytest.approx(core_mass_fd(cfg, xi, amp, dts, d_amp=d, h=1e-3), rel=1e-6)
 
 
 def test_tangent_stokes_matches_fd():
