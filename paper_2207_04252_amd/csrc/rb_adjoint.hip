@@ -209,209 +209,185 @@ __device__ void riemann_rev(const GasC& c, const double* WL, const double* WR, c
   WRb[4] -= s * R.fp;
 }
 
-// Reverse of the face-frame primitives of a conservative gas state q (field order).
-template <int DIR>
-__device__ __forceinline__ void prim_rev(const double q[5], double gm1, const double Wb[5],
-                                         double qb[5]) {
-  const double ir = 1.0 / q[4];
-  const double vel[3] = {q[0] * ir, q[1] * ir, q[2] * ir};
-  double vb[3];
-  vb[Dirs<DIR>::n] = Wb[1];
-  vb[Dirs<DIR>::t1] = Wb[2];
-  vb[Dirs<DIR>::t2] = Wb[3];
-  const double pb = Wb[4] * gm1;
-  double dot = 0.0, v2 = 0.0;
+// Cotangent of a cell's reconstructed variables -> cotangent of its conservative
+// variables.  Gas: W = (u, v, w, P, rho) of E = (rho u, rho v, rho w, E, rho) at the full
+// state (the stationary flow b plus the cell's W'), u = m / rho,
+// P = (g - 1)(E - |m|^2 / (2 rho)).
+__device__ __forceinline__ void gas_cot_to_cons(const double* w, const double* b, double gm1,
+                                                const double* wb, double* eb) {
+  const double rho = b[WB_RHO] + w[4];
+  const double ir = 1.0 / rho;
+  const double u[3] = {b[WB_U] + w[0], b[WB_V] + w[1], b[WB_W] + w[2]};
+  const double pb = gm1 * wb[3];
+  double dot = 0.0, u2 = 0.0;
 #pragma unroll
-  for (int i = 0; i < 3; ++i) {
-    qb[i] = vb[i] * ir - pb * vel[i];
-    dot += vb[i] * vel[i];
-    v2 += vel[i] * vel[i];
+  for (int m = 0; m < 3; ++m) {
+    eb[m] = wb[m] * ir - pb * u[m];
+    dot += wb[m] * u[m];
+    u2 += u[m] * u[m];
   }
-  qb[3] = pb;
-  qb[4] = Wb[0] + 0.5 * pb * v2 - ir * dot;
+  eb[3] = pb;
+  eb[4] = wb[4] - dot * ir + 0.5 * pb * u2;
+}
+// Dust: W = (u, v, w, rho_d) of (rho_d u, rho_d v, rho_d w, rho_d); the velocity of an
+// empty cell is held at zero.
+__device__ __forceinline__ void dust_cot_to_cons(const double* w, const double* wb, double* eb) {
+  const double rd = w[3];
+  if (rd > 0.0) {
+    const double ir = 1.0 / rd;
+    eb[0] = wb[0] * ir;
+    eb[1] = wb[1] * ir;
+    eb[2] = wb[2] * ir;
+    eb[3] = wb[3] - (wb[0] * w[0] + wb[1] * w[1] + wb[2] * w[2]) * ir;
+  } else {
+    eb[0] = 0.0; eb[1] = 0.0; eb[2] = 0.0;
+    eb[3] = wb[3];
+  }
 }
 
-// Reverse of one gas face: Fb (field order) is the cotangent of the face flux; the
-// contributions to the stencil cells A, B | C, D are added to cA..cD.  The face states
-// are rebuilt for the reverse sweep rather than kept across the solve (registers).
+// limited face states of the gas (stationary flow at the face + W' + increment), rebuilt
+// for the reverse sweep rather than kept across the solve (registers)
 template <int DIR>
-__device__ __forceinline__ void gas_face_states(const double* eA, const double* eB,
-                                                const double* eC, const double* eD,
+__device__ __forceinline__ void gas_face_states(const double* wA, const double* wB,
+                                                const double* wC, const double* wD,
                                                 const double* coB, const double* coC,
-                                                const double* bgf, double qL[5], double qR[5]) {
+                                                const double* bf, double qL[5], double qR[5]) {
 #pragma unroll
   for (int f = 0; f < 5; ++f) {
     double iB, iC;
     if (DIR == 0) {
-      iB = inc_up_c(eA[f], eB[f], eC[f], coB);
-      iC = inc_lo_c(eB[f], eC[f], eD[f], coC);
+      iB = inc_up_c(wA[f], wB[f], wC[f], coB);
+      iC = inc_lo_c(wB[f], wC[f], wD[f], coC);
     } else {
-      iB = inc_up_u(eA[f], eB[f], eC[f]);
-      iC = inc_lo_u(eB[f], eC[f], eD[f]);
+      iB = inc_up_u(wA[f], wB[f], wC[f]);
+      iC = inc_lo_u(wB[f], wC[f], wD[f]);
     }
-    qL[f] = bgf[f] + (eB[f] + iB);
-    qR[f] = bgf[f] + (eC[f] + iC);
+    qL[f] = bf[f] + (wB[f] + iB);
+    qR[f] = bf[f] + (wC[f] + iC);
   }
 }
 
+// Reverse of one gas face: Fb (field order) is the cotangent of the face flux; the
+// contributions to the reconstructed variables W' of the stencil cells A, B | C, D are
+// added to cA..cD.
 template <int DIR, bool G75>
-__device__ void gas_face_vjp(const GasC& c, const double* eA, const double* eB, const double* eC,
-                             const double* eD, const double* coB, const double* coC,
-                             const double* bgf, const double* cenB, double sB,
-                             const double* cenC, double sC, const double* Fb, double* cA,
-                             double* cB, double* cC, double* cD) {
+__device__ void gas_face_vjp(const GasC& c, const double* wA, const double* wB, const double* wC,
+                             const double* wD, const double* coB, const double* coC,
+                             const double* bf, const double* bB, const double* bC,
+                             const double* Fb, double* cA, double* cB, double* cC, double* cD) {
+  constexpr int N = Dirs<DIR>::n, T1 = Dirs<DIR>::t1, T2 = Dirs<DIR>::t2;
   double qL[5], qR[5];
-  gas_face_states<DIR>(eA, eB, eC, eD, coB, coC, bgf, qL, qR);
-  Prim5 L = gas_prim<DIR>(qL, c.gm1);
-  Prim5 R = gas_prim<DIR>(qR, c.gm1);
-  const bool fbL = !(L.rho > 0.0 && L.p > 0.0);
-  const bool fbR = !(R.rho > 0.0 && R.p > 0.0);
+  gas_face_states<DIR>(wA, wB, wC, wD, coB, coC, bf, qL, qR);
+  const bool fbL = !(qL[4] > 0.0 && qL[3] > 0.0);
+  const bool fbR = !(qR[4] > 0.0 && qR[3] > 0.0);
   if (fbL) {
 #pragma unroll
-    for (int f = 0; f < 5; ++f) qL[f] = cenB[f] + sB * eB[f];
-    L = gas_prim<DIR>(qL, c.gm1);
+    for (int f = 0; f < 5; ++f) qL[f] = bB[f] + wB[f];
   }
   if (fbR) {
 #pragma unroll
-    for (int f = 0; f < 5; ++f) qR[f] = cenC[f] + sC * eC[f];
-    R = gas_prim<DIR>(qR, c.gm1);
+    for (int f = 0; f < 5; ++f) qR[f] = bC[f] + wC[f];
   }
   double WLb[5], WRb[5];
   {
     double fl[5];
     TStat st = {0, 0, 0, 0, 0};
     GasRec rec;
-    gas_riemann<G75, true>(c, L.rho, L.irho, L.un, L.t1, L.t2, L.p, R.rho, R.irho, R.un, R.t1,
-                           R.t2, R.p, fl, st, &rec);
-    const double flb[5] = {Fb[4], Fb[Dirs<DIR>::n], Fb[Dirs<DIR>::t1], Fb[Dirs<DIR>::t2], Fb[3]};
+    gas_riemann<G75, true>(c, qL[4], frcp(qL[4]), qL[N], qL[T1], qL[T2], qL[3], qR[4], frcp(qR[4]),
+                           qR[N], qR[T1], qR[T2], qR[3], fl, st, &rec);
+    const double flb[5] = {Fb[4], Fb[N], Fb[T1], Fb[T2], Fb[3]};
     double Wb[5];
     flux_rev(c, rec, flb, Wb);
-    const double WL[5] = {L.rho, L.un, L.t1, L.t2, L.p};
-    const double WR[5] = {R.rho, R.un, R.t1, R.t2, R.p};
+    const double WL[5] = {qL[4], qL[N], qL[T1], qL[T2], qL[3]};
+    const double WR[5] = {qR[4], qR[N], qR[T1], qR[T2], qR[3]};
     riemann_rev<G75>(c, WL, WR, rec, Wb, WLb, WRb);
   }
-  // left face state -> cells A, B, C (or B alone after a fallback)
-  {
-    double qb[5];
-    if (!fbL) {
-      double q2[5], q3[5];
-      gas_face_states<DIR>(eA, eB, eC, eD, coB, coC, bgf, q2, q3);
-      prim_rev<DIR>(q2, c.gm1, WLb, qb);
+  // face-frame cotangents (rho, un, t1, t2, p) -> field slots (u, v, w, P, rho)
+  double qLb[5], qRb[5];
+  qLb[4] = WLb[0]; qLb[N] = WLb[1]; qLb[T1] = WLb[2]; qLb[T2] = WLb[3]; qLb[3] = WLb[4];
+  qRb[4] = WRb[0]; qRb[N] = WRb[1]; qRb[T1] = WRb[2]; qRb[T2] = WRb[3]; qRb[3] = WRb[4];
+  // left face state -> cells A, B, C (or B alone after a fallback); right -> B, C, D
+#pragma unroll
+  for (int f = 0; f < 5; ++f) {
+    if (fbL) {
+      cB[f] += qLb[f];
     } else {
-      double q2[5];
-#pragma unroll
-      for (int f = 0; f < 5; ++f) q2[f] = cenB[f] + sB * eB[f];
-      prim_rev<DIR>(q2, c.gm1, WLb, qb);
+      double cm, cp;
+      if (DIR == 0) dinc_up_c(wA[f], wB[f], wC[f], coB, cm, cp);
+      else dinc_up_u(wA[f], wB[f], wC[f], cm, cp);
+      cA[f] -= cm * qLb[f];
+      cB[f] += (1.0 + cm - cp) * qLb[f];
+      cC[f] += cp * qLb[f];
     }
-#pragma unroll
-    for (int f = 0; f < 5; ++f) {
-      if (fbL) {
-        cB[f] += sB * qb[f];
-      } else {
-        double cm, cp;
-        if (DIR == 0) dinc_up_c(eA[f], eB[f], eC[f], coB, cm, cp);
-        else dinc_up_u(eA[f], eB[f], eC[f], cm, cp);
-        cA[f] -= cm * qb[f];
-        cB[f] += (1.0 + cm - cp) * qb[f];
-        cC[f] += cp * qb[f];
-      }
-    }
-  }
-  // right face state -> cells B, C, D (or C alone)
-  {
-    double qb[5];
-    if (!fbR) {
-      double q2[5], q3[5];
-      gas_face_states<DIR>(eA, eB, eC, eD, coB, coC, bgf, q2, q3);
-      prim_rev<DIR>(q3, c.gm1, WRb, qb);
+    if (fbR) {
+      cC[f] += qRb[f];
     } else {
-      double q3[5];
-#pragma unroll
-      for (int f = 0; f < 5; ++f) q3[f] = cenC[f] + sC * eC[f];
-      prim_rev<DIR>(q3, c.gm1, WRb, qb);
-    }
-#pragma unroll
-    for (int f = 0; f < 5; ++f) {
-      if (fbR) {
-        cC[f] += sC * qb[f];
-      } else {
-        double cm, cp;
-        if (DIR == 0) dinc_lo_c(eB[f], eC[f], eD[f], coC, cm, cp);
-        else dinc_lo_u(eB[f], eC[f], eD[f], cm, cp);
-        cB[f] -= cm * qb[f];
-        cC[f] += (1.0 + cm - cp) * qb[f];
-        cD[f] += cp * qb[f];
-      }
+      double cm, cp;
+      if (DIR == 0) dinc_lo_c(wB[f], wC[f], wD[f], coC, cm, cp);
+      else dinc_lo_u(wB[f], wC[f], wD[f], cm, cp);
+      cB[f] -= cm * qRb[f];
+      cC[f] += (1.0 + cm - cp) * qRb[f];
+      cD[f] += cp * qRb[f];
     }
   }
 }
 
-// Reverse of one dust face (variables reconstructed whole; a negative face density
-// falls back to the cell value).
+// Reverse of one dust face (velocity and density reconstructed whole; a negative face
+// density falls back to the cell value).  Contributions to the cells' reconstructed
+// variables.
 template <int DIR>
-__device__ void dust_face_vjp(const double* eA, const double* eB, const double* eC,
-                              const double* eD, const double* coB, const double* coC,
+__device__ void dust_face_vjp(const double* wA, const double* wB, const double* wC,
+                              const double* wD, const double* coB, const double* coC,
                               const double* Fb, double* cA, double* cB, double* cC, double* cD) {
+  constexpr int N = Dirs<DIR>::n, T1 = Dirs<DIR>::t1, T2 = Dirs<DIR>::t2;
   double qL[4], qR[4], cmB[4], cpB[4], cmC[4], cpC[4];
 #pragma unroll
   for (int f = 0; f < 4; ++f) {
     double iB, iC;
     if (DIR == 0) {
-      iB = inc_up_c(eA[f], eB[f], eC[f], coB);
-      iC = inc_lo_c(eB[f], eC[f], eD[f], coC);
-      dinc_up_c(eA[f], eB[f], eC[f], coB, cmB[f], cpB[f]);
-      dinc_lo_c(eB[f], eC[f], eD[f], coC, cmC[f], cpC[f]);
+      iB = inc_up_c(wA[f], wB[f], wC[f], coB);
+      iC = inc_lo_c(wB[f], wC[f], wD[f], coC);
+      dinc_up_c(wA[f], wB[f], wC[f], coB, cmB[f], cpB[f]);
+      dinc_lo_c(wB[f], wC[f], wD[f], coC, cmC[f], cpC[f]);
     } else {
-      iB = inc_up_u(eA[f], eB[f], eC[f]);
-      iC = inc_lo_u(eB[f], eC[f], eD[f]);
-      dinc_up_u(eA[f], eB[f], eC[f], cmB[f], cpB[f]);
-      dinc_lo_u(eB[f], eC[f], eD[f], cmC[f], cpC[f]);
+      iB = inc_up_u(wA[f], wB[f], wC[f]);
+      iC = inc_lo_u(wB[f], wC[f], wD[f]);
+      dinc_up_u(wA[f], wB[f], wC[f], cmB[f], cpB[f]);
+      dinc_lo_u(wB[f], wC[f], wD[f], cmC[f], cpC[f]);
     }
-    qL[f] = eB[f] + iB;
-    qR[f] = eC[f] + iC;
+    qL[f] = wB[f] + iB;
+    qR[f] = wC[f] + iC;
   }
   const bool fbL = qL[3] < 0.0, fbR = qR[3] < 0.0;
   if (fbL) {
 #pragma unroll
-    for (int f = 0; f < 4; ++f) qL[f] = eB[f];
+    for (int f = 0; f < 4; ++f) qL[f] = wB[f];
   }
   if (fbR) {
 #pragma unroll
-    for (int f = 0; f < 4; ++f) qR[f] = eC[f];
-  }
-  double vL[3] = {0.0, 0.0, 0.0}, vR[3] = {0.0, 0.0, 0.0}, iL = 0.0, iR = 0.0;
-  if (qL[3] > 0.0) {
-    iL = 1.0 / qL[3];
-    vL[0] = qL[0] * iL; vL[1] = qL[1] * iL; vL[2] = qL[2] * iL;
-  }
-  if (qR[3] > 0.0) {
-    iR = 1.0 / qR[3];
-    vR[0] = qR[0] * iR; vR[1] = qR[1] * iR; vR[2] = qR[2] * iR;
+    for (int f = 0; f < 4; ++f) qR[f] = wC[f];
   }
   double fl[4];
   int side;
-  dust_riemann<true>(qL[3], vL[Dirs<DIR>::n], vL[Dirs<DIR>::t1], vL[Dirs<DIR>::t2], qR[3],
-                     vR[Dirs<DIR>::n], vR[Dirs<DIR>::t1], vR[Dirs<DIR>::t2], fl, &side);
-  const double flb[4] = {Fb[3], Fb[Dirs<DIR>::n], Fb[Dirs<DIR>::t1], Fb[Dirs<DIR>::t2]};
+  dust_riemann<true>(qL[3], qL[N], qL[T1], qL[T2], qR[3], qR[N], qR[T1], qR[T2], fl, &side);
+  const double flb[4] = {Fb[3], Fb[N], Fb[T1], Fb[T2]};
   double qLb[4] = {0.0, 0.0, 0.0, 0.0}, qRb[4] = {0.0, 0.0, 0.0, 0.0};
-  // one side's flux (r u, r u^2, r u a, r u b) in terms of (r, u, a, b) = (rho, m/rho)
-  auto side_rev = [&](const double* q, const double* v, double inv, double wgt, double* qb) {
+  // one side's flux (r u, r u^2, r u a, r u b) in its face state (r, u, a, b); zero for an
+  // empty side (its velocity is held at zero)
+  auto side_rev = [&](const double* q, double wgt, double* qb) {
     const double r = q[3];
     if (!(r > 0.0)) return;
-    const double u = v[Dirs<DIR>::n], ta = v[Dirs<DIR>::t1], tb = v[Dirs<DIR>::t2];
-    const double rb = wgt * (flb[0] * u + flb[1] * u * u + flb[2] * u * ta + flb[3] * u * tb);
-    const double ub = wgt * (flb[0] * r + 2.0 * flb[1] * r * u + flb[2] * r * ta + flb[3] * r * tb);
-    const double ab = wgt * flb[2] * r * u, bb = wgt * flb[3] * r * u;
-    qb[Dirs<DIR>::n] += ub * inv;
-    qb[Dirs<DIR>::t1] += ab * inv;
-    qb[Dirs<DIR>::t2] += bb * inv;
-    qb[3] += rb - inv * (ub * u + ab * ta + bb * tb);
+    const double u = q[N], ta = q[T1], tb = q[T2];
+    qb[3] += wgt * (flb[0] * u + flb[1] * u * u + flb[2] * u * ta + flb[3] * u * tb);
+    qb[N] += wgt * (flb[0] * r + 2.0 * flb[1] * r * u + flb[2] * r * ta + flb[3] * r * tb);
+    qb[T1] += wgt * flb[2] * r * u;
+    qb[T2] += wgt * flb[3] * r * u;
   };
-  if (side == -1) side_rev(qL, vL, iL, 1.0, qLb);
-  else if (side == 1) side_rev(qR, vR, iR, 1.0, qRb);
+  if (side == -1) side_rev(qL, 1.0, qLb);
+  else if (side == 1) side_rev(qR, 1.0, qRb);
   else if (side == 0) {
-    side_rev(qL, vL, iL, 0.5, qLb);
-    side_rev(qR, vR, iR, 0.5, qRb);
+    side_rev(qL, 0.5, qLb);
+    side_rev(qR, 0.5, qRb);
   }
 #pragma unroll
   for (int f = 0; f < 4; ++f) {
@@ -462,15 +438,23 @@ struct AdjCtx {
 };
 
 template <int D, bool GAS, bool G75>
-__device__ __forceinline__ void face_vjp(const GasC& gc, const double* eA, const double* eB,
-                                         const double* eC, const double* eD, const double* coB,
-                                         const double* coC, const double* bgf, const double* cB,
-                                         double sB, const double* cC, double sC, const double* Fb,
-                                         double* oA, double* oB, double* oC, double* oD) {
+__device__ __forceinline__ void face_vjp(const GasC& gc, const double* wA, const double* wB,
+                                         const double* wC, const double* wD, const double* coB,
+                                         const double* coC, const double* bf, const double* bB,
+                                         const double* bC, const double* Fb, double* oA,
+                                         double* oB, double* oC, double* oD) {
   if constexpr (GAS)
-    gas_face_vjp<D, G75>(gc, eA, eB, eC, eD, coB, coC, bgf, cB, sB, cC, sC, Fb, oA, oB, oC, oD);
+    gas_face_vjp<D, G75>(gc, wA, wB, wC, wD, coB, coC, bf, bB, bC, Fb, oA, oB, oC, oD);
   else
-    dust_face_vjp<D>(eA, eB, eC, eD, coB, coC, Fb, oA, oB, oC, oD);
+    dust_face_vjp<D>(wA, wB, wC, wD, coB, coC, Fb, oA, oB, oC, oD);
+}
+
+// cotangent of a cell's reconstructed variables w (stationary flow b) -> conservative
+template <bool GAS>
+__device__ __forceinline__ void cot_to_cons(const double* w, const double* b, double gm1,
+                                            const double* wb, double* eb) {
+  if constexpr (GAS) gas_cot_to_cons(w, b, gm1, wb, eb);
+  else dust_cot_to_cons(w, wb, eb);
 }
 
 template <bool GAS, int ND, bool G75>
@@ -525,9 +509,9 @@ __global__ void __launch_bounds__(NT) k_adj_plane(AdjArgs A, int species) {
       Fb[f] = ath * (X.wc(f, k, i, jc) - X.wc(f, k, i, jb));
       oA[f] = 0.0; oB[f] = 0.0; oC[f] = 0.0; oD[f] = 0.0;
     }
-    const double* bgf = a.t.bgc + ((size_t)k * g.nr + i) * 5;
-    face_vjp<DT::value, GAS, G75>(X.gc, eA, eB, eC, eD, nullptr, nullptr, bgf, bgf, 1.0, bgf, 1.0,
-                                  Fb, oA, oB, oC, oD);
+    const double* bf = a.t.wc + ((size_t)k * g.nr + i) * WB_N;
+    face_vjp<DT::value, GAS, G75>(X.gc, eA, eB, eC, eD, nullptr, nullptr, bf, bf, bf, Fb, oA, oB,
+                                  oC, oD);
   };
   // r face between tile rows rb and rb + 1 (s_e row rb + H) of tile column cl
   auto r_face = [&](int k, int rb, int cl, double* oA, double* oB, double* oC, double* oD) {
@@ -542,12 +526,9 @@ __global__ void __launch_bounds__(NT) k_adj_plane(AdjArgs A, int species) {
       Fb[f] = ar * (X.wc(f, k, ib + 1, j) - X.wc(f, k, ib, j));
       oA[f] = 0.0; oB[f] = 0.0; oC[f] = 0.0; oD[f] = 0.0;
     }
-    const double* bgf = a.t.bgr + ((size_t)k * (g.nr + 1) + (ib + 1)) * 5;
-    double sB = 1.0, sC = 1.0;
-    const double* cB = GAS ? centre_ptr(a, k, ib, sB) : nullptr;
-    const double* cC = GAS ? centre_ptr(a, k, ib + 1, sC) : nullptr;
-    face_vjp<DR::value, GAS, G75>(X.gc, eA, eB, eC, eD, rco_ptr(a, ib), rco_ptr(a, ib + 1), bgf,
-                                  cB, sB, cC, sC, Fb, oA, oB, oC, oD);
+    const double* bf = a.t.wr + ((size_t)k * (g.nr + 1) + (ib + 1)) * WB_N;
+    face_vjp<DR::value, GAS, G75>(X.gc, eA, eB, eC, eD, rco_ptr(a, ib), rco_ptr(a, ib + 1), bf,
+                                  bg_ptr(a, k, ib), bg_ptr(a, k, ib + 1), Fb, oA, oB, oC, oD);
   };
 
   double stb = 0.0;  // Stokes-number partial (dust)
@@ -559,8 +540,8 @@ __global__ void __launch_bounds__(NT) k_adj_plane(AdjArgs A, int species) {
       static_assert(NC <= 2 * NT, "two staged cells per thread");
       const int h0 = tid, h1 = tid + NT;
       double v0[NG], v1[NG];
-      fetch_all<false, false, NG>(a, E, F0, k, i0 + h0 / W - H, X.jwrap(j0 + h0 % W - H), v0);
-      if (h1 < NC) fetch_all<false, false, NG>(a, E, F0, k, i0 + h1 / W - H, X.jwrap(j0 + h1 % W - H), v1);
+      load_recon<false, false, NG>(a, E, F0, k, i0 + h0 / W - H, X.jwrap(j0 + h0 % W - H), v0);
+      if (h1 < NC) load_recon<false, false, NG>(a, E, F0, k, i0 + h1 / W - H, X.jwrap(j0 + h1 % W - H), v1);
 #pragma unroll
       for (int f = 0; f < NG; ++f) s_e[f][h0 / W][h0 % W] = v0[f];
       if (h1 < NC) {
@@ -633,8 +614,16 @@ __global__ void __launch_bounds__(NT) k_adj_plane(AdjArgs A, int species) {
     // ---- in-plane total of the thread's cell, the reverse of its sources, the bases
     if (!act) continue;
     double cur[NG];
+    {
+      // in-plane faces' cotangent of the cell's reconstructed variables -> conservative
+      double wb[NG], w[NG];
 #pragma unroll
-    for (int f = 0; f < NG; ++f) cur[f] = s_at[f][ti][tj] + s_ar[f][ti][tj];
+      for (int f = 0; f < NG; ++f) {
+        wb[f] = s_at[f][ti][tj] + s_ar[f][ti][tj];
+        w[f] = s_e[f][ti + H][tj + H];
+      }
+      cot_to_cons<GAS>(w, a.t.wc + ((size_t)k * g.nr + ig) * WB_N, X.gc.gm1, wb, cur);
+    }
     const size_t cell = ((size_t)k * g.nr + ig) * g.nth + jg;
     const double gr = a.t.grav[((size_t)k * g.nr + ig) * 2 + 0];
     const double gz = a.t.grav[((size_t)k * g.nr + ig) * 2 + 1];
@@ -766,28 +755,26 @@ __global__ void __launch_bounds__(256) k_adj_z(AdjArgs A, int species, int tkz) 
   const double Az = a.t.rt[(size_t)ig * RT_N + RT_AZ];
 
   double ra[NG], rb[NG], rc[NG], rd[NG];  // cells kf-1 .. kf+2 of the face kf+1/2
-  auto load = [&](double* dst, int k) {
-#pragma unroll
-    for (int f = 0; f < NG; ++f) dst[f] = fetch<false>(a, E, F0 + f, k, ig, jg);
-  };
+  auto load = [&](double* dst, int k) { load_recon<false, false, NG>(a, E, F0, k, ig, jg, dst); };
   // adds the face's contributions into oA..oD
   auto zface = [&](int kf, double* oA, double* oB, double* oC, double* oD) {
     double Fb[NG];
 #pragma unroll
     for (int f = 0; f < NG; ++f) Fb[f] = Az * (X.wc(f, kf + 1, ig, jg) - X.wc(f, kf, ig, jg));
-    double sB = 1.0, sC = 1.0;
-    const double* cB = GAS ? centre_ptr(a, kf, ig, sB) : nullptr;
-    const double* cC = GAS ? centre_ptr(a, kf + 1, ig, sC) : nullptr;
-    const double* bgf = a.t.bgz + ((size_t)(kf + 1) * g.nr + ig) * 5;
-    face_vjp<2, GAS, G75>(X.gc, ra, rb, rc, rd, nullptr, nullptr, bgf, cB, sB, cC, sC, Fb, oA, oB,
-                          oC, oD);
+    const double* bf = a.t.wz + ((size_t)(kf + 1) * g.nr + ig) * WB_N;
+    face_vjp<2, GAS, G75>(X.gc, ra, rb, rc, rd, nullptr, nullptr, bf, bg_ptr(a, kf, ig),
+                          bg_ptr(a, kf + 1, ig), Fb, oA, oB, oC, oD);
   };
   auto real = [&](int kf) { return kf >= -1 && kf <= g.nz - 1; };
-  auto add_out = [&](int k, const double* v) {
+  // adds the z faces' cotangent v of cell k's reconstructed variables (w: the cell's W')
+  // to the cell's conservative cotangent
+  auto add_out = [&](int k, const double* w, const double* v) {
     const size_t cell = ((size_t)k * g.nr + ig) * g.nth + jg;
+    double ec[NG];
+    cot_to_cons<GAS>(w, a.t.wc + ((size_t)k * g.nr + ig) * WB_N, X.gc.gm1, v, ec);
     double o[NG];
 #pragma unroll
-    for (int f = 0; f < NG; ++f) o[f] = A.out[(size_t)(F0 + f) * g.N + cell] + v[f];
+    for (int f = 0; f < NG; ++f) o[f] = A.out[(size_t)(F0 + f) * g.N + cell] + ec[f];
 #pragma unroll
     for (int f = 0; f < NG; ++f) A.out[(size_t)(F0 + f) * g.N + cell] = o[f];
   };
@@ -820,7 +807,7 @@ __global__ void __launch_bounds__(256) k_adj_z(AdjArgs A, int species, int tkz) 
     load(rd, k + 2);
     // face k+1/2 (cells k-1, k, k+1, k+2)
     if (real(k)) zface(k, za, zb, zc, zd);
-    if (k - 1 >= k0) add_out(k - 1, za);
+    if (k - 1 >= k0) add_out(k - 1, ra, za);
 #pragma unroll
     for (int f = 0; f < NG; ++f) { za[f] = zb[f]; zb[f] = zc[f]; zc[f] = zd[f]; zd[f] = 0.0; }
   }

@@ -133,12 +133,15 @@ Layout make_layout(const rb_config& c) {
   L.bgc = take(nz * nr * 5);
   L.bgr = take(nz * (nr + 1) * 5);
   L.bgz = take((nz + 1) * nr * 5);
+  L.wc = take(nz * nr * WB_N);
+  L.wr = take(nz * (nr + 1) * WB_N);
+  L.wz = take((nz + 1) * nr * WB_N);
   L.r0 = take(nz * nr * 5);
   L.grav = take(nz * nr * 2);
   L.ghr = take(4 * nz * nf);
-  L.ghrf = take(2 * nz * 5);
+  L.ghrw = take(4 * nz * WB_N);
   L.ghz = take(4 * nr * nf);
-  L.ghzf = take(2 * nr * 5);
+  L.ghzw = take(4 * nr * WB_N);
   L.trig = take(2 * nth);
   L.indw = take(nz * nr);
   L.indab = take(2);
@@ -186,7 +189,8 @@ StageArgs base_args(rb_ctx* x) {
   double* w = x->work;
   a.t.rt = w + L.rt; a.t.ar = w + L.ar; a.t.rco = w + L.rco; a.t.bgc = w + L.bgc;
   a.t.bgr = w + L.bgr; a.t.bgz = w + L.bgz; a.t.r0 = w + L.r0; a.t.grav = w + L.grav;
-  a.t.ghr = w + L.ghr; a.t.ghrf = w + L.ghrf; a.t.ghz = w + L.ghz; a.t.ghzf = w + L.ghzf;
+  a.t.wc = w + L.wc; a.t.wr = w + L.wr; a.t.wz = w + L.wz;
+  a.t.ghr = w + L.ghr; a.t.ghrw = w + L.ghrw; a.t.ghz = w + L.ghz; a.t.ghzw = w + L.ghzw;
   a.t.trig = w + L.trig; a.t.indw = w + L.indw; a.t.indab = w + L.indab;
   a.t.damp = w + L.damp;
   a.t.ozr = w + L.ozr;

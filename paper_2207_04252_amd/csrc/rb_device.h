@@ -424,118 +424,94 @@ template <int DIR> struct Dirs {
   static constexpr int t2 = DIR == 2 ? 1 : 2;
 };
 
-struct Prim5 {
-  double rho, irho, un, t1, t2, p;
-};
+// ------------------------------------------------------------------------------------
+// Face states and fluxes.  The parabola and MinMod limiter of Sect. 2.7 act on the
+// primitive form of the variables: the gas velocity, pressure and density as deviations
+// W' = W(E) - W(E0) from the stationary flow, each dust fluid's velocity and density
+// whole.  A gas face state is W0(face) + W'(cell) + limited increment; only the flux of
+// the Riemann solution, F* = F(E*), is formed from the face states (Sect. 2.6).
 
-template <int DIR>
-__device__ __forceinline__ Prim5 gas_prim(const double q[5], double gm1) {
-  Prim5 w;
-  double inv = frcp(q[4]);
-  w.irho = inv;
-  double u = q[0] * inv, v = q[1] * inv, z = q[2] * inv;
-  w.rho = q[4];
-  w.p = gm1 * (q[3] - 0.5 * (q[0] * u + q[1] * v + q[2] * z));
-  double vel[3] = {u, v, z};
-  w.un = vel[Dirs<DIR>::n];
-  w.t1 = vel[Dirs<DIR>::t1];
-  w.t2 = vel[Dirs<DIR>::t2];
-  return w;
-}
-
-// Reconstructed gas face states (Sect. 2.7: E0 at the face + E' + limited parabola
-// increment), positivity fallback to the cell-centre state, exact Riemann problem,
-// F* = F(E*) in field order.  Cells A, B | C, D along DIR; the face lies between B and C.
+// Reconstructed gas face states, positivity fallback to the cell-centre state
+// W0(cell) + W'(cell), exact Riemann problem, F* in field order.  Cells A, B | C, D along
+// DIR (the face lies between B and C), given by their W' in field slots (u, v, w, P, rho);
+// bf: the stationary flow at the face, bB / bC: at the centres of B and C (WB_N entries).
 template <int DIR, bool G75>
-__device__ __forceinline__ void gas_face(const GasC& c, const double* eA, const double* eB,
-                                         const double* eC, const double* eD, const double* coB,
-                                         const double* coC, const double* bgf, const double* cenB,
-                                         double sB, const double* cenC, double sC, double F[5],
-                                         TStat& st) {
+__device__ __forceinline__ void gas_face(const GasC& c, const double* wA, const double* wB,
+                                         const double* wC, const double* wD, const double* coB,
+                                         const double* coC, const double* bf, const double* bB,
+                                         const double* bC, double F[5], TStat& st) {
   double qL[5], qR[5];
 #pragma unroll
   for (int f = 0; f < 5; ++f) {
     double iB, iC;
     if (DIR == 0) {
-      iB = inc_up_c(eA[f], eB[f], eC[f], coB);
-      iC = inc_lo_c(eB[f], eC[f], eD[f], coC);
+      iB = inc_up_c(wA[f], wB[f], wC[f], coB);
+      iC = inc_lo_c(wB[f], wC[f], wD[f], coC);
     } else {
-      iB = inc_up_u(eA[f], eB[f], eC[f]);
-      iC = inc_lo_u(eB[f], eC[f], eD[f]);
+      iB = inc_up_u(wA[f], wB[f], wC[f]);
+      iC = inc_lo_u(wB[f], wC[f], wD[f]);
     }
-    qL[f] = bgf[f] + (eB[f] + iB);
-    qR[f] = bgf[f] + (eC[f] + iC);
+    qL[f] = bf[f] + (wB[f] + iB);
+    qR[f] = bf[f] + (wC[f] + iC);
   }
-  Prim5 L = gas_prim<DIR>(qL, c.gm1);
-  Prim5 R = gas_prim<DIR>(qR, c.gm1);
-  if (!(L.rho > 0.0 && L.p > 0.0)) {
+  if (!(qL[4] > 0.0 && qL[3] > 0.0)) {
 #pragma unroll
-    for (int f = 0; f < 5; ++f) qL[f] = cenB[f] + sB * eB[f];
-    L = gas_prim<DIR>(qL, c.gm1);
+    for (int f = 0; f < 5; ++f) qL[f] = bB[f] + wB[f];
     st.fall++;
   }
-  if (!(R.rho > 0.0 && R.p > 0.0)) {
+  if (!(qR[4] > 0.0 && qR[3] > 0.0)) {
 #pragma unroll
-    for (int f = 0; f < 5; ++f) qR[f] = cenC[f] + sC * eC[f];
-    R = gas_prim<DIR>(qR, c.gm1);
+    for (int f = 0; f < 5; ++f) qR[f] = bC[f] + wC[f];
     st.fall++;
   }
+  constexpr int N = Dirs<DIR>::n, T1 = Dirs<DIR>::t1, T2 = Dirs<DIR>::t2;
   double fl[5];
-  gas_riemann<G75>(c, L.rho, L.irho, L.un, L.t1, L.t2, L.p, R.rho, R.irho, R.un, R.t1, R.t2, R.p,
-                   fl, st);
+  gas_riemann<G75>(c, qL[4], frcp(qL[4]), qL[N], qL[T1], qL[T2], qL[3], qR[4], frcp(qR[4]), qR[N],
+                   qR[T1], qR[T2], qR[3], fl, st);
   F[4] = fl[0];
-  F[Dirs<DIR>::n] = fl[1];
-  F[Dirs<DIR>::t1] = fl[2];
-  F[Dirs<DIR>::t2] = fl[3];
+  F[N] = fl[1];
+  F[T1] = fl[2];
+  F[T2] = fl[3];
   F[3] = fl[4];
 }
 
-// Dust face: the dust variables are reconstructed whole (no stationary reference);
-// a face density below zero falls back to the cell-centre state.
+// Dust face: velocity and density reconstructed whole (no stationary reference); a face
+// density below zero falls back to the cell-centre state.
 template <int DIR>
-__device__ __forceinline__ void dust_face(const double* eA, const double* eB, const double* eC,
-                                          const double* eD, const double* coB, const double* coC,
+__device__ __forceinline__ void dust_face(const double* wA, const double* wB, const double* wC,
+                                          const double* wD, const double* coB, const double* coC,
                                           double F[4], TStat& st) {
   double qL[4], qR[4];
 #pragma unroll
   for (int f = 0; f < 4; ++f) {
     double iB, iC;
     if (DIR == 0) {
-      iB = inc_up_c(eA[f], eB[f], eC[f], coB);
-      iC = inc_lo_c(eB[f], eC[f], eD[f], coC);
+      iB = inc_up_c(wA[f], wB[f], wC[f], coB);
+      iC = inc_lo_c(wB[f], wC[f], wD[f], coC);
     } else {
-      iB = inc_up_u(eA[f], eB[f], eC[f]);
-      iC = inc_lo_u(eB[f], eC[f], eD[f]);
+      iB = inc_up_u(wA[f], wB[f], wC[f]);
+      iC = inc_lo_u(wB[f], wC[f], wD[f]);
     }
-    qL[f] = eB[f] + iB;
-    qR[f] = eC[f] + iC;
+    qL[f] = wB[f] + iB;
+    qR[f] = wC[f] + iC;
   }
   if (qL[3] < 0.0) {
 #pragma unroll
-    for (int f = 0; f < 4; ++f) qL[f] = eB[f];
+    for (int f = 0; f < 4; ++f) qL[f] = wB[f];
     st.fall++;
   }
   if (qR[3] < 0.0) {
 #pragma unroll
-    for (int f = 0; f < 4; ++f) qR[f] = eC[f];
+    for (int f = 0; f < 4; ++f) qR[f] = wC[f];
     st.fall++;
   }
-  double vL[3] = {0.0, 0.0, 0.0}, vR[3] = {0.0, 0.0, 0.0};
-  if (qL[3] > 0.0) {
-    double inv = 1.0 / qL[3];
-    vL[0] = qL[0] * inv; vL[1] = qL[1] * inv; vL[2] = qL[2] * inv;
-  }
-  if (qR[3] > 0.0) {
-    double inv = 1.0 / qR[3];
-    vR[0] = qR[0] * inv; vR[1] = qR[1] * inv; vR[2] = qR[2] * inv;
-  }
+  constexpr int N = Dirs<DIR>::n, T1 = Dirs<DIR>::t1, T2 = Dirs<DIR>::t2;
   double fl[4];
-  dust_riemann(qL[3], vL[Dirs<DIR>::n], vL[Dirs<DIR>::t1], vL[Dirs<DIR>::t2], qR[3],
-               vR[Dirs<DIR>::n], vR[Dirs<DIR>::t1], vR[Dirs<DIR>::t2], fl);
+  dust_riemann(qL[3], qL[N], qL[T1], qL[T2], qR[3], qR[N], qR[T1], qR[T2], fl);
   F[3] = fl[0];
-  F[Dirs<DIR>::n] = fl[1];
-  F[Dirs<DIR>::t1] = fl[2];
-  F[Dirs<DIR>::t2] = fl[3];
+  F[N] = fl[1];
+  F[T1] = fl[2];
+  F[T2] = fl[3];
 }
 
 }  // namespace rb
@@ -544,34 +520,34 @@ __device__ __forceinline__ void dust_face(const double* eA, const double* eB, co
 
 namespace rb {
 
-// FP32-perturbation gas face: reconstructed perturbations about the face background,
-// the perturbation Riemann problem and the flux change dF = F* - F(W0); faces the FP32
-// form cannot take (strong perturbation, transonic fan, no convergence, non-positive
-// face state) are re-solved in FP64 on the full states.
+// FP32-perturbation gas face: reconstructed W' about the face's stationary flow, the
+// perturbation Riemann problem and the flux change dF = F* - F(W0); faces the FP32 form
+// cannot take (strong perturbation, transonic fan, no convergence, non-positive face
+// state) are re-solved in FP64 on the full states.
 template <int DIR>
-__device__ __forceinline__ void gas_face_p32(const GasC& c, const float* eA, const float* eB,
-                                             const float* eC, const float* eD, const double* coB,
-                                             const double* coC, const double* bgf,
-                                             const double* cenB, double sB, const double* cenC,
-                                             double sC, float F[5], TStat& st) {
+__device__ __forceinline__ void gas_face_p32(const GasC& c, const float* wA, const float* wB,
+                                             const float* wC, const float* wD, const double* coB,
+                                             const double* coC, const double* bf,
+                                             const double* bB, const double* bC, float F[5],
+                                             TStat& st) {
   float qL[5], qR[5];
 #pragma unroll
   for (int f = 0; f < 5; ++f) {
     float iB, iC;
     if (DIR == 0) {
-      iB = inc_up_c<float>(eA[f], eB[f], eC[f], coB);
-      iC = inc_lo_c<float>(eB[f], eC[f], eD[f], coC);
+      iB = inc_up_c<float>(wA[f], wB[f], wC[f], coB);
+      iC = inc_lo_c<float>(wB[f], wC[f], wD[f], coC);
     } else {
-      iB = inc_up_u<float>(eA[f], eB[f], eC[f]);
-      iC = inc_lo_u<float>(eB[f], eC[f], eD[f]);
+      iB = inc_up_u<float>(wA[f], wB[f], wC[f]);
+      iC = inc_lo_u<float>(wB[f], wC[f], wD[f]);
     }
-    qL[f] = eB[f] + iB;
-    qR[f] = eC[f] + iC;
+    qL[f] = wB[f] + iB;
+    qR[f] = wC[f] + iC;
   }
-  const BgW b = bg_prims<DIR>(bgf, c.g);
-  const float gm1 = (float)c.gm1;
-  const PW L = pert_prims<DIR>(b, qL, gm1);
-  const PW R = pert_prims<DIR>(b, qR, gm1);
+  constexpr int N = Dirs<DIR>::n, T1 = Dirs<DIR>::t1, T2 = Dirs<DIR>::t2;
+  const BgW b = bg_face<DIR>(bf);
+  const PW L = {qL[4], qL[N], qL[T1], qL[T2], qL[3]};
+  const PW R = {qR[4], qR[N], qR[T1], qR[T2], qR[3]};
   const bool okL = (b.rho + (double)L.rho > 0.0) && (b.p + (double)L.p > 0.0);
   const bool okR = (b.rho + (double)R.rho > 0.0) && (b.p + (double)R.p > 0.0);
   PW W;
@@ -580,19 +556,17 @@ __device__ __forceinline__ void gas_face_p32(const GasC& c, const float* eA, con
     flux_pert(b, W, (float)c.inv_gm1, fl);
   } else {
     st.resolve++;
-    double qL64[5], qR64[5];
+    double xL[5], xR[5];
 #pragma unroll
     for (int f = 0; f < 5; ++f) {
-      qL64[f] = okL ? bgf[f] + (double)qL[f] : cenB[f] + sB * (double)eB[f];
-      qR64[f] = okR ? bgf[f] + (double)qR[f] : cenC[f] + sC * (double)eC[f];
+      xL[f] = okL ? bf[f] + (double)qL[f] : bB[f] + (double)wB[f];
+      xR[f] = okR ? bf[f] + (double)qR[f] : bC[f] + (double)wC[f];
     }
     if (!okL) st.fall++;
     if (!okR) st.fall++;
-    const Prim5 PL = gas_prim<DIR>(qL64, c.gm1);
-    const Prim5 PR = gas_prim<DIR>(qR64, c.gm1);
     double f64[5];
-    gas_riemann<true>(c, PL.rho, PL.irho, PL.un, PL.t1, PL.t2, PL.p, PR.rho, PR.irho, PR.un, PR.t1,
-                      PR.t2, PR.p, f64, st);
+    gas_riemann<true>(c, xL[4], frcp(xL[4]), xL[N], xL[T1], xL[T2], xL[3], xR[4], frcp(xR[4]),
+                      xR[N], xR[T1], xR[T2], xR[3], f64, st);
     const double m0 = b.rho * b.un;
     fl[0] = (float)(f64[0] - m0);
     fl[1] = (float)(f64[1] - (m0 * b.un + b.p));
@@ -601,9 +575,9 @@ __device__ __forceinline__ void gas_face_p32(const GasC& c, const float* eA, con
     fl[4] = (float)(f64[4] - b.h * b.un);
   }
   F[4] = fl[0];
-  F[Dirs<DIR>::n] = fl[1];
-  F[Dirs<DIR>::t1] = fl[2];
-  F[Dirs<DIR>::t2] = fl[3];
+  F[N] = fl[1];
+  F[T1] = fl[2];
+  F[T2] = fl[3];
   F[3] = fl[4];
 }
 
@@ -619,7 +593,8 @@ __device__ __forceinline__ size_t p32_f64_base(const Geo& g) {
   return (((size_t)(5 + 3 * g.nd) * g.N + 63) / 64 * 64) / 2;
 }
 
-// interior value of field f (FP64 storage, or the FP32-perturbation layout above)
+// interior conservative value of field f (FP64 storage: the gas deviation E' and the dust
+// variables; or the FP32-perturbation layout above)
 template <bool P32>
 __device__ __forceinline__ double ld_cell(const StageArgs& a, const void* st, int f, int k, int i,
                                           size_t cell) {
@@ -663,72 +638,144 @@ __device__ __forceinline__ void st_dust32(const StageArgs& a, void* st, int sp, 
   for (int c = 0; c < 3; ++c) vel[(size_t)c * g.N] = v[3] > 1e-300 ? (float)(v[c] * ir) : 0.0f;
 }
 
-// EXT: the optional physics and boundary options (outflow ghosts here) may be active; the
-// base instantiation compiles them out.
-template <bool P32, bool EXT = false>
-__device__ __forceinline__ double fetch(const StageArgs& a, const void* st, int f, int k, int i,
-                                        int j) {
+// All NG conservative fields of a group at an interior cell: the gas deviation E', the
+// dust momenta and density.
+template <bool P32, int NG>
+__device__ __forceinline__ void load_cons(const StageArgs& a, const void* st, int F0, int k, int i,
+                                          int j, double* out) {
   const Geo& g = a.g;
-  if (k < 0 || k >= g.nz) {
-    int ii = min(max(i, 0), g.nr - 1);
-    int side = k < 0 ? 0 : 1;
-    int layer = min(k < 0 ? -1 - k : k - g.nz, 1);
-    if (EXT && g.bc_z == 1) {
-      // outflow: the boundary cell's dust variables, and its gas deviation carried at the
-      // same fraction of the stationary density
-      const int kb = k < 0 ? 0 : g.nz - 1;
-      const double v = ld_cell<P32>(a, st, f, kb, ii, ((size_t)kb * g.nr + ii) * g.nth + j);
-      return f < 5 ? v * a.t.ozr[(size_t)(side * 2 + layer) * g.nr + ii] : v;
-    }
-    return a.t.ghz[((size_t)(side * 2 + layer) * g.nr + ii) * g.nf + f];
-  }
-  if (i < 0 || i >= g.nr) {
-    int side = i < 0 ? 0 : 1;
-    int layer = min(i < 0 ? -1 - i : i - g.nr, 1);
-    return a.t.ghr[((size_t)(side * 2 + layer) * g.nz + k) * g.nf + f];
-  }
-  return ld_cell<P32>(a, st, f, k, i, ((size_t)k * g.nr + i) * g.nth + j);
-}
-
-// All NG reconstructed fields of a group at one cell.  A dust group in the FP32 layout
-// reads its density once for the three momenta (density x stored velocity).
-template <bool P32, bool EXT, int NG, class T>
-__device__ __forceinline__ void fetch_all(const StageArgs& a, const void* st, int F0, int k, int i,
-                                          int j, T* out) {
-  const Geo& g = a.g;
+  const size_t cell = ((size_t)k * g.nr + i) * g.nth + j;
   if constexpr (P32 && NG == 4) {
-    if (k >= 0 && k < g.nz && i >= 0 && i < g.nr) {
-      const size_t cell = ((size_t)k * g.nr + i) * g.nth + j;
-      const int sp = (F0 - 5) >> 2;
-      const double rd = ((const double*)st)[p32_f64_base(g) + (size_t)sp * g.N + cell];
-      const float* vel = (const float*)st + (size_t)(5 + 3 * sp) * g.N + cell;
-      out[0] = (T)(rd * (double)vel[0]);
-      out[1] = (T)(rd * (double)vel[g.N]);
-      out[2] = (T)(rd * (double)vel[2 * g.N]);
-      out[3] = (T)rd;
-      return;
-    }
+    const int sp = (F0 - 5) >> 2;
+    const double rd = ((const double*)st)[p32_f64_base(g) + (size_t)sp * g.N + cell];
+    const float* vel = (const float*)st + (size_t)(5 + 3 * sp) * g.N + cell;
+    out[0] = rd * (double)vel[0];
+    out[1] = rd * (double)vel[g.N];
+    out[2] = rd * (double)vel[2 * g.N];
+    out[3] = rd;
+    return;
   }
 #pragma unroll
-  for (int f = 0; f < NG; ++f) out[f] = (T)fetch<P32, EXT>(a, st, F0 + f, k, i, j);
+  for (int f = 0; f < NG; ++f) out[f] = ld_cell<P32>(a, st, F0 + f, k, i, cell);
 }
 
-// centre state used by the gas fallback: E0(centre) + E' for interior cells and outflow
-// z ghosts (scale 1), the ghost's full state (scale 0) otherwise
-template <bool EXT = false>
-__device__ __forceinline__ const double* centre_ptr(const StageArgs& a, int k, int i, double& s) {
+// Gas deviation W' = W(E0 + E') - W(E0) of a cell from its conservative deviation e and
+// its stationary flow b (WB_N entry), free of cancellation: rho' = e_rho,
+// u' = (m' - u0 rho') / rho, P' = (g - 1)(E' - dKE) with the kinetic-energy change
+// dKE = rho' |u0|^2 / 2 + rho u0.u' + rho |u'|^2 / 2.  Exactly zero for e = 0; for the Sod
+// annulus (b = 0) it is the state's own primitives.
+__device__ __forceinline__ void cell_w(const double* e, const double* b, double gm1, double* w) {
+  const double rp = e[4];
+  const double rho = b[WB_RHO] + rp;
+  const double ir = frcp(rho);
+  const double u0 = b[WB_U], v0 = b[WB_V], w0 = b[WB_W];
+  const double up = (e[0] - u0 * rp) * ir, vp = (e[1] - v0 * rp) * ir, wp = (e[2] - w0 * rp) * ir;
+  const double dke = 0.5 * rp * (u0 * u0 + v0 * v0 + w0 * w0) + rho * (u0 * up + v0 * vp + w0 * wp) +
+                     0.5 * rho * (up * up + vp * vp + wp * wp);
+  w[0] = up; w[1] = vp; w[2] = wp;
+  w[3] = gm1 * (e[3] - dke);
+  w[4] = rp;
+}
+__device__ __forceinline__ void cell_w(const float* e, const double* b, float gm1, float* w) {
+  const float rp = e[4];
+  const float rho = (float)(b[WB_RHO] + (double)rp);
+  const float ir = rcp32(rho);
+  const float u0 = (float)b[WB_U], v0 = (float)b[WB_V], w0 = (float)b[WB_W];
+  const float u0sq = (float)(b[WB_U] * b[WB_U] + b[WB_V] * b[WB_V] + b[WB_W] * b[WB_W]);
+  const float up = (e[0] - u0 * rp) * ir, vp = (e[1] - v0 * rp) * ir, wp = (e[2] - w0 * rp) * ir;
+  const float dke = 0.5f * rp * u0sq + rho * (u0 * up + v0 * vp + w0 * wp) +
+                    0.5f * rho * (up * up + vp * vp + wp * wp);
+  w[0] = up; w[1] = vp; w[2] = wp;
+  w[3] = gm1 * (e[3] - dke);
+  w[4] = rp;
+}
+
+// Reconstructed variables of a group at any cell, interior or ghost: the gas W', or the
+// dust velocity (zero where the density is not positive) and density.  EXT: the optional
+// boundary options may be active (outflow z ghosts carry the boundary cell's gas
+// deviation E' scaled by the ratio of the stationary densities, and its dust variables);
+// the base instantiation compiles them out.
+template <bool P32, bool EXT, int NG, class T>
+__device__ __forceinline__ void load_recon(const StageArgs& a, const void* st, int F0, int k,
+                                           int i, int j, T* out) {
+  const Geo& g = a.g;
+  constexpr bool GAS = NG == 5;
+  int kc = k;             // interior cell whose data are read
+  double scale = 1.0;     // outflow: gas deviation scale
+  const double* bw = nullptr;
+  if (k < 0 || k >= g.nz) {
+    const int ii = min(max(i, 0), g.nr - 1);
+    const int side = k < 0 ? 0 : 1;
+    const int layer = min(k < 0 ? -1 - k : k - g.nz, 1);
+    if (!(EXT && g.bc_z == 1)) {
+      const double* gt = a.t.ghz + ((size_t)(side * 2 + layer) * g.nr + ii) * g.nf + F0;
+#pragma unroll
+      for (int f = 0; f < NG; ++f) out[f] = (T)gt[f];
+      return;
+    }
+    kc = k < 0 ? 0 : g.nz - 1;
+    i = ii;
+    scale = a.t.ozr[(size_t)(side * 2 + layer) * g.nr + ii];
+    bw = a.t.ghzw + ((size_t)(side * 2 + layer) * g.nr + ii) * WB_N;
+  } else if (i < 0 || i >= g.nr) {
+    const int side = i < 0 ? 0 : 1;
+    const int layer = min(i < 0 ? -1 - i : i - g.nr, 1);
+    const double* gt = a.t.ghr + ((size_t)(side * 2 + layer) * g.nz + k) * g.nf + F0;
+#pragma unroll
+    for (int f = 0; f < NG; ++f) out[f] = (T)gt[f];
+    return;
+  }
+  const size_t cell = ((size_t)kc * g.nr + i) * g.nth + j;
+  if constexpr (GAS) {
+    if (!bw) bw = a.t.wc + ((size_t)kc * g.nr + i) * WB_N;
+    if constexpr (std::is_same<T, float>::value && P32) {
+      float e[5];
+#pragma unroll
+      for (int f = 0; f < 5; ++f) e[f] = ((const float*)st)[(size_t)f * g.N + cell];
+      if (EXT && scale != 1.0) {
+#pragma unroll
+        for (int f = 0; f < 5; ++f) e[f] = (float)((double)e[f] * scale);
+      }
+      cell_w(e, bw, (float)(g.gamma - 1.0), out);
+    } else {
+      double e[5], w[5];
+#pragma unroll
+      for (int f = 0; f < 5; ++f) e[f] = ld_cell<P32>(a, st, f, kc, i, cell) * scale;
+      cell_w(e, bw, g.gamma - 1.0, w);
+#pragma unroll
+      for (int f = 0; f < 5; ++f) out[f] = (T)w[f];
+    }
+  } else {
+    const int sp = (F0 - 5) >> 2;
+    if constexpr (P32) {
+      // the FP32 layout stores the dust velocities themselves
+      const float* vel = (const float*)st + (size_t)(5 + 3 * sp) * g.N + cell;
+      out[0] = (T)vel[0];
+      out[1] = (T)vel[g.N];
+      out[2] = (T)vel[2 * g.N];
+      out[3] = (T)((const double*)st)[p32_f64_base(g) + (size_t)sp * g.N + cell];
+    } else {
+      const double* d = (const double*)st + (size_t)F0 * g.N + cell;
+      const double rd = d[3 * g.N];
+      const double id = rd > 0.0 ? 1.0 / rd : 0.0;
+      out[0] = (T)(d[0] * id);
+      out[1] = (T)(d[g.N] * id);
+      out[2] = (T)(d[2 * g.N] * id);
+      out[3] = (T)rd;
+    }
+  }
+}
+
+// stationary-flow primitives (WB_N entry) of an interior cell or of the ghost next to the
+// boundary (the face-state fallback's cell-centre state is this plus the cell's W')
+__device__ __forceinline__ const double* bg_ptr(const StageArgs& a, int k, int i) {
   const Geo& g = a.g;
   if (k < 0 || k >= g.nz) {
-    s = (EXT && g.bc_z == 1) ? 1.0 : 0.0;
-    int ii = min(max(i, 0), g.nr - 1);
-    return a.t.ghzf + ((size_t)(k < 0 ? 0 : 1) * g.nr + ii) * 5;
+    const int ii = min(max(i, 0), g.nr - 1);
+    return a.t.ghzw + ((size_t)(k < 0 ? 0 : 2) * g.nr + ii) * WB_N;
   }
-  if (i < 0 || i >= g.nr) {
-    s = 0.0;
-    return a.t.ghrf + ((size_t)(i < 0 ? 0 : 1) * g.nz + k) * 5;
-  }
-  s = 1.0;
-  return a.t.bgc + ((size_t)k * g.nr + i) * 5;
+  if (i < 0 || i >= g.nr) return a.t.ghrw + ((size_t)(i < 0 ? 0 : 2) * g.nz + k) * WB_N;
+  return a.t.wc + ((size_t)k * g.nr + i) * WB_N;
 }
 
 __device__ __forceinline__ const double* rco_ptr(const StageArgs& a, int i) {

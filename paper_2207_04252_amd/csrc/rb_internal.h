@@ -27,6 +27,12 @@ enum { RT_V = 0, RT_INVV, RT_ATH, RT_AZ, RT_INVRC, RT_OMK, RT_MAXA, RT_RC, RT_N 
 // minmod(wpm*dm + wpp*dp, lpm*dm, lpp*dp), to the lower face
 // minmod(wmm*dm + wmp*dp, lmm*dm, lmp*dp), dm/dp the backward/forward differences.
 enum { RC_WPM = 0, RC_WPP, RC_LPM, RC_LPP, RC_WMM, RC_WMP, RC_LMM, RC_LMP, RC_N };
+// primitive variables of the stationary flow at a cell centre or face centre (the
+// reference of the reconstructed gas deviation W' = W(E) - W(E0)): velocity (r, theta, z),
+// pressure and density in the slots of the gas fields, then the adiabatic sound speed,
+// the total enthalpy per volume E + P and 1/rho.  All zero where the split has no
+// reference (the Sod annulus).
+enum { WB_U = 0, WB_V, WB_W, WB_P, WB_RHO, WB_C, WB_H, WB_IRHO, WB_N };
 
 // Device control block at the start of the work area.
 struct Ctrl {
@@ -45,7 +51,7 @@ struct Ctrl {
 
 // Offsets (in doubles) of the tables inside the work area.
 struct Layout {
-  size_t ctrl, rt, ar, rco, rcell, zc, bgc, bgr, bgz, r0, grav, ghr, ghrf, ghz, ghzf;
+  size_t ctrl, rt, ar, rco, rcell, zc, bgc, bgr, bgz, wc, wr, wz, r0, grav, ghr, ghrw, ghz, ghzw;
   size_t trig, indw, indab, indp, damp, ozr, dtlog, cflp, outp, tsp, red, total;
   int nind;      // blocks of the indirect-gravity sums
   int nblocks;   // stage-kernel blocks
@@ -75,12 +81,15 @@ struct Tables {
   const double* bgc;
   const double* bgr;
   const double* bgz;
+  const double* wc;    // stationary-flow primitives [k][i][WB_N] at cell centres
+  const double* wr;    //   at r faces [k][i + 1/2][WB_N]
+  const double* wz;    //   at z faces [k + 1/2][i][WB_N]
   const double* r0;
   const double* grav;
-  const double* ghr;
-  const double* ghrf;
-  const double* ghz;
-  const double* ghzf;
+  const double* ghr;   // reconstructed variables of the r ghosts [side][layer][k][nf]
+  const double* ghrw;  // their stationary-flow primitives [side][layer][k][WB_N]
+  const double* ghz;   // reconstructed variables of the z ghosts [side][layer][i][nf]
+  const double* ghzw;  // their stationary-flow primitives [side][layer][i][WB_N]
   const double* trig;  // cos, sin of the theta cell centres [2][ntheta]
   const double* indw;  // V r / (r^2 + z^2)^(3/2) per (k, i) (indirect-gravity sums)
   const double* indab; // the indirect-gravity sums A, B of the current stage input

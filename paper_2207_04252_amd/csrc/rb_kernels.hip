@@ -73,14 +73,15 @@ __global__ void __launch_bounds__(NT) k_march(StageArgs a, int species) {
   const double invrc = rt[RT_INVRC], omk = rt[RT_OMK], maxA = rt[RT_MAXA];
   const double Arlo = a.t.ar[igc], Arhi = a.t.ar[igc + 1];
 
-  // gas face: FP64 full states, or FP32 perturbations about the face background
-  auto face = [&](auto dirc, const T* eA, const T* eB, const T* eC, const T* eD, const double* coB,
-                  const double* coC, const double* bgf, const double* cB, double sB,
-                  const double* cC, double sC, T* F) {
+  // gas face: FP64 full states, or FP32 perturbations about the face background; the
+  // cells' reconstructed variables, the stationary flow at the face (bf) and at the
+  // centres of the two cells next to it (bB, bC: the positivity fallback)
+  auto face = [&](auto dirc, const T* wA, const T* wB, const T* wC, const T* wD, const double* coB,
+                  const double* coC, const double* bf, const double* bB, const double* bC, T* F) {
     constexpr int D = decltype(dirc)::value;
-    if constexpr (PG) gas_face_p32<D>(gc, eA, eB, eC, eD, coB, coC, bgf, cB, sB, cC, sC, F, st);
-    else if constexpr (GAS) gas_face<D, G75>(gc, eA, eB, eC, eD, coB, coC, bgf, cB, sB, cC, sC, F, st);
-    else dust_face<D>(eA, eB, eC, eD, coB, coC, F, st);
+    if constexpr (PG) gas_face_p32<D>(gc, wA, wB, wC, wD, coB, coC, bf, bB, bC, F, st);
+    else if constexpr (GAS) gas_face<D, G75>(gc, wA, wB, wC, wD, coB, coC, bf, bB, bC, F, st);
+    else dust_face<D>(wA, wB, wC, wD, coB, coC, F, st);
   };
   using DR = std::integral_constant<int, 0>;
   using DT = std::integral_constant<int, 1>;
@@ -92,18 +93,16 @@ __global__ void __launch_bounds__(NT) k_march(StageArgs a, int species) {
   const bool twod = g.twod != 0;
   if (!twod) {
     T e2[NG];
-    fetch_all<P32, EXT, NG>(a, in, F0, k0 - 2, ig, jw, e2);
-    fetch_all<P32, EXT, NG>(a, in, F0, k0 - 1, ig, jw, rm);
-    fetch_all<P32, EXT, NG>(a, in, F0, k0, ig, jw, r0);
-    fetch_all<P32, EXT, NG>(a, in, F0, k0 + 1, ig, jw, rp);
-    double sB = 1.0, sC = 1.0;
-    const double* cB = GAS ? centre_ptr<EXT>(a, k0 - 1, igc, sB) : nullptr;
-    const double* cC = GAS ? centre_ptr<EXT>(a, k0, igc, sC) : nullptr;
-    const double* bgf = a.t.bgz + ((size_t)k0 * g.nr + igc) * 5;
-    face(DZ(), e2, rm, r0, rp, nullptr, nullptr, bgf, cB, sB, cC, sC, fzlo);
+    load_recon<P32, EXT, NG>(a, in, F0, k0 - 2, ig, jw, e2);
+    load_recon<P32, EXT, NG>(a, in, F0, k0 - 1, ig, jw, rm);
+    load_recon<P32, EXT, NG>(a, in, F0, k0, ig, jw, r0);
+    load_recon<P32, EXT, NG>(a, in, F0, k0 + 1, ig, jw, rp);
+    const double* bf = a.t.wz + ((size_t)k0 * g.nr + igc) * WB_N;
+    face(DZ(), e2, rm, r0, rp, nullptr, nullptr, bf, bg_ptr(a, k0 - 1, igc), bg_ptr(a, k0, igc),
+         fzlo);
     if (a.second && k0 == 0 && act) {
       double fm = (double)fzlo[NG - 1];
-      if (PG) fm += bgf[2];  // background normal mass flux rho0 w0
+      if (PG) fm += bf[WB_RHO] * bf[WB_W];  // background normal mass flux rho0 w0
       ledger -= Az * fm;
     }
     if constexpr (LR) {
@@ -111,7 +110,7 @@ __global__ void __launch_bounds__(NT) k_march(StageArgs a, int species) {
       for (int f = 0; f < NG; ++f) { s_rm[f][tslot] = rm[f]; s_fz[f][tslot] = fzlo[f]; }
     }
   } else {
-    fetch_all<P32, EXT, NG>(a, in, F0, 0, ig, jw, r0);
+    load_recon<P32, EXT, NG>(a, in, F0, 0, ig, jw, r0);
 #pragma unroll
     for (int f = 0; f < NG; ++f) {
       rm[f] = T(0); rp[f] = T(0); rn[f] = T(0); fzlo[f] = T(0); fzhi[f] = T(0);
@@ -133,20 +132,20 @@ __global__ void __launch_bounds__(NT) k_march(StageArgs a, int species) {
   const int h_jj = (j0 + h_cc - 2 + g.nth) % g.nth;
   constexpr bool PF = !PG;
   T hv[NG];
-  if (PF && halo_t) fetch_all<P32, EXT, NG>(a, in, F0, k0, h_ii, h_jj, hv);
+  if (PF && halo_t) load_recon<P32, EXT, NG>(a, in, F0, k0, h_ii, h_jj, hv);
 
   for (int k = k0; k < k1; ++k) {
     if (!twod) {
-      fetch_all<P32, EXT, NG>(a, in, F0, k + 2, ig, jw, rn);
+      load_recon<P32, EXT, NG>(a, in, F0, k + 2, ig, jw, rn);
     }
     // ---- stage the plane (with halo) in LDS
 #pragma unroll
     for (int f = 0; f < NG; ++f) s_pl[f][ti + 2][tj + 2] = r0[f];
     if (halo_t) {
-      if (!PF) fetch_all<P32, EXT, NG>(a, in, F0, k, h_ii, h_jj, hv);
+      if (!PF) load_recon<P32, EXT, NG>(a, in, F0, k, h_ii, h_jj, hv);
 #pragma unroll
       for (int f = 0; f < NG; ++f) s_pl[f][h_rr][h_cc] = hv[f];
-      if (PF && k + 1 < k1) fetch_all<P32, EXT, NG>(a, in, F0, k + 1, h_ii, h_jj, hv);
+      if (PF && k + 1 < k1) load_recon<P32, EXT, NG>(a, in, F0, k + 1, h_ii, h_jj, hv);
     }
     __syncthreads();
     // ---- theta face j+1/2 and r face i+1/2 of this cell
@@ -158,8 +157,8 @@ __global__ void __launch_bounds__(NT) k_march(StageArgs a, int species) {
         eC[f] = s_pl[f][ti + 2][tj + 3]; eD[f] = s_pl[f][ti + 2][tj + 4];
       }
       {
-        const double* bgf = a.t.bgc + ((size_t)k * g.nr + igc) * 5;
-        face(DT(), eA, eB, eC, eD, nullptr, nullptr, bgf, bgf, 1.0, bgf, 1.0, F);
+        const double* bf = a.t.wc + ((size_t)k * g.nr + igc) * WB_N;
+        face(DT(), eA, eB, eC, eD, nullptr, nullptr, bf, bf, bf, F);
       }
 #pragma unroll
       for (int f = 0; f < NG; ++f) s_ft[f][ti][tj + 1] = F[f];
@@ -170,14 +169,12 @@ __global__ void __launch_bounds__(NT) k_march(StageArgs a, int species) {
       }
       {
         const int ifc = min(ig + 1, g.nr);
-        const double* bgf = a.t.bgr + ((size_t)k * (g.nr + 1) + ifc) * 5;
-        double sB = 1.0, sC = 1.0;
-        const double* cB = GAS ? centre_ptr<EXT>(a, k, min(ig, g.nr), sB) : nullptr;
-        const double* cC = GAS ? centre_ptr<EXT>(a, k, min(ig + 1, g.nr), sC) : nullptr;
-        face(DR(), eA, eB, eC, eD, rco_ptr(a, ig), rco_ptr(a, ig + 1), bgf, cB, sB, cC, sC, F);
+        const double* bf = a.t.wr + ((size_t)k * (g.nr + 1) + ifc) * WB_N;
+        face(DR(), eA, eB, eC, eD, rco_ptr(a, ig), rco_ptr(a, ig + 1), bf,
+             bg_ptr(a, k, min(ig, g.nr)), bg_ptr(a, k, min(ig + 1, g.nr)), F);
         if (a.second && act && ig == g.nr - 1) {
           double fm = (double)F[NG - 1];
-          if (PG) fm += bgf[0];  // background normal mass flux rho0 u0
+          if (PG) fm += bf[WB_RHO] * bf[WB_U];  // background normal mass flux rho0 u0
           ledger += Arhi * fm;
         }
       }
@@ -194,16 +191,14 @@ __global__ void __launch_bounds__(NT) k_march(StageArgs a, int species) {
         eA[f] = s_pl[f][0][col + 2]; eB[f] = s_pl[f][1][col + 2];
         eC[f] = s_pl[f][2][col + 2]; eD[f] = s_pl[f][3][col + 2];
       }
-      const double* bgf = a.t.bgr + ((size_t)k * (g.nr + 1) + i0) * 5;
-      double sB = 1.0, sC = 1.0;
-      const double* cB = GAS ? centre_ptr<EXT>(a, k, i0 - 1, sB) : nullptr;
-      const double* cC = GAS ? centre_ptr<EXT>(a, k, i0, sC) : nullptr;
-      face(DR(), eA, eB, eC, eD, rco_ptr(a, i0 - 1), rco_ptr(a, i0), bgf, cB, sB, cC, sC, F);
+      const double* bf = a.t.wr + ((size_t)k * (g.nr + 1) + i0) * WB_N;
+      face(DR(), eA, eB, eC, eD, rco_ptr(a, i0 - 1), rco_ptr(a, i0), bf, bg_ptr(a, k, i0 - 1),
+           bg_ptr(a, k, i0), F);
 #pragma unroll
       for (int f = 0; f < NG; ++f) s_fr[f][0][col] = F[f];
       if (a.second && i0 == 0 && j0 + col < g.nth) {
         double fm = (double)F[NG - 1];
-        if (PG) fm += bgf[0];
+        if (PG) fm += bf[WB_RHO] * bf[WB_U];
         ledger -= a.t.ar[0] * fm;
       }
     } else if (tid < TJ + TI) {
@@ -215,8 +210,8 @@ __global__ void __launch_bounds__(NT) k_march(StageArgs a, int species) {
         eA[f] = s_pl[f][row + 2][0]; eB[f] = s_pl[f][row + 2][1];
         eC[f] = s_pl[f][row + 2][2]; eD[f] = s_pl[f][row + 2][3];
       }
-      const double* bgf = a.t.bgc + ((size_t)k * g.nr + irow) * 5;
-      face(DT(), eA, eB, eC, eD, nullptr, nullptr, bgf, bgf, 1.0, bgf, 1.0, F);
+      const double* bf = a.t.wc + ((size_t)k * g.nr + irow) * WB_N;
+      face(DT(), eA, eB, eC, eD, nullptr, nullptr, bf, bf, bf, F);
 #pragma unroll
       for (int f = 0; f < NG; ++f) s_ft[f][row][0] = F[f];
     }
@@ -226,14 +221,12 @@ __global__ void __launch_bounds__(NT) k_march(StageArgs a, int species) {
 #pragma unroll
         for (int f = 0; f < NG; ++f) rm[f] = s_rm[f][tslot];
       }
-      double sB = 1.0, sC = 1.0;
-      const double* cB = GAS ? centre_ptr<EXT>(a, k, igc, sB) : nullptr;
-      const double* cC = GAS ? centre_ptr<EXT>(a, k + 1, igc, sC) : nullptr;
-      const double* bgf = a.t.bgz + ((size_t)(k + 1) * g.nr + igc) * 5;
-      face(DZ(), rm, r0, rp, rn, nullptr, nullptr, bgf, cB, sB, cC, sC, fzhi);
+      const double* bf = a.t.wz + ((size_t)(k + 1) * g.nr + igc) * WB_N;
+      face(DZ(), rm, r0, rp, rn, nullptr, nullptr, bf, bg_ptr(a, k, igc), bg_ptr(a, k + 1, igc),
+           fzhi);
       if (a.second && act && k == g.nz - 1) {
         double fm = (double)fzhi[NG - 1];
-        if (PG) fm += bgf[2];
+        if (PG) fm += bf[WB_RHO] * bf[WB_W];
         ledger += Az * fm;
       }
     }
@@ -252,27 +245,25 @@ __global__ void __launch_bounds__(NT) k_march(StageArgs a, int species) {
     const double gr = a.t.grav[((size_t)k * g.nr + igc) * 2 + 0];
     const double gz = a.t.grav[((size_t)k * g.nr + igc) * 2 + 1];
     const double* bgc = a.t.bgc + ((size_t)k * g.nr + igc) * 5;
+    const double* bw = a.t.wc + ((size_t)k * g.nr + igc) * WB_N;
     T S[NG];
     if constexpr (PG) {
-      // source change S(E) - S(E0): every term formed from the perturbations
-      const BgW bc = bg_prims<0>(bgc, gc.g);
-      const PW w = pert_prims<0>(bc, r0, (float)gc.gm1);
-      const float v0 = (float)bc.t1;
-      const float mth = (float)bgc[1] + r0[1];
-      const float mr = (float)bgc[0] + r0[0];
+      // source change S(E) - S(E0), every term formed from the perturbations W' (the
+      // stationary flow has no radial or vertical velocity)
+      const float rp = r0[4], up = r0[0], vp = r0[1], wp = r0[2], pp = r0[3];
+      const float v0 = (float)bw[WB_V];
+      const float rho = (float)(bw[WB_RHO] + (double)rp);
       const float ir = (float)invrc, fgr = (float)gr, fgz = (float)gz;
-      S[0] = (r0[1] * v0 + mth * w.t1 + w.p) * ir + r0[4] * fgr;
-      S[1] = -(r0[0] * v0 + mr * w.t1) * ir;
-      S[2] = r0[4] * fgz;
-      S[3] = r0[0] * fgr + r0[2] * fgz;
+      const float dmv2 = rp * (float)(bw[WB_V] * bw[WB_V]) + rho * vp * (2.0f * v0 + vp);
+      S[0] = (dmv2 + pp) * ir + rp * fgr;
+      S[1] = -(rho * up * (v0 + vp)) * ir;
+      S[2] = rp * fgz;
+      S[3] = rho * (up * fgr + wp * fgz);
       S[4] = 0.0f;
       if (drag) {
-        double q[5];
-#pragma unroll
-        for (int f = 0; f < 5; ++f) q[f] = bgc[f] + (double)r0[f];
-        const double inv = 1.0 / q[4];
-        const double u = q[0] * inv, v = q[1] * inv, w2 = q[2] * inv;
-        const double pq = (EXT && g.drag_law) ? gc.gm1 * (q[3] - 0.5 * (q[0] * u + q[1] * v + q[2] * w2)) : 0.0;
+        const double rg = bw[WB_RHO] + (double)rp;
+        const double u = (double)up, v = bw[WB_V] + (double)vp, w2 = (double)wp;
+        const double pq = (EXT && g.drag_law) ? bw[WB_P] + (double)pp : 0.0;
         double dx = 0.0, dy = 0.0, dzz = 0.0;
 #pragma unroll
         for (int s2 = 0; s2 < ND; ++s2) {
@@ -281,7 +272,7 @@ __global__ void __launch_bounds__(NT) k_march(StageArgs a, int species) {
           const double rd = ld_cell<P32>(a, in, o + 3, k, igc, cellw);
           const float* vel = (const float*)in + (size_t)(5 + 3 * s2) * g.N + cellw;
           const double ud = vel[0], vd = vel[g.N], wd = vel[2 * (size_t)g.N];
-          const double its = inv_tstop<EXT>(g, s2, omk, q[4], pq);
+          const double its = inv_tstop<EXT>(g, s2, omk, rg, pq);
           dx += rd * (ud - u) * its;
           dy += rd * (vd - v) * its;
           dzz += rd * (wd - w2) * its;
@@ -292,16 +283,14 @@ __global__ void __launch_bounds__(NT) k_march(StageArgs a, int species) {
         S[3] += (float)(u * dx + v * dy + w2 * dzz);
       }
     } else if constexpr (GAS) {
-      double q[5];
-#pragma unroll
-      for (int f = 0; f < 5; ++f) q[f] = bgc[f] + r0[f];
-      const double inv = 1.0 / q[4];
-      const double u = q[0] * inv, v = q[1] * inv, w = q[2] * inv;
-      const double p = gc.gm1 * (q[3] - 0.5 * (q[0] * u + q[1] * v + q[2] * w));
-      S[0] = (q[1] * v + p) * invrc + q[4] * gr;
-      S[1] = -(q[0] * v) * invrc;
-      S[2] = q[4] * gz;
-      S[3] = q[0] * gr + q[2] * gz;
+      // the cell's primitives: stationary flow + W'
+      const double rho = bw[WB_RHO] + r0[4];
+      const double u = bw[WB_U] + r0[0], v = bw[WB_V] + r0[1], w = bw[WB_W] + r0[2];
+      const double p = bw[WB_P] + r0[3];
+      S[0] = (rho * v * v + p) * invrc + rho * gr;
+      S[1] = -(rho * u * v) * invrc;
+      S[2] = rho * gz;
+      S[3] = rho * (u * gr + w * gz);
       S[4] = 0.0;
       if (drag) {
         double dx = 0.0, dy = 0.0, dzz = 0.0;
@@ -316,7 +305,7 @@ __global__ void __launch_bounds__(NT) k_march(StageArgs a, int species) {
             vd = ld_cell<P32>(a, in, o + 1, k, igc, cellw) * id;
             wd = ld_cell<P32>(a, in, o + 2, k, igc, cellw) * id;
           }
-          const double its = inv_tstop<EXT>(g, s2, omk, q[4], p);
+          const double its = inv_tstop<EXT>(g, s2, omk, rho, p);
           dx += rd * (ud - u) * its;
           dy += rd * (vd - v) * its;
           dzz += rd * (wd - w) * its;
@@ -327,12 +316,8 @@ __global__ void __launch_bounds__(NT) k_march(StageArgs a, int species) {
         S[3] += u * dx + v * dy + w * dzz;
       }
     } else {
-      const double rd = r0[3];
-      double ud = 0.0, vd = 0.0, wd = 0.0;
-      if (rd > 0.0) {
-        double id = 1.0 / rd;
-        ud = r0[0] * id; vd = r0[1] * id; wd = r0[2] * id;
-      }
+      // the dust cell's primitives (velocity zero where the density is not positive)
+      const double rd = r0[3], ud = r0[0], vd = r0[1], wd = r0[2];
       double fx = 0.0, fy = 0.0, fz = 0.0;
       if (drag) {
         double q[5];
@@ -346,8 +331,8 @@ __global__ void __launch_bounds__(NT) k_march(StageArgs a, int species) {
         fy = rd * (vd - v) * its;
         fz = rd * (wd - w) * its;
       }
-      S[0] = (r0[1] * vd) * invrc + rd * gr - fx;
-      S[1] = -(r0[0] * vd) * invrc - fy;
+      S[0] = (rd * vd * vd) * invrc + rd * gr - fx;
+      S[1] = -(rd * ud * vd) * invrc - fy;
       S[2] = rd * gz - fz;
       S[3] = 0.0;
     }
@@ -357,8 +342,8 @@ __global__ void __launch_bounds__(NT) k_march(StageArgs a, int species) {
       const double cs = a.t.trig[jw], sn = a.t.trig[g.nth + jw];
       const double ar = -g.GM * (A * cs + B * sn), at = -g.GM * (B * cs - A * sn);
       if constexpr (GAS) {
-        const double mr = bgc[0] + (double)r0[0], mt = bgc[1] + (double)r0[1];
-        const double rho = bgc[4] + (double)r0[4];
+        const double rho = bw[WB_RHO] + (double)r0[4];
+        const double mr = rho * (bw[WB_U] + (double)r0[0]), mt = rho * (bw[WB_V] + (double)r0[1]);
         S[0] += (T)(rho * ar);
         S[1] += (T)(rho * at);
         S[3] += (T)(mr * ar + mt * at);
@@ -369,9 +354,11 @@ __global__ void __launch_bounds__(NT) k_march(StageArgs a, int species) {
     }
     // boundary damping zones (Sect. 2.4): the gas deviation relaxes to the stationary flow
     if (EXT && GAS && g.damp) {
-      const T kd = (T)a.t.damp[(size_t)k * g.nr + igc];
+      const double kd = a.t.damp[(size_t)k * g.nr + igc];
+      double e[NG];
+      load_cons<P32, NG>(a, in, F0, k, igc, jw, e);
 #pragma unroll
-      for (int f = 0; f < NG; ++f) S[f] -= kd * r0[f];
+      for (int f = 0; f < NG; ++f) S[f] -= (T)(kd * e[f]);
     }
     T Gt[NG];
 #pragma unroll
@@ -410,7 +397,7 @@ __global__ void __launch_bounds__(NT) k_march(StageArgs a, int species) {
       } else {
         const double cdt = a.coef * dt * invV;
         double bv[NG];
-        fetch_all<P32, EXT, NG>(a, a.base, F0, k, ig, jg, bv);
+        load_cons<P32, NG>(a, a.base, F0, k, ig, jg, bv);
 #pragma unroll
         for (int f = 0; f < NG; ++f) nvd[f] = fma(cdt, (double)Gt[f], bv[f]);
         if (!P32 || GAS) {
@@ -638,6 +625,46 @@ __device__ void gas_cons(double g, double rho, double u, double v, double P, dou
   q[4] = rho;
 }
 
+// Primitive variables of a conservative gas state q as a WB_N table entry: velocity,
+// pressure, density, sound speed, E + P, 1/rho.  Zero for the Sod annulus (its split has
+// no stationary reference).
+__device__ void prim_entry(const rb_config& c, const double* q, double* o) {
+  if (c.init_kind != RB_INIT_DISC) {
+    for (int s = 0; s < WB_N; ++s) o[s] = 0.0;
+    return;
+  }
+  const double rho = q[4];
+  o[WB_U] = q[0] / rho;
+  o[WB_V] = q[1] / rho;
+  o[WB_W] = q[2] / rho;
+  o[WB_P] = (c.gamma - 1.0) * (q[3] - 0.5 * (q[0] * o[WB_U] + q[1] * o[WB_V] + q[2] * o[WB_W]));
+  o[WB_RHO] = rho;
+  o[WB_C] = sqrt(c.gamma * o[WB_P] / rho);
+  o[WB_H] = q[3] + o[WB_P];
+  o[WB_IRHO] = 1.0 / rho;
+}
+
+// Reconstructed variables of a ghost cell whose full state is q (nf fields): the gas
+// deviation W(q) - W0 (zero on a disc, whose ghosts hold the stationary flow; the
+// state's own primitives for the Sod annulus), and each dust fluid's velocity (zero
+// where it is empty) and density.
+__device__ void ghost_recon(const rb_config& c, int nf, const double* q, double* o) {
+  if (c.init_kind == RB_INIT_DISC) {
+    for (int f = 0; f < 5; ++f) o[f] = 0.0;
+  } else {
+    const double rho = q[4];
+    const double u = q[0] / rho, v = q[1] / rho, w = q[2] / rho;
+    o[0] = u; o[1] = v; o[2] = w;
+    o[3] = (c.gamma - 1.0) * (q[3] - 0.5 * (q[0] * u + q[1] * v + q[2] * w));
+    o[4] = rho;
+  }
+  for (int b = 5; b < nf; b += 4) {
+    const double rd = q[b + 3];
+    for (int m = 0; m < 3; ++m) o[b + m] = rd > 0.0 ? q[b + m] / rd : 0.0;
+    o[b + 3] = rd;
+  }
+}
+
 // initial dust layer of species s: eps (H/H_d) rho_mid(r) exp(-z^2 / 2 H_d^2)
 __device__ double dust_layer(const rb_config& c, int s, double r, double z) {
   const double c2 = c.h0 * c.h0 * c.GM * pow(r, c.beta_T);
@@ -784,6 +811,7 @@ __global__ void __launch_bounds__(256) k_tables_2d(InitArgs a) {
       background_full(a, r, zc, q);
       for (int f = 0; f < 5; ++f) w[L.bgc + ((size_t)kk * nr + ii) * 5 + f] =
           c.init_kind == RB_INIT_DISC ? q[f] : 0.0;
+      prim_entry(c, q, w + L.wc + ((size_t)kk * nr + ii) * WB_N);
       double s3 = pow(r * r + zc * zc, 1.5);
       w[L.grav + ((size_t)kk * nr + ii) * 2 + 0] = -c.GM * r / s3;
       w[L.grav + ((size_t)kk * nr + ii) * 2 + 1] = -c.GM * zc / s3;
@@ -792,30 +820,27 @@ __global__ void __launch_bounds__(256) k_tables_2d(InitArgs a) {
       background_full(a, face_r(c, ii), zc, q);
       for (int f = 0; f < 5; ++f) w[L.bgr + ((size_t)kk * (nr + 1) + ii) * 5 + f] =
           c.init_kind == RB_INIT_DISC ? q[f] : 0.0;
+      prim_entry(c, q, w + L.wr + ((size_t)kk * (nr + 1) + ii) * WB_N);
     }
     if (!twod && iin && kk >= 0 && kk <= nz) {
       background_full(a, cell_r(c, ii), (kk - 0.5 * nz) * dz, q);
       for (int f = 0; f < 5; ++f) w[L.bgz + ((size_t)kk * nr + ii) * 5 + f] =
           c.init_kind == RB_INIT_DISC ? q[f] : 0.0;
+      prim_entry(c, q, w + L.wz + ((size_t)kk * nr + ii) * WB_N);
     }
-    // ghost cells: reconstructed variables (gas E', dust whole) and full gas state
+    // ghost cells: reconstructed variables (gas W', dust primitives) and the stationary
+    // flow's primitives
     if (kin && !iin && ii >= -2 && ii <= nr + 1) {
       const int side = ii < 0 ? 0 : 1, layer = ii < 0 ? -1 - ii : ii - nr;
       background_full(a, cell_r(c, ii), zc, q);
-      double* ge = w + L.ghr + ((size_t)(side * 2 + layer) * nz + kk) * nf;
-      for (int f = 0; f < nf; ++f)
-        ge[f] = (f < 5 && c.init_kind == RB_INIT_DISC) ? 0.0 : q[f];
-      if (layer == 0)
-        for (int f = 0; f < 5; ++f) w[L.ghrf + ((size_t)side * nz + kk) * 5 + f] = q[f];
+      ghost_recon(c, nf, q, w + L.ghr + ((size_t)(side * 2 + layer) * nz + kk) * nf);
+      prim_entry(c, q, w + L.ghrw + ((size_t)(side * 2 + layer) * nz + kk) * WB_N);
     }
     if (!twod && iin && !kin && kk >= -2 && kk <= nz + 1) {
       const int side = kk < 0 ? 0 : 1, layer = kk < 0 ? -1 - kk : kk - nz;
       background_full(a, cell_r(c, ii), zc, q);
-      double* ge = w + L.ghz + ((size_t)(side * 2 + layer) * nr + ii) * nf;
-      for (int f = 0; f < nf; ++f)
-        ge[f] = (f < 5 && c.init_kind == RB_INIT_DISC) ? 0.0 : q[f];
-      if (layer == 0)
-        for (int f = 0; f < 5; ++f) w[L.ghzf + ((size_t)side * nr + ii) * 5 + f] = q[f];
+      ghost_recon(c, nf, q, w + L.ghz + ((size_t)(side * 2 + layer) * nr + ii) * nf);
+      prim_entry(c, q, w + L.ghzw + ((size_t)(side * 2 + layer) * nr + ii) * WB_N);
       // outflow ghosts: stationary density of the ghost over that of the boundary cell
       const double rho_g = q[4];
       background_full(a, cell_r(c, ii), (side == 0 ? 0.5 - 0.5 * nz : nz - 0.5 - 0.5 * nz) * dz, q);

@@ -1,10 +1,11 @@
 // FP32 perturbation form of the gas face flux (included by rb_kernels.hip).
 //
 // The face background W0 (the stationary flow at the face, FP64) is the same on both
-// sides, so the Riemann problem between W0 + W'_L and W0 + W'_R is solved for the
-// perturbations: q = p* - p0 by Newton in FP32, every pressure-function term written
-// without cancellation ((1+x)^(1/7) - 1 = x / sum_{k<7} y^k), the sampled state as a
-// perturbation, and the flux returned as dF = F(W0 + W') - F(W0).  The empty-run
+// sides, so the Riemann problem between W0 + W'_L and W0 + W'_R (the reconstructed
+// primitive deviations) is solved for the perturbations: q = p* - p0 by Newton in FP32,
+// every pressure-function term written without cancellation ((1+x)^(1/7) - 1 =
+// x / sum_{k<7} y^k), the sampled state as a perturbation, and the flux returned as
+// dF = F(W0 + W') - F(W0).  The empty-run
 // residual is then never formed: G(E) - G(E0) = S' V - sum A dF.  Strong perturbations,
 // a transonic fan or a Newton failure fall back to the FP64 solver.
 #pragma once
@@ -16,24 +17,21 @@ namespace rb {
 __device__ __forceinline__ float rcp32(float x) { return __builtin_amdgcn_rcpf(x); }
 __device__ __forceinline__ float sqrt32(float x) { return __builtin_amdgcn_sqrtf(x); }
 
-// background primitives at a face in the face frame (FP64)
+// stationary-flow primitives at a face in the face frame (FP64), from its WB_N entry
 struct BgW {
   double rho, un, t1, t2, p, c, h;  // h = E + p per volume
 };
 
 template <int DIR>
-__device__ __forceinline__ BgW bg_prims(const double* q, double g) {
+__device__ __forceinline__ BgW bg_face(const double* w) {
   BgW b;
-  const double ir = frcp(q[4]);
-  const double vel[3] = {q[0] * ir, q[1] * ir, q[2] * ir};
-  b.rho = q[4];
-  b.un = vel[Dirs<DIR>::n];
-  b.t1 = vel[Dirs<DIR>::t1];
-  b.t2 = vel[Dirs<DIR>::t2];
-  b.p = (g - 1.0) * (q[3] - 0.5 * (q[0] * vel[0] + q[1] * vel[1] + q[2] * vel[2]));
-  const double c2 = g * b.p * ir;
-  b.c = c2 * frsq(c2);
-  b.h = q[3] + b.p;
+  b.rho = w[WB_RHO];
+  b.un = w[Dirs<DIR>::n];
+  b.t1 = w[Dirs<DIR>::t1];
+  b.t2 = w[Dirs<DIR>::t2];
+  b.p = w[WB_P];
+  b.c = w[WB_C];
+  b.h = w[WB_H];
   return b;
 }
 
@@ -41,26 +39,6 @@ __device__ __forceinline__ BgW bg_prims(const double* q, double g) {
 struct PW {
   float rho, un, t1, t2, p;
 };
-
-// conservative perturbation e (field order, FP32) -> primitive perturbation, with the
-// kinetic-energy change formed as 1/2 rho'|u0|^2 + rho u0.u' + 1/2 rho |u'|^2
-template <int DIR>
-__device__ __forceinline__ PW pert_prims(const BgW& b, const float* e, float gm1) {
-  PW w;
-  w.rho = e[4];
-  const float rho = (float)(b.rho + (double)e[4]);
-  const float ir = rcp32(rho);
-  const float un0 = (float)b.un, t10 = (float)b.t1, t20 = (float)b.t2;
-  w.un = (e[Dirs<DIR>::n] - un0 * w.rho) * ir;
-  w.t1 = (e[Dirs<DIR>::t1] - t10 * w.rho) * ir;
-  w.t2 = (e[Dirs<DIR>::t2] - t20 * w.rho) * ir;
-  const float u0sq = (float)(b.un * b.un + b.t1 * b.t1 + b.t2 * b.t2);
-  const float dot = un0 * w.un + t10 * w.t1 + t20 * w.t2;
-  const float usq = w.un * w.un + w.t1 * w.t1 + w.t2 * w.t2;
-  const float dke = 0.5f * w.rho * u0sq + rho * dot + 0.5f * rho * usq;
-  w.p = gm1 * (e[3] - dke);
-  return w;
-}
 
 // flux perturbation of a primitive perturbation about the face background
 __device__ __forceinline__ void flux_pert(const BgW& b, const PW& w, float inv_gm1, float out[5]) {
