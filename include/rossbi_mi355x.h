@@ -154,9 +154,11 @@ rb_status rb_query_sizes(const rb_config* cfg, rb_buffers* sizes);
 
 /* Builds the geometry, the stationary flow at cell and face centres (App. A), the
  * empty-run residual R0 = G(E0) (Sect. 2.8, computed by the step kernel itself) and
- * the initial state, all on the device.  noise: host array of ncells doubles in
- * [-1, 1) multiplying noise_amp (NULL: no noise); amp: host array of ncells vortex
- * amplitudes (NULL: vortex_amp everywhere).  Both are read before the call returns.
+ * the initial state, all on the device.  noise: host array of (1 + n_dust) x ncells
+ * doubles in [-1, 1), one field per fluid (gas, then each dust species), each
+ * multiplying noise_amp in that fluid's initial density (NULL: no noise); amp: host
+ * array of ncells vortex amplitudes (NULL: vortex_amp everywhere).  Both are read before
+ * the call returns.
  * stream: hipStream_t (NULL: default stream).  *out receives the context. */
 rb_status rb_init_state(const rb_config* cfg, const rb_buffers* bufs, const double* noise,
                         const double* amp, void* stream, rb_ctx** out);
@@ -183,6 +185,13 @@ rb_status rb_eval_operator(rb_ctx* ctx, double* host_out, size_t n_doubles);
 
 /* Copies the empty-run residual R0 to host memory, [nz][nr][5]. */
 rb_status rb_get_residual(rb_ctx* ctx, double* host_out, size_t n_doubles);
+
+/* The mesh of the context as the kernels use it (Sect. 2.3): r_faces[nr + 1] (logarithmic
+ * or uniform in r), r_centres[nr] (mid-points of the radial faces), volumes[nr] (the
+ * volume of a cell of each radial row, (r+^2 - r-^2)/2 dtheta dz), z_centres[nz] (zero
+ * in 2D).  Host arrays, each may be NULL; EINVAL on a null context. */
+rb_status rb_get_geometry(rb_ctx* ctx, double* r_faces, double* r_centres, double* volumes,
+                          double* z_centres);
 
 /* CFL time step of the current state (Sect. 2.5), computed on the device. */
 rb_status rb_cfl_dt(rb_ctx* ctx, double* dt);
@@ -235,8 +244,9 @@ rb_status rb_adjoint(rb_ctx* ctx, const void* lambda_final, void* grad_state0,
 
 /* Contracts a state cotangent lam (device, layout of rb_get_fields) with the derivative
  * of the initial disc state with respect to the per-cell vortex amplitude: out[cell] =
- * sum_f lam[f][cell] dE_f/dA(cell).  noise and amp (host, ncells each, may be NULL) must
- * be those given to rb_init_state; out is a device array of ncells doubles. */
+ * sum_f lam[f][cell] dE_f/dA(cell).  noise ((1 + n_dust) x ncells) and amp (ncells),
+ * host arrays that may be NULL, must be those given to rb_init_state; out is a device
+ * array of ncells doubles. */
 rb_status rb_amp_gradient(rb_ctx* ctx, const double* noise, const double* amp, const void* lam,
                           void* out);
 

@@ -25,8 +25,11 @@ DT_CFL, DT_FIXED, DT_LIST = 0, 1, 2
 
 
 def build(verbose: bool = False) -> str:
-    """Compile the oracle with g++ (portable x86-64 code, no FMA contraction)."""
-    cmd = ["g++", "-O2", "-std=c++17", "-fopenmp", "-ffp-contract=off", "-fno-fast-math",
+    """Compile the oracle with g++: -O3, no FMA contraction and no fast-math (every
+    operation rounds as written).  Generic x86-64 code: the library is built on one host
+    and may run on another, whose CPU need not have the build host's instruction-set
+    extensions."""
+    cmd = ["g++", "-O3", "-std=c++17", "-fopenmp", "-ffp-contract=off", "-fno-fast-math",
            "-fPIC", "-shared", "-Wall", "-o", LIB_PATH + ".tmp", SRC_PATH]
     if verbose:
         print(" ".join(cmd), flush=True)
@@ -151,6 +154,8 @@ def lib() -> ctypes.CDLL:
         L.or_tangent.argtypes = [ctypes.POINTER(OrConfig), _D, _D, _D, _D, ctypes.c_int, _D,
                                  ctypes.c_double, ctypes.c_double, ctypes.c_double, _D, _D]
         L.or_threads.restype = ctypes.c_int
+        L.or_set_threads.restype = ctypes.c_int
+        L.or_set_threads.argtypes = [ctypes.c_int]
         L.or_count_ops.restype = ctypes.c_double
         L.or_count_ops.argtypes = [ctypes.POINTER(OrConfig), _D]
         L.or_indirect_sums.argtypes = [ctypes.c_void_p, _D, _D]
@@ -337,6 +342,11 @@ def tangent_state(cfg: synth.Config, state0, dstate0, st_dot, dt_list):
     status = lib().or_tangent_state(ctypes.byref(s), _ptr(x0), _ptr(dx0), _ptr(st), len(dts),
                                     _ptr(dts), _ptr(out), _ptr(dout))
     return status, out, dout
+
+
+def set_threads(n: int) -> int:
+    """OpenMP threads of the oracle's loops; returns the number in use."""
+    return lib().or_set_threads(int(n))
 
 
 def count_ops(cfg: synth.Config, noise=None) -> float:

@@ -577,7 +577,9 @@ struct Sim {
   /* Initial state: Sod annulus, or the disc with the column Gaussian vortex (velocity
    * from the streamfunction psi = psi0 exp(-X^2/2sr^2 - Y^2/2sa^2), X = r - r_v,
    * Y = r_v wrap(theta - theta_v), centre vorticity 2 Ro Omega_K(r_v), Ro = -amplitude),
-   * density noise rho0 (1 + a xi), unchanged pressure, dust moving with the gas. */
+   * density noise rho0 (1 + a xi) on the gas at unchanged pressure and on each dust
+   * layer (its own noise field: noise holds (1 + n_dust) fields of N values), dust moving
+   * with the gas. */
   void initial_state(const double* noise, const T* amp) {
     for (int k = 0; k < nz; ++k)
       for (int i = 0; i < nr; ++i)
@@ -625,7 +627,8 @@ struct Sim {
           gas_conservative(rho, u, v, P0 * bump, q);
           for (int f = 0; f < 5; ++f) E[f * N + id] = q[f];
           for (int s = 0; s < nd; ++s) {
-            double rd = dust_density(s, r, z);
+            double xd = noise ? noise[(size_t)(1 + s) * N + id] : 0.0;
+            double rd = dust_density(s, r, z) * (1.0 + c.noise_amp * xd);
             E[(5 + 4 * s + 0) * N + id] = rd * u;
             E[(5 + 4 * s + 1) * N + id] = rd * v;
             E[(5 + 4 * s + 2) * N + id] = T(0.0);
@@ -1404,6 +1407,18 @@ int or_threads(void) {
 #ifdef _OPENMP
   return omp_get_max_threads();
 #else
+  return 1;
+#endif
+}
+
+/* sets the number of OpenMP threads of the oracle's loops (the CPU baseline times one
+ * thread and all threads); returns the number now in use */
+int or_set_threads(int n) {
+#ifdef _OPENMP
+  if (n > 0) omp_set_num_threads(n);
+  return omp_get_max_threads();
+#else
+  (void)n;
   return 1;
 #endif
 }

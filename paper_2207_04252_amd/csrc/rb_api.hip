@@ -129,6 +129,7 @@ Layout make_layout(const rb_config& c) {
   L.ar = take(nr + 1);
   L.rco = take((nr + 2) * RC_N);
   L.rcell = take(nr + 4);
+  L.rface = take(nr + 1);
   L.zc = take(nz);
   L.bgc = take(nz * nr * 5);
   L.bgr = take(nz * (nr + 1) * 5);
@@ -385,19 +386,20 @@ rb_status rb_init_state(const rb_config* cfg, const rb_buffers* bufs, const doub
     a.gas_only = 1;
     if (launch_stage(a, x->L.nblocks, x->stream) != hipSuccess) return bail(RB_EDEVICE);
   }
-  // initial state: noise and amplitude fields staged through the stage buffer
-  const size_t N = x->g.N;
+  // initial state: noise (one field per fluid) and amplitude fields staged through the
+  // stage buffer, which holds at least (2 + n_dust) N doubles in either storage form
+  const size_t N = x->g.N, NN = (size_t)(1 + x->g.nd) * N;
   if (noise) {
-    if (hipMemcpyAsync(x->stage, noise, N * sizeof(double), hipMemcpyHostToDevice, x->stream) !=
+    if (hipMemcpyAsync(x->stage, noise, NN * sizeof(double), hipMemcpyHostToDevice, x->stream) !=
         hipSuccess)
       return bail(RB_EDEVICE);
     ia.noise = (const double*)x->stage;
   }
   if (amp) {
-    if (hipMemcpyAsync((double*)x->stage + N, amp, N * sizeof(double), hipMemcpyHostToDevice,
+    if (hipMemcpyAsync((double*)x->stage + NN, amp, N * sizeof(double), hipMemcpyHostToDevice,
                        x->stream) != hipSuccess)
       return bail(RB_EDEVICE);
-    ia.amp = (const double*)x->stage + N;
+    ia.amp = (const double*)x->stage + NN;
   }
   if (launch_init_state(ia, x->stream) != hipSuccess) return bail(RB_EDEVICE);
   if (hipStreamSynchronize(x->stream) != hipSuccess) return bail(RB_EDEVICE);
@@ -553,6 +555,27 @@ rb_status rb_get_residual(rb_ctx* x, double* host_out, size_t n_doubles) {
   HIPCHK(x, hipMemcpyAsync(host_out, x->work + x->L.r0, n * sizeof(double), hipMemcpyDeviceToHost,
                            x->stream), "copy out");
   HIPCHK(x, hipStreamSynchronize(x->stream), "sync");
+  return RB_OK;
+}
+
+rb_status rb_get_geometry(rb_ctx* x, double* r_faces, double* r_centres, double* volumes,
+                          double* z_centres) {
+  if (!x) return RB_EINVAL;
+  const int nr = x->cfg.nr, nz = x->cfg.nz;
+  std::vector<double> rt((size_t)nr * RT_N);
+  HIPCHK(x, hipMemcpyAsync(rt.data(), x->work + x->L.rt, rt.size() * sizeof(double),
+                           hipMemcpyDeviceToHost, x->stream), "copy radial table");
+  if (r_faces)
+    HIPCHK(x, hipMemcpyAsync(r_faces, x->work + x->L.rface, (nr + 1) * sizeof(double),
+                             hipMemcpyDeviceToHost, x->stream), "copy faces");
+  if (z_centres)
+    HIPCHK(x, hipMemcpyAsync(z_centres, x->work + x->L.zc, nz * sizeof(double),
+                             hipMemcpyDeviceToHost, x->stream), "copy z centres");
+  HIPCHK(x, hipStreamSynchronize(x->stream), "sync");
+  for (int i = 0; i < nr; ++i) {
+    if (r_centres) r_centres[i] = rt[(size_t)i * RT_N + RT_RC];
+    if (volumes) volumes[i] = rt[(size_t)i * RT_N + RT_V];
+  }
   return RB_OK;
 }
 
@@ -800,15 +823,16 @@ rb_status rb_amp_gradient(rb_ctx* x, const double* noise, const double* amp, con
   ia.work = x->work;
   ia.L = x->L;
   ia.state = x->state;
+  const size_t NN = (size_t)(1 + x->g.nd) * N;
   if (noise) {
-    HIPCHK(x, hipMemcpyAsync(x->stage, noise, N * sizeof(double), hipMemcpyHostToDevice, x->stream),
-           "noise");
+    HIPCHK(x, hipMemcpyAsync(x->stage, noise, NN * sizeof(double), hipMemcpyHostToDevice,
+                             x->stream), "noise");
     ia.noise = (const double*)x->stage;
   }
   if (amp) {
-    HIPCHK(x, hipMemcpyAsync((double*)x->stage + N, amp, N * sizeof(double), hipMemcpyHostToDevice,
+    HIPCHK(x, hipMemcpyAsync((double*)x->stage + NN, amp, N * sizeof(double), hipMemcpyHostToDevice,
                              x->stream), "amp");
-    ia.amp = (const double*)x->stage + N;
+    ia.amp = (const double*)x->stage + NN;
   }
   HIPCHK(x, launch_amp_grad(ia, (const double*)lam, (double*)out, x->stream), "amp gradient");
   HIPCHK(x, hipStreamSynchronize(x->stream), "sync");

@@ -584,11 +584,13 @@ __device__ __forceinline__ void gas_face_p32(const GasC& c, const float* wA, con
 // ------------------------------------------------------------------------------------
 // state access with ghost cells (Sect. 2.4): r and z ghosts come from tables, theta wraps
 
-// FP32-perturbation storage layout: the gas deviation (5 fields) and the dust velocities
-// (momentum / density, 3 per species) in FP32, then the dust densities in FP64 (mass is
-// accumulated in FP64).  f64_base: first double of that part.  A dust momentum is read as
-// density x velocity; it is stored as momentum / density after the cell's new density,
-// which must therefore be written first (zero velocity where the density is below 1e-300).
+// FP32-perturbation storage layout: the gas deviation E' (5 fields) and each dust
+// species' velocity as a deviation from the stationary flow's velocity at the cell centre
+// (3 per species) in FP32, then the dust densities in FP64 (mass is accumulated in FP64).
+// f64_base: first double of that part.  A dust momentum is read as density x (stationary
+// velocity + stored deviation); it is stored as momentum / density - stationary velocity
+// after the cell's new density, which must therefore be written first (zero deviation
+// where the density is below 1e-300; the velocity of a cell without dust reads as zero).
 __device__ __forceinline__ size_t p32_f64_base(const Geo& g) {
   return (((size_t)(5 + 3 * g.nd) * g.N + 63) / 64 * 64) / 2;
 }
@@ -604,7 +606,8 @@ __device__ __forceinline__ double ld_cell(const StageArgs& a, const void* st, in
     const int sp = (f - 5) >> 2, c = (f - 5) & 3;
     const double rd = ((const double*)st)[p32_f64_base(g) + (size_t)sp * g.N + cell];
     if (c == 3) return rd;
-    return rd * (double)((const float*)st)[(size_t)(5 + 3 * sp + c) * g.N + cell];
+    const double u0 = a.t.wc[((size_t)k * g.nr + i) * WB_N + c];
+    return rd * (u0 + (double)((const float*)st)[(size_t)(5 + 3 * sp + c) * g.N + cell]);
   }
   return ((const double*)st)[(size_t)f * g.N + cell];
 }
@@ -619,23 +622,25 @@ __device__ __forceinline__ void st_cell(const StageArgs& a, void* st, int f, int
     double* dens = (double*)st + p32_f64_base(g) + (size_t)sp * g.N + cell;
     if (c == 3) { *dens = v; return; }
     const double rd = *dens;  // the new density, written before the momenta
-    ((float*)st)[(size_t)(5 + 3 * sp + c) * g.N + cell] = rd > 1e-300 ? (float)(v * frcp(rd)) : 0.0f;
+    const double u0 = a.t.wc[((size_t)k * g.nr + i) * WB_N + c];
+    ((float*)st)[(size_t)(5 + 3 * sp + c) * g.N + cell] = rd > 1e-300 ? (float)(v * frcp(rd) - u0) : 0.0f;
   } else {
     ((double*)st)[(size_t)f * g.N + cell] = v;
   }
 }
 
-// A whole dust cell (momenta r, theta, z, density) into the FP32 layout from registers: the
-// density, then the velocities formed with it (the same values st_cell stores field by field,
-// without reading the density back)
-__device__ __forceinline__ void st_dust32(const StageArgs& a, void* st, int sp, size_t cell,
-                                          const double v[4]) {
+// A whole dust cell (momenta r, theta, z, density) of cell (k, i) into the FP32 layout from
+// registers: the density, then the velocity deviations formed with it (the same values
+// st_cell stores field by field, without reading the density back)
+__device__ __forceinline__ void st_dust32(const StageArgs& a, void* st, int sp, int k, int i,
+                                          size_t cell, const double v[4]) {
   const Geo& g = a.g;
   ((double*)st)[p32_f64_base(g) + (size_t)sp * g.N + cell] = v[3];
   const double ir = v[3] > 1e-300 ? frcp(v[3]) : 0.0;
+  const double* u0 = a.t.wc + ((size_t)k * g.nr + i) * WB_N;
   float* vel = (float*)st + (size_t)(5 + 3 * sp) * g.N + cell;
 #pragma unroll
-  for (int c = 0; c < 3; ++c) vel[(size_t)c * g.N] = v[3] > 1e-300 ? (float)(v[c] * ir) : 0.0f;
+  for (int c = 0; c < 3; ++c) vel[(size_t)c * g.N] = v[3] > 1e-300 ? (float)(v[c] * ir - u0[c]) : 0.0f;
 }
 
 // All NG conservative fields of a group at an interior cell: the gas deviation E', the
@@ -649,9 +654,10 @@ __device__ __forceinline__ void load_cons(const StageArgs& a, const void* st, in
     const int sp = (F0 - 5) >> 2;
     const double rd = ((const double*)st)[p32_f64_base(g) + (size_t)sp * g.N + cell];
     const float* vel = (const float*)st + (size_t)(5 + 3 * sp) * g.N + cell;
-    out[0] = rd * (double)vel[0];
-    out[1] = rd * (double)vel[g.N];
-    out[2] = rd * (double)vel[2 * g.N];
+    const double* u0 = a.t.wc + ((size_t)k * g.nr + i) * WB_N;
+    out[0] = rd * (u0[0] + (double)vel[0]);
+    out[1] = rd * (u0[1] + (double)vel[g.N]);
+    out[2] = rd * (u0[2] + (double)vel[2 * g.N]);
     out[3] = rd;
     return;
   }
@@ -748,12 +754,15 @@ __device__ __forceinline__ void load_recon(const StageArgs& a, const void* st, i
   } else {
     const int sp = (F0 - 5) >> 2;
     if constexpr (P32) {
-      // the FP32 layout stores the dust velocities themselves
+      // the FP32 layout stores the dust velocity deviations from the stationary flow
       const float* vel = (const float*)st + (size_t)(5 + 3 * sp) * g.N + cell;
-      out[0] = (T)vel[0];
-      out[1] = (T)vel[g.N];
-      out[2] = (T)vel[2 * g.N];
-      out[3] = (T)((const double*)st)[p32_f64_base(g) + (size_t)sp * g.N + cell];
+      const double* u0 = a.t.wc + ((size_t)kc * g.nr + i) * WB_N;
+      const double rd = ((const double*)st)[p32_f64_base(g) + (size_t)sp * g.N + cell];
+      const bool full = rd > 0.0;
+      out[0] = full ? (T)(u0[0] + (double)vel[0]) : T(0);
+      out[1] = full ? (T)(u0[1] + (double)vel[g.N]) : T(0);
+      out[2] = full ? (T)(u0[2] + (double)vel[2 * g.N]) : T(0);
+      out[3] = (T)rd;
     } else {
       const double* d = (const double*)st + (size_t)F0 * g.N + cell;
       const double rd = d[3 * g.N];

@@ -51,7 +51,7 @@ struct Ctrl {
 
 // Offsets (in doubles) of the tables inside the work area.
 struct Layout {
-  size_t ctrl, rt, ar, rco, rcell, zc, bgc, bgr, bgz, wc, wr, wz, r0, grav, ghr, ghrw, ghz, ghzw;
+  size_t ctrl, rt, ar, rco, rcell, rface, zc, bgc, bgr, bgz, wc, wr, wz, r0, grav, ghr, ghrw, ghz, ghzw;
   size_t trig, indw, indab, indp, damp, ozr, dtlog, cflp, outp, tsp, red, total;
   int nind;      // blocks of the indirect-gravity sums
   int nblocks;   // stage-kernel blocks

@@ -268,14 +268,18 @@ __global__ void __launch_bounds__(NT) k_march(StageArgs a, int species) {
 #pragma unroll
         for (int s2 = 0; s2 < ND; ++s2) {
           const int o = 5 + 4 * s2;
-          // the FP32 layout stores the dust velocities themselves
+          // the FP32 layout stores the dust velocities as deviations from the stationary
+          // flow's, as the gas W' is: the velocity difference is formed from the deviations
           const double rd = ld_cell<P32>(a, in, o + 3, k, igc, cellw);
           const float* vel = (const float*)in + (size_t)(5 + 3 * s2) * g.N + cellw;
-          const double ud = vel[0], vd = vel[g.N], wd = vel[2 * (size_t)g.N];
+          const bool full = rd > 0.0;
+          const double dud = full ? (double)vel[0] - (double)up : -u;
+          const double dvd = full ? (double)vel[g.N] - (double)vp : -v;
+          const double dwd = full ? (double)vel[2 * (size_t)g.N] - (double)wp : -w2;
           const double its = inv_tstop<EXT>(g, s2, omk, rg, pq);
-          dx += rd * (ud - u) * its;
-          dy += rd * (vd - v) * its;
-          dzz += rd * (wd - w2) * its;
+          dx += rd * dud * its;
+          dy += rd * dvd * its;
+          dzz += rd * dwd * its;
         }
         S[0] += (float)dx;
         S[1] += (float)dy;
@@ -406,7 +410,7 @@ __global__ void __launch_bounds__(NT) k_march(StageArgs a, int species) {
         } else {
           // FP32 dust velocities are formed with the new density (all values above were
           // read before any store, the update may be in place)
-          st_dust32(a, a.out, species, cell, nvd);
+          st_dust32(a, a.out, species, k, ig, cell, nvd);
         }
       }
       if (GAS) {
@@ -712,6 +716,9 @@ __global__ void __launch_bounds__(256) k_tables_r(InitArgs a) {
   const double dth = 2.0 * M_PI / c.ntheta;
   const double dz = twod ? 1.0 : 2.0 * c.z_half / c.nz;
   for (int i = threadIdx.x; i < nr + 4; i += blockDim.x) w[L.rcell + i] = cell_r(c, i - 2);
+  for (int i = threadIdx.x; i <= nr; i += blockDim.x) w[L.rface + i] = face_r(c, i);
+  for (int k = threadIdx.x; k < c.nz; k += blockDim.x)
+    w[L.zc + k] = twod ? 0.0 : (k + 0.5 - 0.5 * c.nz) * dz;
   for (int j = threadIdx.x; j < c.ntheta; j += blockDim.x) {
     const double th = (j + 0.5) * dth;
     w[L.trig + j] = cos(th);
@@ -850,7 +857,7 @@ __global__ void __launch_bounds__(256) k_tables_2d(InitArgs a) {
 }
 
 // store of the initial state: FP64, or the FP32 layout (dust velocity components given
-// directly through dust_vel)
+// directly through dust_vel, stored as deviations from the stationary flow's velocity)
 __device__ __forceinline__ void store_init(const InitArgs& a, int f, int k, int i, size_t cl,
                                            double v, double dust_vel = 0.0) {
   const Geo& g = a.g;
@@ -858,7 +865,8 @@ __device__ __forceinline__ void store_init(const InitArgs& a, int f, int k, int 
     if (f < 5) { ((float*)a.state)[(size_t)f * g.N + cl] = (float)v; return; }
     const int sp = (f - 5) >> 2, c = (f - 5) & 3;
     if (c == 3) { ((double*)a.state)[p32_f64_base(g) + (size_t)sp * g.N + cl] = v; return; }
-    ((float*)a.state)[(size_t)(5 + 3 * sp + c) * g.N + cl] = (float)dust_vel;
+    const double u0 = a.work[a.L.wc + ((size_t)k * g.nr + i) * WB_N + c];
+    ((float*)a.state)[(size_t)(5 + 3 * sp + c) * g.N + cl] = (float)(dust_vel - u0);
   } else {
     ((double*)a.state)[(size_t)f * g.N + cl] = v;
   }
@@ -867,8 +875,8 @@ __device__ __forceinline__ void store_init(const InitArgs& a, int f, int k, int 
 // Initial state: Sod annulus, or the disc with the column Gaussian vortex (streamfunction
 // psi = psi0 exp(-X^2/2 sr^2 - Y^2/2 sa^2), X = r - r_v, Y = r_v wrap(theta - theta_v),
 // centre vorticity 2 Ro Omega_K(r_v) with Ro = -amplitude), density noise
-// rho0 (1 + a xi), unchanged pressure, dust moving with the gas.  Stored as E' (gas) and
-// whole variables (dust).
+// rho0 (1 + a xi) at unchanged pressure, the same on each dust layer from its own noise
+// field, dust moving with the gas.  Stored as E' (gas) and whole variables (dust).
 __global__ void __launch_bounds__(256) k_init_state(InitArgs a) {
   const rb_config& c = a.cfg;
   const Geo& g = a.g;
@@ -919,7 +927,8 @@ __global__ void __launch_bounds__(256) k_init_state(InitArgs a) {
     gas_cons(c.gamma, rho, u, v, e.P * B, q);
     for (int f = 0; f < 5; ++f) store_init(a, f, k, i, cl, q[f] - q0[f]);
     for (int s = 0; s < c.n_dust; ++s) {
-      const double rd = dust_layer(c, s, r, z);
+      const double xd = a.noise ? a.noise[(size_t)(1 + s) * g.N + cl] : 0.0;
+      const double rd = dust_layer(c, s, r, z) * (1.0 + c.noise_amp * xd);
       const int o = 5 + 4 * s;
       store_init(a, o + 0, k, i, cl, rd * u, u);
       store_init(a, o + 1, k, i, cl, rd * v, v);
@@ -966,7 +975,8 @@ __global__ void __launch_bounds__(256) k_amp_grad(InitArgs a, const double* lam,
     double acc = lam[0 * g.N + cl] * rho * uh + lam[1 * g.N + cl] * rho * vh +
                  lam[3 * g.N + cl] * rho * (u * uh + v * vh);
     for (int s = 0; s < c.n_dust; ++s) {
-      const double rd = dust_layer(c, s, r, z);
+      const double xd = a.noise ? a.noise[(size_t)(1 + s) * g.N + cl] : 0.0;
+      const double rd = dust_layer(c, s, r, z) * (1.0 + c.noise_amp * xd);
       const int o = 5 + 4 * s;
       acc += lam[(size_t)(o + 0) * g.N + cl] * rd * uh + lam[(size_t)(o + 1) * g.N + cl] * rd * vh;
     }

@@ -80,7 +80,8 @@ class rb_diag(ctypes.Structure):
 
 # names exported by the library, in the order of include/rossbi_mi355x.h
 EXPORTS = ("rb_query_sizes", "rb_init_state", "rb_step", "rb_get_fields", "rb_set_fields",
-           "rb_eval_operator", "rb_get_residual", "rb_cfl_dt", "rb_diagnostics", "rb_profile",
+           "rb_eval_operator", "rb_get_residual", "rb_get_geometry", "rb_cfl_dt",
+           "rb_diagnostics", "rb_profile",
            "rb_profile_read", "rb_adjoint_workspace", "rb_record", "rb_adjoint",
            "rb_amp_gradient", "rb_last_error", "rb_destroy")
 
@@ -107,6 +108,7 @@ def load() -> ctypes.CDLL:
     L.rb_set_fields.argtypes = [ctypes.c_void_p, _D, ctypes.c_size_t]
     L.rb_eval_operator.argtypes = [ctypes.c_void_p, _D, ctypes.c_size_t]
     L.rb_get_residual.argtypes = [ctypes.c_void_p, _D, ctypes.c_size_t]
+    L.rb_get_geometry.argtypes = [ctypes.c_void_p, _D, _D, _D, _D]
     L.rb_cfl_dt.argtypes = [ctypes.c_void_p, _D]
     L.rb_diagnostics.argtypes = [ctypes.c_void_p, ctypes.POINTER(rb_diag)]
     L.rb_profile.argtypes = [ctypes.c_void_p, ctypes.c_int]
@@ -200,9 +202,10 @@ class Sim:
                           sizes.state_bytes, sizes.stage_bytes, sizes.work_bytes)
         self._noise = None if noise is None else np.ascontiguousarray(noise, dtype=np.float64)
         self._amp = None if amp is None else np.ascontiguousarray(amp, dtype=np.float64)
-        for a in (self._noise, self._amp):
-            if a is not None and a.size != cfg.n_cells:
-                raise ValueError("noise/amp must have one value per cell")
+        if self._noise is not None and self._noise.size != cfg.n_cells * (1 + cfg.n_dust):
+            raise ValueError("noise must have one value per cell and fluid")
+        if self._amp is not None and self._amp.size != cfg.n_cells:
+            raise ValueError("amp must have one value per cell")
         ctx = ctypes.c_void_p()
         st = self.lib.rb_init_state(ctypes.byref(self.c), ctypes.byref(bufs), _ptr(self._noise),
                                     _ptr(self._amp), ctypes.c_void_p(self.stream.cuda_stream),
@@ -275,6 +278,16 @@ class Sim:
         if st != RB_OK:
             raise RbError(st, self.error())
         return out
+
+    def geometry(self) -> dict:
+        """rb_get_geometry: r faces, r centres, cell volume per radial row, z centres."""
+        c = self.cfg
+        g = dict(rf=np.empty(c.nr + 1), rc=np.empty(c.nr), V=np.empty(c.nr), zc=np.empty(c.nz))
+        st = self.lib.rb_get_geometry(self.ctx, _ptr(g["rf"]), _ptr(g["rc"]), _ptr(g["V"]),
+                                      _ptr(g["zc"]))
+        if st != RB_OK:
+            raise RbError(st, self.error())
+        return g
 
     def cfl_dt(self) -> float:
         d = ctypes.c_double()
@@ -357,36 +370,15 @@ class Sim:
         return out
 
 
-def radial_faces(cfg: synth.Config) -> np.ndarray:
-    """Radial face positions of the mesh (log-spaced or uniform)."""
-    i = np.arange(cfg.nr + 1, dtype=np.float64)
-    if cfg.log_r:
-        return cfg.r_in * (cfg.r_out / cfg.r_in) ** (i / cfg.nr)
-    return cfg.r_in + (cfg.r_out - cfg.r_in) * i / cfg.nr
-
-
-def cell_centres_r(cfg: synth.Config) -> np.ndarray:
-    """Radial cell centres, the mid-points of the radial faces."""
-    rf = radial_faces(cfg)
-    return 0.5 * (rf[1:] + rf[:-1])
-
-
-def cell_volumes(cfg: synth.Config) -> np.ndarray:
-    """Cell volumes per radial row (1/2 (r+^2 - r-^2) dtheta dz)."""
-    rf = radial_faces(cfg)
-    dth = 2.0 * np.pi / cfg.nth
-    dz = 1.0 if cfg.nz == 1 else 2.0 * cfg.z_half / cfg.nz
-    return 0.5 * (rf[1:] ** 2 - rf[:-1] ** 2) * dth * dz
-
-
 def _make_disc_run():
     import torch
 
     class DiscRun(torch.autograd.Function):
-        """n RK2 steps of the disc from its initial state, differentiable with respect to
-        the per-cell vortex amplitude field and the Stokes numbers.  Forward: rb_record
-        (checkpoints every ckpt_every steps); backward: rb_adjoint + rb_amp_gradient.
-        Returns the final fields (float64, on the device)."""
+        """n RK2 steps of the disc from its initial state with the given time steps,
+        differentiable with respect to the per-cell vortex amplitude field and the Stokes
+        numbers.  Forward: rb_record (checkpoints every ckpt_every steps); backward:
+        rb_adjoint + rb_amp_gradient.  Returns the final fields (float64, on the device);
+        the gradients come back on the devices of amp and stokes."""
 
         @staticmethod
         def forward(ctx, amp, stokes, cfg, n, ckpt_every, noise, dt_list):
@@ -397,7 +389,7 @@ def _make_disc_run():
             dts = sim.record(n, ckpt_every, dt_list=dt_list)
             out = torch.as_tensor(sim.fields(), device=sim.state.device)
             ctx.sim, ctx.noise, ctx.amp_np, ctx.dts = sim, noise, amp_np, dts
-            ctx.amp_shape, ctx.amp_device = amp.shape, amp.device
+            ctx.amp_shape, ctx.amp_device, ctx.st_device = amp.shape, amp.device, stokes.device
             return out
 
         @staticmethod
@@ -408,7 +400,7 @@ def _make_disc_run():
             sim.close()
             ctx.sim = None
             gamp = gamp.reshape(ctx.amp_shape).to(ctx.amp_device)
-            gst_t = torch.as_tensor(gst, dtype=torch.float64)
+            gst_t = torch.as_tensor(gst, dtype=torch.float64, device=ctx.st_device)
             return gamp, gst_t, None, None, None, None, None
 
     return DiscRun
@@ -417,9 +409,14 @@ def _make_disc_run():
 _disc_run = None
 
 
-def disc_run(amp, stokes, cfg: synth.Config, n: int, ckpt_every: int = 20, noise=None,
-             dt_list=None):
-    """Differentiable n-step disc run (torch.autograd): see DiscRun."""
+def disc_run(amp, stokes, cfg: synth.Config, n: int, dt_list, ckpt_every: int = 20, noise=None):
+    """Differentiable n-step disc run (torch.autograd): see DiscRun.  The time steps are
+    given (dt_list, n entries): the adjoint differentiates the step map at fixed steps, so
+    a run with Courant steps, which depend on the amplitude and the Stokes numbers, has no
+    gradient here."""
+    if dt_list is None or len(dt_list) != n:
+        raise ValueError("disc_run needs the n time steps (dt_list): the gradient is taken at "
+                         "fixed steps")
     global _disc_run
     if _disc_run is None:
         _disc_run = _make_disc_run()

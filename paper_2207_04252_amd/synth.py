@@ -6,9 +6,10 @@ CPU oracle read: it contains parameters and random numbers, and none of the
 method's arithmetic (no mesh, no equilibrium, no flux).
 
 Noise: SplitMix64 (Steele, Lea & Flood, "Fast splittable pseudorandom number
-generators", OOPSLA 2014), keyed by ``seed XOR global cell index`` with the
-global index ``(k*nr + i)*ntheta + j``; the top 53 bits give a uniform double
-in [0, 1) which is mapped to [-1, 1).
+generators", OOPSLA 2014), keyed by ``seed XOR (fluid*ncells + global cell index)``
+with the global index ``(k*nr + i)*ntheta + j`` and fluid 0 the gas, 1 + s dust
+species s; the top 53 bits give a uniform double in [0, 1) which is mapped to
+[-1, 1).  Every fluid's density carries its own noise.
 """
 from __future__ import annotations
 
@@ -176,12 +177,13 @@ def splitmix64(x: np.ndarray) -> np.ndarray:
 
 
 def noise(cfg: Config) -> np.ndarray:
-    """Uniform noise xi in [-1, 1), shape (nz, nr, nth), float64, C order."""
-    n = cfg.n_cells
+    """Uniform noise xi in [-1, 1) for the density of every fluid (gas, then each dust
+    species), shape (1 + n_dust, nz, nr, nth), float64, C order."""
+    n = cfg.n_cells * (1 + cfg.n_dust)
     idx = np.arange(n, dtype=np.uint64)
     z = splitmix64(np.uint64(cfg.seed) ^ idx)
     u = (z >> np.uint64(11)).astype(np.float64) * (1.0 / 9007199254740992.0)
-    return (2.0 * u - 1.0).reshape(cfg.nz, cfg.nr, cfg.nth)
+    return (2.0 * u - 1.0).reshape(1 + cfg.n_dust, cfg.nz, cfg.nr, cfg.nth)
 
 
 def amplitude_field(cfg: Config, amp: float | None = None) -> np.ndarray:

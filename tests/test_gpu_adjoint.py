@@ -202,10 +202,15 @@ def test_adjoint_amplitude_and_stokes_vs_oracle(rb):
 
 def core_mass_cotangent(rb, cfg):
     """dJ/dE of J = dust mass in the vortex core (r in the core band, |theta - theta_v|
-    below the core half-width): the cell volume on each dust density in the core."""
+    below the core half-width): the cell volume on each dust density in the core.  The
+    oracle's mesh, checked against the library's (rb_get_geometry)."""
     geo = oracle.Oracle(cfg).geometry()
     V, rc = geo["V"], geo["rc"]
-    assert np.allclose(V, rb.cell_volumes(cfg), rtol=1e-13)
+    sim = rb.Sim(cfg)
+    g = sim.geometry()
+    sim.close()
+    assert np.allclose(V, g["V"], rtol=1e-13) and np.allclose(rc, g["rc"], rtol=1e-14)
+    assert np.allclose(geo["rf"], g["rf"], rtol=1e-14) and np.allclose(geo["zc"], g["zc"], atol=1e-15)
     th = (np.arange(cfg.nth) + 0.5) * 2 * np.pi / cfg.nth
     mask = ((rc >= synth.CORE_R[0]) & (rc <= synth.CORE_R[1]))[:, None] & \
            (np.abs(th - cfg.vortex_th0) < synth.CORE_DTH)[None, :]
@@ -238,7 +243,7 @@ def test_autograd_matches_finite_differences(rb):
     amp = torch.full((cfg.nz, cfg.nr, cfg.nth), cfg.vortex_amp, dtype=torch.float64,
                      device="cuda", requires_grad=True)
     st = torch.tensor(cfg.stokes, dtype=torch.float64, requires_grad=True)
-    final = rb.disc_run(amp, st, cfg, n, ckpt_every=2, noise=xi, dt_list=dts)
+    final = rb.disc_run(amp, st, cfg, n, dts, ckpt_every=2, noise=xi)
     J = (final * lam).sum()
     J.backward()
     got_amp = float(amp.grad.sum()) * cfg.vortex_amp

@@ -47,7 +47,7 @@ def band_config(cfg):
 def band_reference():
     cfg = CFG
     bcfg = band_config(cfg)
-    xi = synth.noise(cfg)[:, I0:I1, :].copy()
+    xi = synth.noise(cfg)[:, :, I0:I1, :].copy()
     o = oracle.Oracle(bcfg, noise=xi)
     rc = o.geometry()["rc"]
     assert rc[0] < 1.0 < rc[-1]

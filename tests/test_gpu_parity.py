@@ -1,7 +1,8 @@
 """FP64 HIP path against the CPU oracle, through the C ABI (needs an MI355X).
 
-Bar: <= 1e-10 relative per cell (momenta relative to rho c_s) after 100 steps on
-grids that span several tiles with ragged tails in theta and r and several z chunks;
+Bar: <= 1e-10 relative per cell (momenta relative to rho c_s) after 100 free-running
+steps on grids that span several tiles with ragged tails in theta and r and several z
+chunks, and along the oracle's trajectories;
 one step at the full sizes of the gas disc (128x256x64) and the bi-fluid disc
 (256x512x64); bitwise equilibrium, theta symmetry, determinism; the mass ledger;
 error codes.
@@ -106,27 +107,56 @@ def test_trajectory_parity(rb, name, cfg, n):
     say(f"[trajectory] {name}: worst over checkpoints {worst_all}")
 
 
-@pytest.mark.parametrize("name,cfg,n", TRAJ[:4], ids=[c[0] for c in TRAJ[:4]])
-def test_free_run_statistics(rb, name, cfg, n):
-    """Independent n-step runs of both paths.  The discrete dynamics of the vortex discs
-    amplify rounding-size differences (the oracle against itself with a 1e-13 change of
-    the inputs diverges to ~1e-4 in the vortex column), so per cell this is reported,
-    not gated; conserved totals must agree (ledger-determined) and the GPU-oracle gap
-    must stay within the oracle's own rounding divergence."""
-    from tests.parity import conditioned_check
+# independent free runs of both paths: the disc slices above, 100 steps each (the three-
+# species slice narrower in theta, 68 radial cells: nine tiles with a ragged one)
+FREE = TRAJ[:4] + [("bifluid3", synth.C4_LARGE.scaled(68, 64, 32), 100)]
+
+
+@pytest.mark.parametrize("name,cfg,n", FREE, ids=[c[0] for c in FREE])
+def test_free_run_100_steps(rb, name, cfg, n):
+    """Independent 100-step CFL runs of the HIP path and the oracle from the same seeded
+    input: every cell of every gas field, and of every dust field off the two midplane
+    layers, agrees to 1e-10 (densities and energy relative, momenta relative to
+    max(|m|, rho c_s)); the dust of the two midplane cells agrees through their sum (the
+    standing delta shock there, see tests/parity.py); the Courant steps agree to 1e-12
+    and the masses to 1e-13."""
     sim, o, st, dts, gpu, st2, dts2, ref = _pair(rb, cfg, n)
     assert st == rb.RB_OK and st2 == 0, (st, st2, sim.error())
-    o2 = oracle.Oracle(cfg)
-    o2.set_state(oracle.Oracle(cfg, noise=_noise(cfg)).state() *
-                 (1.0 + 1e-13 * synth.random_direction(cfg, seed=3)[None]))
-    o2.step(n)
-    ok, stats = conditioned_check(gpu, ref, o2.state(), cfg.gamma, factor=1000.0)
-    say(f"[free run] {name}: {stats}")
-    assert np.allclose(dts, dts2, rtol=1e-6, atol=0)
-    m_gpu = sim.mass()
-    m_ref = o.mass()
-    assert np.allclose(m_gpu, m_ref, rtol=1e-9, atol=0), (m_gpu, m_ref)
-    assert stats["max_err"] <= max(1e-10, 1000.0 * stats["max_self_sensitivity"])
+    assert np.allclose(dts, dts2, rtol=1e-12, atol=0), np.max(np.abs(dts / dts2 - 1))
+    mid = {}
+    errs = field_errors(gpu, ref, cfg.gamma, cfg.n_dust, mid=mid)
+    say(f"[free run] {name}: " + " ".join(f"{k}={v:.1e}" for k, v in errs.items()))
+    if mid:
+        say(f"[free run] {name}: dust midplane cells (reported) "
+            + " ".join(f"{k}={v:.1e}" for k, v in mid.items()))
+    for k, v in errs.items():
+        assert v <= TOL, (k, v)
+    m_gpu, m_ref = sim.mass(), o.mass()
+    assert np.allclose(m_gpu, m_ref, rtol=1e-13, atol=0), (m_gpu, m_ref)
+
+
+def test_ledger_matches_oracle_each_step(rb):
+    """The mass ledger of both paths, step by step on a bi-fluid slice: the masses agree
+    to 1e-13 relative, and the boundary outflow rates to 1e-13 of the mass per time step
+    (M / dt: the scale of the ledger identity M(n+1) - M(n) = -dt outflow)."""
+    cfg = synth.C3_BIFLUID.scaled(36, 80, 16)
+    say("[ledger vs oracle] " + cfg.name)
+    xi = _noise(cfg)
+    sim = rb.Sim(cfg, noise=xi)
+    o = oracle.Oracle(cfg, noise=xi)
+    for q in range(10):
+        st, dts = sim.step(1)
+        st2, _ = o.step(1, dt_list=dts)
+        assert st == rb.RB_OK and st2 == 0
+        d1, d2 = sim.diagnostics(), o.diag()
+        nm = 1 + cfg.n_dust
+        m1, m2 = np.array(d1.mass[:nm]), np.array(d2.mass[:nm])
+        f1, f2 = np.array(d1.outflow[:nm]), np.array(d2.outflow[:nm])
+        assert np.all(np.abs(m1 / m2 - 1) <= 1e-13), (q, m1, m2)
+        assert np.all(np.abs(f1 - f2) * dts[0] <= 1e-13 * m2), (q, f1, f2)
+        if q == 9:
+            say(f"[ledger vs oracle] masses {np.abs(m1 / m2 - 1).max():.1e}, "
+                f"outflow {np.max(np.abs(f1 - f2) * dts[0] / m2):.1e} of M per step")
 
 
 def test_residual_parity(rb):

@@ -52,11 +52,9 @@ def test_rwi_initial_state(rb, precision):
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32p"])
 def test_rwi_step_parity(rb, precision):
-    """One step from oracle states along an oracle trajectory.  The limiter (reading of
-    Sect. 2.7) switches near its thresholds on the bump's flanks, where the step map
-    amplifies rounding-size input changes by up to ~1e5; each checkpoint's FP64 gate is
-    therefore max(1e-10, 30 x the oracle's own change under a 1e-15 relative input
-    perturbation)."""
+    """One step from oracle states along an oracle trajectory: every cell to 1e-10 in
+    FP64 (the oracle's own change under a 1e-15 relative input perturbation is printed
+    beside it), density to 1e-5 in the FP32-perturbation form."""
     cfg = CFG
     say(f"[rwi step] {cfg.name} {precision}")
     xi = synth.noise(cfg)
@@ -84,10 +82,9 @@ def test_rwi_step_parity(rb, precision):
             sens = worst(field_errors(o2.state(), ref, cfg.gamma, cfg.n_dust))[1]
             o2.close()
             errs = field_errors(gpu, ref, cfg.gamma, cfg.n_dust)
-            gate = max(1e-10, 30 * sens)
             say(f"[rwi step] checkpoint {c}: worst {worst(errs)}, oracle self-change {sens:.2e}")
             for k, v in errs.items():
-                assert v <= gate, (c, k, v, gate)
+                assert v <= 1e-10, (c, k, v)
         else:
             rel = np.abs(gpu[4] - ref[4]) / ref[4]
             say(f"[rwi step] checkpoint {c}: rho {rel.max():.2e}")
