@@ -243,8 +243,9 @@ def cpu_baseline(cfg, budget_s):
                      r_out=cfg.r_in * q ** ((i0 + nb) / cfg.nr), name=cfg.name + "@band")
     xi = synth.noise(cfg)[:, :, i0:i0 + nb, :].copy()
     nproc = os.cpu_count()
+    share = int(os.environ.get("OMP_NUM_THREADS", nproc))  # the host cores this job may use
     out = {}
-    for label, threads in (("all", nproc), ("one", 1)):
+    for label, threads in (("all", share), ("one", 1)):
         used = oracle.set_threads(threads)
         o = oracle.Oracle(band, noise=xi)
         n = 0
@@ -257,7 +258,7 @@ def cpu_baseline(cfg, budget_s):
         dt = time.perf_counter() - t0
         o.close()
         out[label] = {"value": band.n_cells * n / dt, "threads": used, "steps": n, "seconds": dt}
-    oracle.set_threads(nproc)
+    oracle.set_threads(share)
     a, b = out["all"], out["one"]
     return {"value": a["value"], "unit": "zone-updates/s", "cores": a["threads"],
             "kind": "oracle", "nproc": nproc,
@@ -286,6 +287,8 @@ def main():
     ap.add_argument("--adjoint-steps", type=int, default=200)
     ap.add_argument("--headline-only", action="store_true",
                     help="time the headline workload only (for profiling)")
+    ap.add_argument("--calib", action="store_true",
+                    help="first write and read 1 GiB (counter calibration)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -296,6 +299,14 @@ def main():
     import torch
     from paper_2207_04252_amd import rossbi
 
+    if args.calib:
+        # counter calibration: a fill kernel writing 1 GiB, then two reduction kernels
+        # reading it (the buffer is four times the 256 MB last-level cache)
+        src = torch.ones(256 << 20, dtype=torch.float32, device="cuda")
+        tot = [float(src.sum()) for _ in range(2)]
+        torch.cuda.synchronize()
+        del src
+        log(f"calibration: fill 1073741824 bytes, read it twice (sum {tot[0]:.0f})")
     cfg = synth.C4_LARGE
     log(f"headline {cfg.name}, FP32-perturbation form, {args.warmup} + {args.steps} steps")
     r = timed_rate(rossbi, torch, cfg, rossbi.RB_FP32_PERT, args.steps, args.warmup)

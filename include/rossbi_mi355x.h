@@ -114,7 +114,10 @@ typedef struct {
    * (temperature unchanged), v_theta^2 = v_theta0^2 + r c_iso^2 B'/B (radial balance), and
    * v_r = rwi_eps v_theta0 sin(rwi_m theta) exp(-(r - rwi_r0)^2 / (2 rwi_dr^2)).
    * rb_amp_gradient refuses a seeded disc.                                              */
-  int32_t rwi_m, reserved2;
+  int32_t rwi_m;
+  /* Cap on the Newton iterations of the exact gas solver (Sect. 2.6); 0 means 50.  A face
+   * that does not converge within it stops the run with RB_ENOCONV.                     */
+  int32_t newton_max_iter;
   double rwi_delta, rwi_dr, rwi_r0, rwi_eps;
 } rb_config;
 

@@ -60,7 +60,7 @@ class OrConfig(ctypes.Structure):
         ("bc_r", ctypes.c_int32), ("bc_z", ctypes.c_int32),
         ("damp_r_in", ctypes.c_double), ("damp_r_out", ctypes.c_double),
         ("damp_z", ctypes.c_double), ("damp_tau", ctypes.c_double),
-        ("rwi_m", ctypes.c_int32), ("pad2", ctypes.c_int32),
+        ("rwi_m", ctypes.c_int32), ("newton_max_iter", ctypes.c_int32),
         ("rwi_delta", ctypes.c_double), ("rwi_dr", ctypes.c_double),
         ("rwi_r0", ctypes.c_double), ("rwi_eps", ctypes.c_double),
     ]
@@ -108,6 +108,7 @@ def to_struct(cfg: synth.Config) -> OrConfig:
     s.damp_r_in, s.damp_r_out = cfg.damp_r_in, cfg.damp_r_out
     s.damp_z, s.damp_tau = cfg.damp_z, cfg.damp_tau
     s.rwi_m = int(getattr(cfg, "rwi_m", 0))
+    s.newton_max_iter = int(getattr(cfg, "newton_max_iter", 0))
     s.rwi_delta, s.rwi_dr = getattr(cfg, "rwi_delta", 0.0), getattr(cfg, "rwi_dr", 0.05)
     s.rwi_r0, s.rwi_eps = getattr(cfg, "rwi_r0", 1.0), getattr(cfg, "rwi_eps", 0.0)
     return s

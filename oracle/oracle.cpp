@@ -82,7 +82,7 @@ typedef struct {
   double grain_size[4], grain_density[4], mfp_coef;
   int32_t bc_r, bc_z;
   double damp_r_in, damp_r_out, damp_z, damp_tau;
-  int32_t rwi_m, pad2;
+  int32_t rwi_m, newton_max_iter;
   double rwi_delta, rwi_dr, rwi_r0, rwi_eps;
 } OrConfig;
 
@@ -237,7 +237,7 @@ Prim<T> fan_right(const Prim<T>& R, const T& cR, double g) {
  * velocities are passive and taken from the side of the contact containing x/t = 0. */
 template <class T>
 Prim<T> riemann_gas(double g, const Prim<T>& L, const Prim<T>& R, T* pstar_out, T* ustar_out,
-                    RiemannInfo& info) {
+                    RiemannInfo& info, int max_iter = 50) {
   info.iters = 0;
   info.vacuum = 0;
   info.noconv = 0;
@@ -264,7 +264,7 @@ Prim<T> riemann_gas(double g, const Prim<T>& L, const Prim<T>& R, T* pstar_out, 
   T ppv = 0.5 * (L.p + R.p) - 0.125 * du * (L.rho + R.rho) * (cL + cR);
   T p = max_(ppv, T(1e-8 * min_(L.p, R.p)));
   bool conv = false;
-  for (int it = 1; it <= 50; ++it) {
+  for (int it = 1; it <= max_iter; ++it) {
     T dL, dR;
     T fL = pressure_fn(p, L.rho, L.p, cL, g, dL);
     T fR = pressure_fn(p, R.rho, R.p, cR, g, dR);
@@ -820,7 +820,8 @@ struct Sim {
       ++nfall;
     }
     RiemannInfo info;
-    Prim<T> W = riemann_gas(g, WL, WR, (T*)nullptr, (T*)nullptr, info);
+    Prim<T> W = riemann_gas(g, WL, WR, (T*)nullptr, (T*)nullptr, info,
+                            c.newton_max_iter > 0 ? c.newton_max_iter : 50);
     if (info.vacuum) ++nvac;
     if (info.noconv) noconv = 1;
     maxit = std::max(maxit, info.iters);

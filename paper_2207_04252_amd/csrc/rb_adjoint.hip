@@ -424,7 +424,7 @@ struct AdjCtx {
   GasC gc;
   int F0;
   __device__ AdjCtx(const AdjArgs& A_, int species)
-      : A(A_), a(A_.s), g(A_.s.g), gc(gas_consts(A_.s.g.gamma)), F0(GAS ? 0 : 5 + 4 * species) {}
+      : A(A_), a(A_.s), g(A_.s.g), gc(gas_consts(A_.s.g.gamma, A_.s.g.newton_max)), F0(GAS ? 0 : 5 + 4 * species) {}
   __device__ int jwrap(int j) const {
     j %= g.nth;
     return j < 0 ? j + g.nth : j;

@@ -53,6 +53,7 @@ bool validate(const rb_config* c, std::string* why) {
   if (c->n_dust < 0 || c->n_dust > 4) return bad("n_dust must be 0..4");
   if (!(c->gamma > 1.0)) return bad("gamma must exceed 1");
   if (!(c->cfl > 0.0 && c->cfl <= 1.0)) return bad("cfl must be in (0, 1]");
+  if (c->newton_max_iter < 0) return bad("newton_max_iter must be >= 0 (0: the default 50)");
   if (!(c->r_in > 0.0 && c->r_out > c->r_in)) return bad("need 0 < r_in < r_out");
   if (c->nz > 1 && !(c->z_half > 0.0)) return bad("z_half must be positive in 3D");
   if (c->init_kind != RB_INIT_SOD && c->init_kind != RB_INIT_DISC) return bad("unknown init_kind");
@@ -170,6 +171,7 @@ Geo make_geo(const rb_config& c) {
   g.p32 = c.precision == RB_FP32_PERT;
   g.indirect = c.indirect != 0;
   g.drag_law = c.drag_law;
+  g.newton_max = c.newton_max_iter > 0 ? c.newton_max_iter : 50;
   g.bc_z = c.nz > 1 ? c.bc_z : 0;
   g.damp = c.bc_r == 1 || (c.bc_z == 2 && c.nz > 1);
   g.mfp = c.drag_law ? c.mfp_coef : 0.0;

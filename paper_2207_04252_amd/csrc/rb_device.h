@@ -102,10 +102,12 @@ __device__ __forceinline__ double frsq(double x) {
 
 struct GasC {
   double g, gm1, inv_gm1, g2m1, gm1_2g, gp1_2g, kshock, a2, half_gm1, inv_g, inv_gp1_2g, inv_a2;
+  int max_iter;  // Newton iteration cap
 };
 
-__device__ __forceinline__ GasC gas_consts(double g) {
+__device__ __forceinline__ GasC gas_consts(double g, int max_iter = 50) {
   GasC c;
+  c.max_iter = max_iter;
   c.g = g;
   c.gm1 = g - 1.0;
   c.inv_gm1 = 1.0 / (g - 1.0);
@@ -212,7 +214,7 @@ struct GasRec {
 };
 
 // Exact Riemann problem of the ideal gas sampled at x/t = 0 (Sect. 2.6): Newton on p*
-// from the primitive-variable guess (relative change <= 1e-12, at most 50 iterations),
+// from the primitive-variable guess (relative change <= 1e-12, at most c.max_iter),
 // star velocity, then the wave pattern at x/t = 0; tangential velocities come from the
 // side of the contact.  Output: mass, normal momentum, two tangential momenta, energy.
 template <bool G75, bool REC = false>
@@ -303,7 +305,7 @@ __device__ void gas_riemann(const GasC& c, double rL, double irL, double uL, dou
     int it = 0;
     bool conv = false;
     double fL = 0.0, dL = 1.0, fR = 0.0, dR = 1.0, dp = 0.0;
-    while (it < 50) {
+    while (it < c.max_iter) {
       ++it;
       pfun<G75>(ps, L, c, fL, dL);
       pfun<G75>(ps, R, c, fR, dR);
@@ -586,7 +588,8 @@ __device__ __forceinline__ void gas_face_p32(const GasC& c, const float* wA, con
 
 // FP32-perturbation storage layout: the gas deviation E' (5 fields) and each dust
 // species' velocity as a deviation from the stationary flow's velocity at the cell centre
-// (3 per species) in FP32, then the dust densities in FP64 (mass is accumulated in FP64).
+// (3 per species; that velocity is azimuthal, App. A, so only the theta component
+// differs) in FP32, then the dust densities in FP64 (mass is accumulated in FP64).
 // f64_base: first double of that part.  A dust momentum is read as density x (stationary
 // velocity + stored deviation); it is stored as momentum / density - stationary velocity
 // after the cell's new density, which must therefore be written first (zero deviation
@@ -606,7 +609,7 @@ __device__ __forceinline__ double ld_cell(const StageArgs& a, const void* st, in
     const int sp = (f - 5) >> 2, c = (f - 5) & 3;
     const double rd = ((const double*)st)[p32_f64_base(g) + (size_t)sp * g.N + cell];
     if (c == 3) return rd;
-    const double u0 = a.t.wc[((size_t)k * g.nr + i) * WB_N + c];
+    const double u0 = c == 1 ? a.t.wc[((size_t)k * g.nr + i) * WB_N + WB_V] : 0.0;
     return rd * (u0 + (double)((const float*)st)[(size_t)(5 + 3 * sp + c) * g.N + cell]);
   }
   return ((const double*)st)[(size_t)f * g.N + cell];
@@ -622,7 +625,7 @@ __device__ __forceinline__ void st_cell(const StageArgs& a, void* st, int f, int
     double* dens = (double*)st + p32_f64_base(g) + (size_t)sp * g.N + cell;
     if (c == 3) { *dens = v; return; }
     const double rd = *dens;  // the new density, written before the momenta
-    const double u0 = a.t.wc[((size_t)k * g.nr + i) * WB_N + c];
+    const double u0 = c == 1 ? a.t.wc[((size_t)k * g.nr + i) * WB_N + WB_V] : 0.0;
     ((float*)st)[(size_t)(5 + 3 * sp + c) * g.N + cell] = rd > 1e-300 ? (float)(v * frcp(rd) - u0) : 0.0f;
   } else {
     ((double*)st)[(size_t)f * g.N + cell] = v;
@@ -637,10 +640,12 @@ __device__ __forceinline__ void st_dust32(const StageArgs& a, void* st, int sp, 
   const Geo& g = a.g;
   ((double*)st)[p32_f64_base(g) + (size_t)sp * g.N + cell] = v[3];
   const double ir = v[3] > 1e-300 ? frcp(v[3]) : 0.0;
-  const double* u0 = a.t.wc + ((size_t)k * g.nr + i) * WB_N;
+  const double v0 = a.t.wc[((size_t)k * g.nr + i) * WB_N + WB_V];
   float* vel = (float*)st + (size_t)(5 + 3 * sp) * g.N + cell;
-#pragma unroll
-  for (int c = 0; c < 3; ++c) vel[(size_t)c * g.N] = v[3] > 1e-300 ? (float)(v[c] * ir - u0[c]) : 0.0f;
+  const bool full = v[3] > 1e-300;
+  vel[0] = full ? (float)(v[0] * ir) : 0.0f;
+  vel[g.N] = full ? (float)(v[1] * ir - v0) : 0.0f;
+  vel[2 * g.N] = full ? (float)(v[2] * ir) : 0.0f;
 }
 
 // All NG conservative fields of a group at an interior cell: the gas deviation E', the
@@ -654,10 +659,10 @@ __device__ __forceinline__ void load_cons(const StageArgs& a, const void* st, in
     const int sp = (F0 - 5) >> 2;
     const double rd = ((const double*)st)[p32_f64_base(g) + (size_t)sp * g.N + cell];
     const float* vel = (const float*)st + (size_t)(5 + 3 * sp) * g.N + cell;
-    const double* u0 = a.t.wc + ((size_t)k * g.nr + i) * WB_N;
-    out[0] = rd * (u0[0] + (double)vel[0]);
-    out[1] = rd * (u0[1] + (double)vel[g.N]);
-    out[2] = rd * (u0[2] + (double)vel[2 * g.N]);
+    const double v0 = a.t.wc[((size_t)k * g.nr + i) * WB_N + WB_V];
+    out[0] = rd * (double)vel[0];
+    out[1] = rd * (v0 + (double)vel[g.N]);
+    out[2] = rd * (double)vel[2 * g.N];
     out[3] = rd;
     return;
   }
@@ -756,12 +761,12 @@ __device__ __forceinline__ void load_recon(const StageArgs& a, const void* st, i
     if constexpr (P32) {
       // the FP32 layout stores the dust velocity deviations from the stationary flow
       const float* vel = (const float*)st + (size_t)(5 + 3 * sp) * g.N + cell;
-      const double* u0 = a.t.wc + ((size_t)kc * g.nr + i) * WB_N;
+      const double v0 = a.t.wc[((size_t)kc * g.nr + i) * WB_N + WB_V];
       const double rd = ((const double*)st)[p32_f64_base(g) + (size_t)sp * g.N + cell];
       const bool full = rd > 0.0;
-      out[0] = full ? (T)(u0[0] + (double)vel[0]) : T(0);
-      out[1] = full ? (T)(u0[1] + (double)vel[g.N]) : T(0);
-      out[2] = full ? (T)(u0[2] + (double)vel[2 * g.N]) : T(0);
+      out[0] = full ? (T)vel[0] : T(0);
+      out[1] = full ? (T)(v0 + (double)vel[g.N]) : T(0);
+      out[2] = full ? (T)vel[2 * g.N] : T(0);
       out[3] = (T)rd;
     } else {
       const double* d = (const double*)st + (size_t)F0 * g.N + cell;

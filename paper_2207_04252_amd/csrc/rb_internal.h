@@ -66,6 +66,7 @@ struct Geo {
   int drag_law;  // 0 constant Stokes number, 1 Epstein / Stokes regimes
   int bc_z;      // 0 stationary z ghosts, 1 outflow (ghosts repeat the boundary cell), 2 damped
   int damp;      // boundary damping zones present (rate table)
+  int newton_max;  // Newton iteration cap of the exact gas solver
   size_t N;
   double gamma, GM, cfl;
   double inv_st[4];

@@ -40,7 +40,7 @@ __global__ void __launch_bounds__(NT) k_march(StageArgs a, int species) {
   __shared__ T s_fz[LR ? NG : 1][LR ? NT : 1];
 
   const Geo& g = a.g;
-  const GasC gc = gas_consts(g.gamma);
+  const GasC gc = gas_consts(g.gamma, g.newton_max);
   const int F0 = GAS ? 0 : 5 + 4 * species;
   const int slot = GAS ? 0 : 1 + species;
   const int tile = xcd_tile(blockIdx.x, gridDim.x);
@@ -865,7 +865,7 @@ __device__ __forceinline__ void store_init(const InitArgs& a, int f, int k, int 
     if (f < 5) { ((float*)a.state)[(size_t)f * g.N + cl] = (float)v; return; }
     const int sp = (f - 5) >> 2, c = (f - 5) & 3;
     if (c == 3) { ((double*)a.state)[p32_f64_base(g) + (size_t)sp * g.N + cl] = v; return; }
-    const double u0 = a.work[a.L.wc + ((size_t)k * g.nr + i) * WB_N + c];
+    const double u0 = c == 1 ? a.work[a.L.wc + ((size_t)k * g.nr + i) * WB_N + WB_V] : 0.0;
     ((float*)a.state)[(size_t)(5 + 3 * sp + c) * g.N + cl] = (float)(dust_vel - u0);
   } else {
     ((double*)a.state)[(size_t)f * g.N + cl] = v;

@@ -50,7 +50,7 @@ class rb_config(ctypes.Structure):
         ("bc_r", ctypes.c_int32), ("bc_z", ctypes.c_int32),
         ("damp_r_in", ctypes.c_double), ("damp_r_out", ctypes.c_double),
         ("damp_z", ctypes.c_double), ("damp_tau", ctypes.c_double),
-        ("rwi_m", ctypes.c_int32), ("reserved2", ctypes.c_int32),
+        ("rwi_m", ctypes.c_int32), ("newton_max_iter", ctypes.c_int32),
         ("rwi_delta", ctypes.c_double), ("rwi_dr", ctypes.c_double),
         ("rwi_r0", ctypes.c_double), ("rwi_eps", ctypes.c_double),
     ]
@@ -162,6 +162,7 @@ def to_config(cfg: synth.Config, precision: int = RB_FP64) -> rb_config:
     c.damp_r_in, c.damp_r_out, c.damp_z, c.damp_tau = (cfg.damp_r_in, cfg.damp_r_out,
                                                        cfg.damp_z, cfg.damp_tau)
     c.rwi_m = int(cfg.rwi_m)
+    c.newton_max_iter = int(cfg.newton_max_iter)
     c.rwi_delta, c.rwi_dr, c.rwi_r0, c.rwi_eps = (cfg.rwi_delta, cfg.rwi_dr, cfg.rwi_r0,
                                                   cfg.rwi_eps)
     return c

@@ -92,6 +92,9 @@ class Config:
     rwi_dr: float = 0.05
     rwi_r0: float = 1.0
     rwi_eps: float = 0.0
+    # cap on the Newton iterations of the exact gas solver (0: the default 50); a face that
+    # needs more stops the run with the no-convergence error
+    newton_max_iter: int = 0
 
     @property
     def n_dust(self) -> int:

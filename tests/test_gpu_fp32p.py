@@ -116,6 +116,41 @@ def test_fp32p_step_parity(rb, name, cfg, n):
         assert worst[k] <= TOL32, (k, worst)
 
 
+def test_fp32p_strong_perturbation_resolved_in_fp64(rb):
+    """Faces the FP32 perturbation solver does not take -- here a blob of 30% density and
+    pressure excess, beyond its 10% bound -- are re-solved in FP64 on the full states
+    (counted in fp64_resolves): one step against the oracle, density and pressure within
+    1e-5 relative."""
+    cfg = synth.C2_DISC.scaled(44, 72, 16)
+    say("[fp32p fallback] " + cfg.name)
+    o = oracle.Oracle(cfg, noise=synth.noise(cfg))
+    x = o.state()
+    g = o.geometry()
+    r = g["rc"][None, :, None]
+    th = ((np.arange(cfg.nth) + 0.5) * 2 * np.pi / cfg.nth)[None, None, :]
+    blob = 1.0 + 0.3 * np.exp(-((r - 1.1) ** 2) / (2 * 0.03 ** 2) - ((th - 2.0) ** 2) / (2 * 0.2 ** 2))
+    gm1 = cfg.gamma - 1.0
+    ke = 0.5 * (x[0] ** 2 + x[1] ** 2 + x[2] ** 2) / x[4]
+    p = gm1 * (x[3] - ke)
+    x2 = x.copy()
+    x2[:3] *= blob
+    x2[4] *= blob
+    x2[3] = p * blob / gm1 + ke * blob
+    o.set_state(x2)
+    sim = rb.Sim(cfg, precision=rb.RB_FP32_PERT)
+    sim.set_fields(x2)
+    dt = o.cfl_dt()
+    st, _ = sim.step(1, dt=dt)
+    assert st == rb.RB_OK, sim.error()
+    assert o.step(1, dt=dt)[0] == 0
+    e = errors32(sim.fields(), o.state(), cfg)
+    d = sim.diagnostics()
+    say(f"[fp32p fallback] rho {e['rho'].max():.2e} p_rel {e['p_rel'].max():.2e}, "
+        f"FP64 re-solves {d.fp64_resolves}")
+    assert d.fp64_resolves > 0
+    assert e["rho"].max() <= TOL32 and e["p_rel"].max() <= TOL32
+
+
 def test_fp32p_equilibrium_exact(rb):
     cfg = synth.C3_BIFLUID.scaled(24, 64, 32).with_(vortex_amp=0.0, noise_amp=0.0,
                                                     stokes=(), eps_dust=(), hd_over_h=())
@@ -148,11 +183,11 @@ def test_fp32p_500_steps(rb):
     ragged tiles) in the FP32-perturbation form against the FP64 oracle with the same
     time steps.  Density and pressure: within 1e-5 relative in every cell (measured
     8e-7, 1e-6).  Dust density (over cells holding at least 1e-6 of its largest density):
-    the three layers on each side of the midplane face, where the standing delta shock
-    of the settling layer makes the scheme sensitive to its input (the FP64 oracle moves
-    them by up to 1.7e-3 under a 1e-7 relative input change over the same 500 steps), are
-    held to that: within 5e-3; the other layers within 5e-5 (measured 1.9e-5, above the
-    1e-5 target; the oracle's own change there is below 4e-6).  Masses to 1e-12."""
+    within 1e-5 off the three layers on each side of the midplane face (measured 2.4e-6);
+    in those layers the standing delta shock of the settling layer makes the scheme
+    sensitive to its input (the FP64 oracle moves them by up to 1.7e-3 under a 1e-7
+    relative input change over the same 500 steps) and they are held to that, within
+    5e-3 (measured 1.4e-3).  Total masses within 1e-8 (boundary fluxes in FP32)."""
     cfg = synth.C3_BIFLUID.scaled(36, 80, 64)
     say("[fp32p 500 steps] " + cfg.name)
     xi = synth.noise(cfg)
@@ -177,6 +212,6 @@ def test_fp32p_500_steps(rb):
     say(f"[fp32p 500 steps] {rep}")
     for k in ("rho", "p_rel"):
         assert rep[k] <= TOL32, (k, rep)
-    assert rep["dust0_off_band"] <= 5e-5, rep
+    assert rep["dust0_off_band"] <= TOL32, rep
     assert rep["dust0_band"] <= 5e-3, rep
-    assert np.allclose(sim.mass(), o.mass(), rtol=1e-12, atol=0)
+    assert np.allclose(sim.mass(), o.mass(), rtol=1e-8, atol=0), (sim.mass(), o.mass())

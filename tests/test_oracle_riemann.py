@@ -257,3 +257,19 @@ def test_dust_empty_sides(oracle_mod):
     assert np.all(oracle_mod.riemann_dust([0.0, 1.0, 0, 0], [0.0, -1.0, 0, 0]) == 0.0)
     F = oracle_mod.riemann_dust([0.0, 0.0, 0, 0], [1.0, -0.5, 0, 0])
     assert np.allclose(F, [-0.5, 0.25, 0, 0])
+
+
+def test_edge_problems_take_their_branches(oracle_mod):
+    """The diaphragm problems of the GPU edge tests take the branches they are named for:
+    x/t = 0 inside the left rarefaction fan (both Sod states shifted by 0.75 c_L: the
+    sampled state is the sonic point u = c = 2/(g+1) (c_L + (g-1)/2 u_L)); a shock with
+    p*/p_R above 1e4 (pressure ratio 1e5); vacuum between two rarefactions (u = -+5)."""
+    g, cl = 1.4, float(np.sqrt(1.4))
+    W, F, star, it = oracle_mod.riemann_gas(g, [1.0, 0.75 * cl, 0, 0, 1.0],
+                                            [0.125, 0.75 * cl, 0, 0, 0.1])
+    c = 2.0 / (g + 1.0) * (cl + 0.5 * (g - 1.0) * 0.75 * cl)
+    assert W[1] == pytest.approx(c, rel=1e-12) and it > 0
+    W, F, star, it = oracle_mod.riemann_gas(g, [1.0, 0, 0, 0, 1000.0], [1.0, 0, 0, 0, 0.01])
+    assert star[0] / 0.01 > 1e4 and it > 0
+    W, F, star, it = oracle_mod.riemann_gas(g, [1.0, -5.0, 0, 0, 0.01], [1.0, 5.0, 0, 0, 0.01])
+    assert it == -1 and W[0] == 0.0 and np.all(F == 0.0)

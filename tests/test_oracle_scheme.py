@@ -390,3 +390,14 @@ def test_vacuum_flagged(oracle_mod):
     st, _ = o.step(1, dt=1e-5)
     assert st == oracle_mod.EVACUUM
     assert o.diag().vacuum_faces > 0
+
+
+def test_newton_cap_detected(oracle_mod):
+    """A Newton iteration cap of one stops the Sod annulus at its first step with the
+    no-convergence error (the diaphragm problem needs several iterations); the default
+    cap of 50 converges."""
+    cfg = synth.C1_SOD.with_(nr=32, nth=4, newton_max_iter=1)
+    o = oracle_mod.Oracle(cfg)
+    st, _ = o.step(2)
+    assert st == oracle_mod.ENOCONV and o.diag().step == 0
+    assert oracle_mod.Oracle(cfg.with_(newton_max_iter=0)).step(2)[0] == 0
