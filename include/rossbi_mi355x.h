@@ -199,6 +199,21 @@ rb_status rb_get_geometry(rb_ctx* ctx, double* r_faces, double* r_centres, doubl
 /* CFL time step of the current state (Sect. 2.5), computed on the device. */
 rb_status rb_cfl_dt(rb_ctx* ctx, double* dt);
 
+/* For callers that cannot allocate device memory or synchronise with the host (code
+ * under stream capture, tight serving loops): the CFL time step of any state of the
+ * context's layout (device pointer `state`, not modified) into the device double *dt_dev,
+ * or 0.0 there when the state has a cell with a non-positive density or pressure.  The
+ * same kernels as rb_cfl_dt; their partials live in a static device array of 4,136
+ * doubles (33 KB: the control block, the step, 2 x 2,048 block partials) that each device
+ * holds until the process ends.  The CFL kernel strides over the cells with at most 2,048
+ * blocks, so every grid fits; a context whose launch would need more partials is refused
+ * with RB_EINVAL.  No allocation and no host synchronisation: the result is ready when the
+ * context's stream reaches it; errors of the launches themselves return RB_EDEVICE.  The
+ * array keeps the last call's contents and its control block is cleared at the start of
+ * every call.  Every call on a device shares that device's array: calls that overlap on
+ * one device (two streams, two threads) race. */
+rb_status rb_cfl_dt_static(rb_ctx* ctx, const void* state, double* dt_dev);
+
 /* Counters, time, masses (fixed-tree FP64 sums) and the last boundary outflow. */
 rb_status rb_diagnostics(rb_ctx* ctx, rb_diag* out);
 

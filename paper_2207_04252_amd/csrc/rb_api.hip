@@ -7,6 +7,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -38,11 +39,40 @@ struct rb_ctx {
   int rec_n = 0, rec_k = 0;
   std::vector<double> rec_dts;
   void* rec_ws = nullptr;
+  int device = 0;  // the device current at rb_init_state
 };
 
 namespace {
 
 size_t up32(size_t x) { return (x + 31) / 32 * 32; }
+
+// Scratch of rb_cfl_dt_static: a control block, the reduced step and the per-block CFL and
+// stopping-time partials (at most SCRATCH_PARTS blocks), in one file-scope device array.
+// Each device holds its own copy until the process ends; every call on a device shares it.
+constexpr size_t SCRATCH_CTRL = 32, SCRATCH_DT = 8, SCRATCH_PARTS = 2048;
+constexpr size_t SCRATCH_DOUBLES = SCRATCH_CTRL + SCRATCH_DT + 2 * SCRATCH_PARTS;
+static_assert(sizeof(Ctrl) <= SCRATCH_CTRL * sizeof(double), "control block fits the scratch");
+__device__ __align__(256) double scratch[SCRATCH_DOUBLES];
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_dev[MAX_DEVICES] = {};
+
+// The device address of `scratch` on the current device (the array's name in host code is
+// a host-side stand-in, not that address), taken once per device.
+bool scratch_setup(int dev) {
+  if (dev < 0 || dev >= MAX_DEVICES) return false;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_dev[dev]) return true;
+  void* p = nullptr;
+  if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return false;
+  g_scratch_dev[dev] = (double*)p;
+  return true;
+}
+double* scratch_of(int dev) {
+  if (dev < 0 || dev >= MAX_DEVICES) return nullptr;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  return g_scratch_dev[dev];
+}
 
 bool validate(const rb_config* c, std::string* why) {
   auto bad = [&](const char* m) { if (why) *why = m; return false; };
@@ -349,7 +379,10 @@ rb_status rb_init_state(const rb_config* cfg, const rb_buffers* bufs, const doub
     return RB_ENOMEM;
   if (((uintptr_t)bufs->state | (uintptr_t)bufs->stage | (uintptr_t)bufs->work) & 255)
     return RB_EINVAL;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || !scratch_setup(dev)) return RB_EDEVICE;
   rb_ctx* x = new rb_ctx();
+  x->device = dev;
   x->cfg = *cfg;
   x->g = make_geo(*cfg);
   x->L = make_layout(*cfg);
@@ -578,6 +611,25 @@ rb_status rb_get_geometry(rb_ctx* x, double* r_faces, double* r_centres, double*
     if (r_centres) r_centres[i] = rt[(size_t)i * RT_N + RT_RC];
     if (volumes) volumes[i] = rt[(size_t)i * RT_N + RT_V];
   }
+  return RB_OK;
+}
+
+rb_status rb_cfl_dt_static(rb_ctx* x, const void* state, double* dt_dev) {
+  if (!x || !state || !dt_dev) return RB_EINVAL;
+  if ((size_t)x->L.ncfl > SCRATCH_PARTS)
+    return fail(x, RB_EINVAL, "the state needs more CFL partials than the static scratch holds");
+  double* s = scratch_of(x->device);
+  if (!s) return fail(x, RB_EDEVICE, "no static scratch on the context's device");
+  StageArgs a = base_args(x);
+  a.step = 0;
+  a.c.ctrl = reinterpret_cast<Ctrl*>(s);
+  a.c.dtlog = s + SCRATCH_CTRL;
+  a.c.cflp = s + SCRATCH_CTRL + SCRATCH_DT;
+  a.c.tsp = a.c.cflp + SCRATCH_PARTS;
+  HIPCHK(x, launch_ctrl_init(a.c.ctrl, x->stream), "scratch control block");
+  HIPCHK(x, launch_cfl(a, state, x->L.ncfl, 0, x->stream), "cfl");
+  HIPCHK(x, launch_reduce(a, x->L.ncfl, 0, 1, 0, x->stream), "reduce");
+  HIPCHK(x, launch_cfl_out(a.c.ctrl, a.c.dtlog, dt_dev, x->stream), "cfl out");
   return RB_OK;
 }
 

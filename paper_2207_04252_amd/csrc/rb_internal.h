@@ -159,6 +159,8 @@ hipError_t launch_cfl(const StageArgs& a, const void* state, int blocks, int dt_
 hipError_t launch_reduce(const StageArgs& a, int nparts, int dt_idx_next, int want_dt,
                          int want_ledger, hipStream_t s);
 hipError_t launch_fill(double* p, size_t n, double v, hipStream_t s);
+hipError_t launch_ctrl_init(Ctrl* c, hipStream_t s);
+hipError_t launch_cfl_out(const Ctrl* c, const double* dt, double* out, hipStream_t s);
 hipError_t launch_to_full(const StageArgs& a, const void* state, double* out, int f,
                           hipStream_t s);
 hipError_t launch_from_full(const StageArgs& a, const double* in, void* state, int f,

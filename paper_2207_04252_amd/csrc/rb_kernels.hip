@@ -987,6 +987,27 @@ __global__ void __launch_bounds__(256) k_amp_grad(InitArgs a, const double* lam,
 // ------------------------------------------------------------------------------------
 // conversions and reductions
 
+// a fresh control block (no flags, no bad cell), for calls whose control block is not
+// the context's
+__global__ void k_ctrl_init(Ctrl* c) {
+  if (threadIdx.x == 0) {
+    c->status = 0;
+    c->bad_step = -1;
+    c->maxit = 0;
+    c->first_bad = ~0ull;
+    c->nfall = 0;
+    c->nvac = 0;
+    c->nresolve = 0;
+    c->min_ts = 1e300;
+  }
+}
+
+// the reduced CFL step to the caller's slot, or zero when the state had a cell with a
+// non-positive density or pressure
+__global__ void k_cfl_out(const Ctrl* c, const double* dt, double* out) {
+  if (threadIdx.x == 0) out[0] = (c->status & FL_NEG) ? 0.0 : dt[0];
+}
+
 __global__ void k_fill(double* p, size_t n, double v) {
   for (size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x; q < n;
        q += (size_t)gridDim.x * blockDim.x)
@@ -1184,6 +1205,16 @@ hipError_t launch_reduce(const StageArgs& a, int nparts, int dt_idx_next, int wa
                          int want_ledger, hipStream_t s) {
   hipLaunchKernelGGL(k_reduce, dim3(1), dim3(256), 0, s, a, nparts, dt_idx_next, want_dt,
                      want_ledger);
+  return hipGetLastError();
+}
+
+hipError_t launch_ctrl_init(Ctrl* c, hipStream_t s) {
+  hipLaunchKernelGGL(k_ctrl_init, dim3(1), dim3(64), 0, s, c);
+  return hipGetLastError();
+}
+
+hipError_t launch_cfl_out(const Ctrl* c, const double* dt, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_cfl_out, dim3(1), dim3(64), 0, s, c, dt, out);
   return hipGetLastError();
 }
 

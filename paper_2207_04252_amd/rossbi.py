@@ -81,7 +81,7 @@ class rb_diag(ctypes.Structure):
 # names exported by the library, in the order of include/rossbi_mi355x.h
 EXPORTS = ("rb_query_sizes", "rb_init_state", "rb_step", "rb_get_fields", "rb_set_fields",
            "rb_eval_operator", "rb_get_residual", "rb_get_geometry", "rb_cfl_dt",
-           "rb_diagnostics", "rb_profile",
+           "rb_cfl_dt_static", "rb_diagnostics", "rb_profile",
            "rb_profile_read", "rb_adjoint_workspace", "rb_record", "rb_adjoint",
            "rb_amp_gradient", "rb_last_error", "rb_destroy")
 
@@ -110,6 +110,7 @@ def load() -> ctypes.CDLL:
     L.rb_get_residual.argtypes = [ctypes.c_void_p, _D, ctypes.c_size_t]
     L.rb_get_geometry.argtypes = [ctypes.c_void_p, _D, _D, _D, _D]
     L.rb_cfl_dt.argtypes = [ctypes.c_void_p, _D]
+    L.rb_cfl_dt_static.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
     L.rb_diagnostics.argtypes = [ctypes.c_void_p, ctypes.POINTER(rb_diag)]
     L.rb_profile.argtypes = [ctypes.c_void_p, ctypes.c_int]
     L.rb_profile_read.argtypes = [ctypes.c_void_p, _D, ctypes.POINTER(ctypes.c_int64)]
