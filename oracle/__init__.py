@@ -148,6 +148,9 @@ def lib() -> ctypes.CDLL:
         L.or_pressure_fn.restype = ctypes.c_double
         L.or_pressure_fn.argtypes = [ctypes.c_double] * 4 + [_D]
         L.or_riemann_dust.argtypes = [_D, _D, _D]
+        L.or_gas_face_flux.restype = ctypes.c_int
+        L.or_gas_face_flux.argtypes = [ctypes.POINTER(OrConfig), ctypes.c_int, _D, _D, _D,
+                                       ctypes.c_double, _D, _D]
         L.or_parabola_increment.restype = ctypes.c_double
         L.or_parabola_increment.argtypes = [ctypes.c_double] * 7
         L.or_equilibrium.argtypes = [ctypes.POINTER(OrConfig), ctypes.c_double, ctypes.c_double, _D]
@@ -303,6 +306,18 @@ def riemann_dust(WL, WR):
     F = np.zeros(4)
     lib().or_riemann_dust(_ptr(WL), _ptr(WR), _ptr(F))
     return F
+
+
+def gas_face_flux(cfg: synth.Config, direction, q4, q0, x4, xf, qf):
+    """One gas face: full conservative states of the four cells along the direction and their
+    stationary flow, coordinates, the face's stationary flow.  Returns (flux in field
+    order, number of face states that fell back to the cell-centre state)."""
+    s = to_struct(cfg)
+    q4 = _f64(q4); q0 = _f64(q0); x4 = _f64(x4); qf = _f64(qf)
+    out = np.zeros(5)
+    n = lib().or_gas_face_flux(ctypes.byref(s), int(direction), _ptr(q4), _ptr(q0), _ptr(x4),
+                               float(xf), _ptr(qf), _ptr(out))
+    return out, n
 
 
 def parabola_increment(em, e0, ep, xm, x0, xp, xf):

@@ -784,13 +784,15 @@ struct Sim {
    * adjacent cells, exact Riemann problem, F* = F(E*).  Cells a, b, cR, d are the four
    * cells along the direction (a, b left of the face; cR, d right), given by their
    * reconstructed variables (gas W', dust primitives); x their coordinates, xf the face
-   * coordinate; bgf is E0 at the face; kb/ib/jb and kc/ic/jc locate b and cR.  The face
+   * coordinate; bgf is E0 at the face; centre_b / centre_c give the full states of b and
+   * cR (called only when a fallback needs them).  The face
    * state is W0(face) + W'(b) + increment (Sect. 2.7 on the primitive variables); a gas
    * face state with rho <= 0 or P <= 0 (a dust face state with rho_d < 0) is replaced by
    * the cell-centre state. */
+  template <class CB, class CC>
   void face_flux(int dir, const T* va, const T* vb, const T* vc, const T* vd, const double x[4],
-                 double xf, const double* bgf, int kb, int ib, int jb, int kc, int ic, int jc,
-                 bool with_dust, T* F, long& nfall, long& nvac, int& maxit, int& noconv) const {
+                 double xf, const double* bgf, CB&& centre_b, CC&& centre_c, bool with_dust,
+                 T* F, long& nfall, long& nvac, int& maxit, int& noconv) const {
     const double g = c.gamma;
     int nfl = with_dust ? nf : 5;
     double wf[5];
@@ -808,13 +810,13 @@ struct Sim {
     bool haveL = false, haveR = false;
     Prim<T> WL = frame_gas(qL, dir), WR = frame_gas(qR, dir);
     if (!(val(WL.rho) > 0.0 && val(WL.p) > 0.0)) {
-      centre_state(kb, ib, jb, centL); haveL = true;
+      centre_b(centL); haveL = true;
       gas_primitives(centL, wc);
       WL = frame_gas(wc, dir);
       ++nfall;
     }
     if (!(val(WR.rho) > 0.0 && val(WR.p) > 0.0)) {
-      centre_state(kc, ic, jc, centR); haveR = true;
+      centre_c(centR); haveR = true;
       gas_primitives(centR, wc);
       WR = frame_gas(wc, dir);
       ++nfall;
@@ -837,12 +839,12 @@ struct Sim {
     for (int s = 0; s < nd; ++s) {
       int o = 5 + 4 * s;
       if (val(qL[o + 3]) < 0.0) {
-        if (!haveL) { centre_state(kb, ib, jb, centL); haveL = true; }
+        if (!haveL) { centre_b(centL); haveL = true; }
         dust_primitives(&centL[o], &qL[o]);
         ++nfall;
       }
       if (val(qR[o + 3]) < 0.0) {
-        if (!haveR) { centre_state(kc, ic, jc, centR); haveR = true; }
+        if (!haveR) { centre_c(centR); haveR = true; }
         dust_primitives(&centR[o], &qR[o]);
         ++nfall;
       }
@@ -894,8 +896,10 @@ struct Sim {
             vc[f] = recon(f, k, fi, j);     vd[f] = recon(f, k, fi + 1, j);
           }
           double x[4] = {rce(fi - 2), rce(fi - 1), rce(fi), rce(fi + 1)};
-          face_flux(0, va, vb, vc, vd, x, rfa(fi), &bg_r[((size_t)k * (nr + 1) + fi) * nf], k,
-                    fi - 1, j, k, fi, j, with_dust, F, nfall, nvac, maxit, noconv);
+          face_flux(0, va, vb, vc, vd, x, rfa(fi), &bg_r[((size_t)k * (nr + 1) + fi) * nf],
+                    [&](T* q) { centre_state(k, fi - 1, j, q); },
+                    [&](T* q) { centre_state(k, fi, j, q); }, with_dust, F, nfall, nvac, maxit,
+                    noconv);
           for (int f = 0; f < nfl; ++f) Fr[(((size_t)f * nz + k) * (nr + 1) + fi) * nth + j] = F[f];
         }
     /* theta faces: face j+1/2 between cells j and j+1 (periodic), index coordinates */
@@ -909,8 +913,10 @@ struct Sim {
             vc[f] = recon(f, k, i, j + 1); vd[f] = recon(f, k, i, j + 2);
           }
           double x[4] = {(double)(j - 1), (double)j, (double)(j + 1), (double)(j + 2)};
-          face_flux(1, va, vb, vc, vd, x, j + 0.5, &bg_c[((size_t)k * nr + i) * nf], k, i, j, k, i,
-                    j + 1, with_dust, F, nfall, nvac, maxit, noconv);
+          face_flux(1, va, vb, vc, vd, x, j + 0.5, &bg_c[((size_t)k * nr + i) * nf],
+                    [&](T* q) { centre_state(k, i, j, q); },
+                    [&](T* q) { centre_state(k, i, j + 1, q); }, with_dust, F, nfall, nvac, maxit,
+                    noconv);
           for (int f = 0; f < nfl; ++f) Fth[(((size_t)f * nz + k) * nr + i) * nth + j] = F[f];
         }
     /* z faces: face fk at zf[fk], between cells fk-1 and fk, index coordinates */
@@ -925,8 +931,10 @@ struct Sim {
               vc[f] = recon(f, fk, i, j);     vd[f] = recon(f, fk + 1, i, j);
             }
             double x[4] = {(double)(fk - 2), (double)(fk - 1), (double)fk, (double)(fk + 1)};
-            face_flux(2, va, vb, vc, vd, x, fk - 0.5, &bg_z[((size_t)fk * nr + i) * nf], fk - 1, i,
-                      j, fk, i, j, with_dust, F, nfall, nvac, maxit, noconv);
+            face_flux(2, va, vb, vc, vd, x, fk - 0.5, &bg_z[((size_t)fk * nr + i) * nf],
+                      [&](T* q) { centre_state(fk - 1, i, j, q); },
+                      [&](T* q) { centre_state(fk, i, j, q); }, with_dust, F, nfall, nvac, maxit,
+                      noconv);
             for (int f = 0; f < nfl; ++f) Fz[(((size_t)f * (nz + 1) + fk) * nr + i) * nth + j] = F[f];
           }
     }
@@ -1452,6 +1460,30 @@ double or_pressure_fn(double g, double p, double rhoK, double pK, double* dfdp) 
 void or_riemann_dust(const double* WL, const double* WR, double* flux) {
   Prim<double> L{WL[0], WL[1], WL[2], WL[3], 0.0}, R{WR[0], WR[1], WR[2], WR[3], 0.0};
   riemann_dust(L, R, flux);
+}
+
+/* One gas face for unit tests (Sect. 2.6-2.7): the four cells A, B | C, D along direction
+ * dir (0 r, 1 theta, 2 z) given by their full conservative gas states q4[4][5] and their
+ * stationary flow q0[4][5], coordinates x4, face coordinate xf, stationary flow at the face
+ * qf[5]; flux[5] in field order; returns the number of face states that fell back to the
+ * cell-centre state.  The configuration supplies gamma and the kind of split. */
+int or_gas_face_flux(const OrConfig* cfg, int dir, const double* q4, const double* q0,
+                     const double* x4, double xf, const double* qf, double* flux) {
+  OrConfig c1 = *cfg;
+  c1.n_dust = 0;
+  Sim<double> s;
+  if (!s.setup(c1)) return -1;
+  double w[4][24];
+  for (int a = 0; a < 4; ++a) s.recon_vars(q4 + 5 * a, q0 + 5 * a, w[a], 5);
+  long nfall = 0, nvac = 0;
+  int maxit = 0, noconv = 0;
+  double F[24];
+  s.face_flux(dir, w[0], w[1], w[2], w[3], x4, xf, qf,
+              [&](double* q) { for (int f = 0; f < 5; ++f) q[f] = q4[5 + f]; },
+              [&](double* q) { for (int f = 0; f < 5; ++f) q[f] = q4[10 + f]; }, false, F, nfall,
+              nvac, maxit, noconv);
+  for (int f = 0; f < 5; ++f) flux[f] = F[f];
+  return (int)nfall;
 }
 
 /* Limited parabola increment for unit tests. */

@@ -273,3 +273,88 @@ def test_edge_problems_take_their_branches(oracle_mod):
     assert star[0] / 0.01 > 1e4 and it > 0
     W, F, star, it = oracle_mod.riemann_gas(g, [1.0, -5.0, 0, 0, 0.01], [1.0, 5.0, 0, 0, 0.01])
     assert it == -1 and W[0] == 0.0 and np.all(F == 0.0)
+
+
+def test_sonic_fan_invariants_right(oracle_mod):
+    """Mirror of the left sonic test: a transonic right rarefaction leaves at x/t = 0 the
+    state u = -c on the right state's isentrope and Riemann invariant u - 2c/(g-1)."""
+    rR, pR = 1.0, 1.0
+    cR = math.sqrt(G * pR / rR)
+    u0 = -0.75 * cR
+    W, F, star, it = oracle_mod.riemann_gas(G, [0.125, u0, 0, 0, 0.1], [rR, u0, 0, 0, pR])
+    rho, u, p = W[0], W[1], W[4]
+    c = math.sqrt(G * p / rho)
+    assert abs(u + c) < 1e-12
+    assert abs((u - 2 * c / (G - 1)) - (u0 - 2 * cR / (G - 1))) < 1e-12
+    assert abs(p / rho ** G - pR / rR ** G) < 1e-12
+
+
+@pytest.mark.parametrize("side", ["left", "right"])
+def test_vacuum_fan_states(oracle_mod, side):
+    """A vacuum-generating problem sampled inside a rarefaction that borders the vacuum:
+    the state at x/t = 0 is sonic (u = +-c) on that side's isentrope and Riemann
+    invariant, and the solver reports vacuum."""
+    r0, p0 = 1.0, 0.4
+    c0 = math.sqrt(G * p0 / r0)
+    if side == "left":
+        uL = -0.3 * c0
+        WL, WR = [r0, uL, 0.2, -0.1, p0], [0.5, uL + 9.0, 0, 0, 0.3]
+        W, F, star, it = oracle_mod.riemann_gas(G, WL, WR)
+        sgn, (rK, uK, pK) = 1.0, (r0, uL, p0)
+        assert W[2] == 0.2 and W[3] == -0.1
+    else:
+        uR = 0.3 * c0
+        WL, WR = [0.5, uR - 9.0, 0, 0, 0.3], [r0, uR, 0.2, -0.1, p0]
+        W, F, star, it = oracle_mod.riemann_gas(G, WL, WR)
+        sgn, (rK, uK, pK) = -1.0, (r0, uR, p0)
+    assert it == -1
+    cK = math.sqrt(G * pK / rK)
+    rho, u, p = W[0], W[1], W[4]
+    c = math.sqrt(G * p / rho)
+    assert abs(u - sgn * c) < 1e-12
+    assert abs((u + sgn * 2 * c / (G - 1)) - (uK + sgn * 2 * cK / (G - 1))) < 1e-12
+    assert abs(p / rho ** G - pK / rK ** G) < 1e-12
+    assert F[0] == pytest.approx(rho * u, rel=1e-14)
+
+
+def _disc_point(oracle_mod, cfg, r, z):
+    rho, P, v = oracle_mod.equilibrium(cfg, r, z)
+    return np.array([0.0, rho * v, 0.0, P / (cfg.gamma - 1.0) + 0.5 * rho * v * v, rho])
+
+
+def test_positivity_fallback_face(oracle_mod):
+    """The face-state fallback (a reconstructed gas face state with P <= 0 is replaced by
+    the cell-centre state).  The top z face of a disc column whose top cell holds 1% of the
+    stationary pressure: the parabola on its pressure deviation, added to the face's
+    thinner stationary flow, gives a negative pressure, so the left state is the cell's
+    own; the right state (the ghost, stationary) is the face's stationary flow.  The flux
+    is then the exact Riemann flux between those two states.  With 90% instead of 1% no
+    state falls back."""
+    from paper_2207_04252_amd import synth
+    cfg = synth.C2_DISC.scaled(4, 4, 8).with_(vortex_amp=0.0, noise_amp=0.0)
+    o = oracle_mod.Oracle(cfg)
+    g = o.geometry()
+    r = g["rc"][1]
+    dz = 2 * cfg.z_half / cfg.nz
+    zc = [(k + 0.5 - 0.5 * cfg.nz) * dz for k in range(cfg.nz - 2, cfg.nz + 2)]
+    q0 = np.array([_disc_point(oracle_mod, cfg, r, z) for z in zc])
+    qf = _disc_point(oracle_mod, cfg, r, cfg.z_half)
+    x4 = np.array([cfg.nz - 2, cfg.nz - 1, cfg.nz, cfg.nz + 1], float)
+    for frac, expect_fall in ((0.01, 1), (0.9, 0)):
+        q4 = q0.copy()
+        ke = 0.5 * q4[1, 1] ** 2 / q4[1, 4]
+        p = (cfg.gamma - 1.0) * (q4[1, 3] - ke)
+        q4[1, 3] = frac * p / (cfg.gamma - 1.0) + ke
+        F, nfall = oracle_mod.gas_face_flux(cfg, 2, q4, q0, x4, cfg.nz - 0.5, qf)
+        assert nfall == expect_fall, (frac, nfall)
+        rhoB, vB = q4[1, 4], q4[1, 1] / q4[1, 4]
+        rhoF, vF = qf[4], qf[1] / qf[4]
+        pF = (cfg.gamma - 1.0) * (qf[3] - 0.5 * rhoF * vF * vF)
+        # face frame of z: (rho, w, u_r, v_theta, P)
+        _, flux, _, _ = oracle_mod.riemann_gas(cfg.gamma, [rhoB, 0.0, 0.0, vB, frac * p],
+                                               [rhoF, 0.0, 0.0, vF, pF])
+        want = np.array([flux[2], flux[3], flux[1], flux[4], flux[0]])
+        if expect_fall:
+            assert np.allclose(F, want, rtol=1e-12, atol=1e-14 * np.abs(want).max()), (F, want)
+        else:
+            assert not np.allclose(F, want, rtol=1e-6)
