@@ -124,8 +124,9 @@ typedef struct {
 /* Caller-owned device buffers.  Sizes come from rb_query_sizes; pointers must be
  * 256-byte aligned device addresses that stay valid until rb_destroy. */
 /* State layout.  FP64: all fields in FP64, field-major.  FP32-perturbation: the gas
- * deviation E' (5 fields) and the dust velocities, momentum / density (3 per species), in
- * FP32, padded to a multiple of 64 floats, then the dust densities in FP64.
+ * deviation E' (5 fields) and the dust velocity deviations from the stationary flow's
+ * (3 per species: radial, azimuthal minus the gas equilibrium's, vertical), in FP32,
+ * padded to a multiple of 64 floats, then the dust densities in FP64.
  * rb_get_fields / rb_set_fields always exchange FP64 full values. */
 typedef struct {
   void* state;   /* the state (layout above)                                          */
@@ -148,6 +149,13 @@ typedef struct {
   double outflow[5];      /* boundary mass outflow rate of the last second stage     */
   double dt_last;         /* last time step                                          */
   int64_t fp64_resolves;  /* FP32-perturbation faces re-solved by the FP64 solver    */
+  int64_t newton_hist[8]; /* gas face solves by the Newton iteration count of the     */
+                          /* solve whose flux was kept (Sect. 2.6): bin 0 none needed */
+                          /* (supersonic face, vacuum), bins 1-6 that many, bin 7     */
+                          /* seven or more; every face of the mesh once per stage     */
+                          /* evaluation                                               */
+  int64_t negative_dust;  /* cells and species whose dust density was negative at the */
+                          /* end of a step, summed over steps                         */
 } rb_diag;
 
 typedef struct rb_ctx rb_ctx;

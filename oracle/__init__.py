@@ -74,6 +74,7 @@ class OrDiag(ctypes.Structure):
         ("max_newton", ctypes.c_int32), ("pad", ctypes.c_int32),
         ("mass", ctypes.c_double * 5), ("outflow", ctypes.c_double * 5),
         ("dt_last", ctypes.c_double),
+        ("newton_hist", ctypes.c_int64 * 8), ("negative_dust", ctypes.c_int64),
     ]
 
 

@@ -99,6 +99,9 @@ typedef struct {
   double mass[5];     /* gas, dust species 0..3, after the last step          */
   double outflow[5];  /* boundary mass outflow rate of the last second stage   */
   double dt_last;
+  int64_t newton_hist[8]; /* gas face solves by Newton iteration count (0: vacuum;   */
+                          /* 7: seven or more), every face once per evaluation        */
+  int64_t negative_dust;  /* dust densities negative at the end of a step, summed    */
 } OrDiag;
 
 }  // extern "C"
@@ -433,6 +436,8 @@ struct Sim {
   long first_bad_cell = -1;
   long fallbacks = 0, vacuum_faces = 0;
   int max_newton = 0;
+  long newton_hist[8] = {0, 0, 0, 0, 0, 0, 0, 0};  /* gas solves by Newton iterations */
+  long negative_dust = 0;  /* dust densities negative at the end of a step */
   double outflow[5] = {0, 0, 0, 0, 0};
   double dt_last = 0.0;
 
@@ -792,7 +797,7 @@ struct Sim {
   template <class CB, class CC>
   void face_flux(int dir, const T* va, const T* vb, const T* vc, const T* vd, const double x[4],
                  double xf, const double* bgf, CB&& centre_b, CC&& centre_c, bool with_dust,
-                 T* F, long& nfall, long& nvac, int& maxit, int& noconv) const {
+                 T* F, long& nfall, long& nvac, int& maxit, int& noconv, long* hist) const {
     const double g = c.gamma;
     int nfl = with_dust ? nf : 5;
     double wf[5];
@@ -827,6 +832,7 @@ struct Sim {
     if (info.vacuum) ++nvac;
     if (info.noconv) noconv = 1;
     maxit = std::max(maxit, info.iters);
+    hist[std::min(info.vacuum ? 0 : info.iters, 7)]++;
     T fl[5];
     gas_flux(g, W, fl);
     int t1 = dir == 0 ? 1 : 0, t2 = dir == 2 ? 1 : 2;
@@ -885,8 +891,9 @@ struct Sim {
         }
     long nfall = 0, nvac = 0;
     int maxit = 0, noconv = 0;
+    long nh[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     /* r faces: face fi at rf[fi], between cells fi-1 and fi */
-#pragma omp parallel for collapse(2) schedule(static) reduction(+ : nfall, nvac) reduction(max : maxit, noconv)
+#pragma omp parallel for collapse(2) schedule(static) reduction(+ : nfall, nvac, nh) reduction(max : maxit, noconv)
     for (int k = 0; k < nz; ++k)
       for (int fi = 0; fi <= nr; ++fi)
         for (int j = 0; j < nth; ++j) {
@@ -899,11 +906,11 @@ struct Sim {
           face_flux(0, va, vb, vc, vd, x, rfa(fi), &bg_r[((size_t)k * (nr + 1) + fi) * nf],
                     [&](T* q) { centre_state(k, fi - 1, j, q); },
                     [&](T* q) { centre_state(k, fi, j, q); }, with_dust, F, nfall, nvac, maxit,
-                    noconv);
+                    noconv, nh);
           for (int f = 0; f < nfl; ++f) Fr[(((size_t)f * nz + k) * (nr + 1) + fi) * nth + j] = F[f];
         }
     /* theta faces: face j+1/2 between cells j and j+1 (periodic), index coordinates */
-#pragma omp parallel for collapse(2) schedule(static) reduction(+ : nfall, nvac) reduction(max : maxit, noconv)
+#pragma omp parallel for collapse(2) schedule(static) reduction(+ : nfall, nvac, nh) reduction(max : maxit, noconv)
     for (int k = 0; k < nz; ++k)
       for (int i = 0; i < nr; ++i)
         for (int j = 0; j < nth; ++j) {
@@ -916,12 +923,12 @@ struct Sim {
           face_flux(1, va, vb, vc, vd, x, j + 0.5, &bg_c[((size_t)k * nr + i) * nf],
                     [&](T* q) { centre_state(k, i, j, q); },
                     [&](T* q) { centre_state(k, i, j + 1, q); }, with_dust, F, nfall, nvac, maxit,
-                    noconv);
+                    noconv, nh);
           for (int f = 0; f < nfl; ++f) Fth[(((size_t)f * nz + k) * nr + i) * nth + j] = F[f];
         }
     /* z faces: face fk at zf[fk], between cells fk-1 and fk, index coordinates */
     if (!twod) {
-#pragma omp parallel for collapse(2) schedule(static) reduction(+ : nfall, nvac) reduction(max : maxit, noconv)
+#pragma omp parallel for collapse(2) schedule(static) reduction(+ : nfall, nvac, nh) reduction(max : maxit, noconv)
       for (int fk = 0; fk <= nz; ++fk)
         for (int i = 0; i < nr; ++i)
           for (int j = 0; j < nth; ++j) {
@@ -934,12 +941,13 @@ struct Sim {
             face_flux(2, va, vb, vc, vd, x, fk - 0.5, &bg_z[((size_t)fk * nr + i) * nf],
                       [&](T* q) { centre_state(fk - 1, i, j, q); },
                       [&](T* q) { centre_state(fk, i, j, q); }, with_dust, F, nfall, nvac, maxit,
-                      noconv);
+                      noconv, nh);
             for (int f = 0; f < nfl; ++f) Fz[(((size_t)f * (nz + 1) + fk) * nr + i) * nth + j] = F[f];
           }
     }
     fallbacks += nfall;
     vacuum_faces += nvac;
+    for (int b = 0; b < 8; ++b) newton_hist[b] += nh[b];
     max_newton = std::max(max_newton, maxit);
     if (nvac) flags |= F_VAC;
     if (noconv) flags |= F_NOCONV;
@@ -1240,6 +1248,9 @@ struct Sim {
           }
         }
     boundary_outflow(outflow);
+    for (int q = 0; q < nd; ++q)
+      for (size_t id = 0; id < N; ++id)
+        if (val(E[(size_t)(5 + 4 * q + 3) * N + id]) < 0.0) ++negative_dust;
     if (flags & F_NOCONV) return OR_ENOCONV;
     bad = first_negative(E);
     if (bad >= 0) { flags |= F_NEG; record_bad(bad); return OR_ENEGATIVE; }
@@ -1395,6 +1406,8 @@ void or_diag(void* h, OrDiag* d) {
   s->masses(d->mass);
   for (int q = 0; q < 5; ++q) d->outflow[q] = s->outflow[q];
   d->dt_last = s->dt_last;
+  for (int b = 0; b < 8; ++b) d->newton_hist[b] = s->newton_hist[b];
+  d->negative_dust = s->negative_dust;
 }
 
 /* indirect-gravity sums A, B of the current state (evaluates the operator once) */
@@ -1477,11 +1490,12 @@ int or_gas_face_flux(const OrConfig* cfg, int dir, const double* q4, const doubl
   for (int a = 0; a < 4; ++a) s.recon_vars(q4 + 5 * a, q0 + 5 * a, w[a], 5);
   long nfall = 0, nvac = 0;
   int maxit = 0, noconv = 0;
+  long nh[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   double F[24];
   s.face_flux(dir, w[0], w[1], w[2], w[3], x4, xf, qf,
               [&](double* q) { for (int f = 0; f < 5; ++f) q[f] = q4[5 + f]; },
               [&](double* q) { for (int f = 0; f < 5; ++f) q[f] = q4[10 + f]; }, false, F, nfall,
-              nvac, maxit, noconv);
+              nvac, maxit, noconv, nh);
   for (int f = 0; f < 5; ++f) flux[f] = F[f];
   return (int)nfall;
 }

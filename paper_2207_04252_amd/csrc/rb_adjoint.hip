@@ -291,7 +291,7 @@ __device__ void gas_face_vjp(const GasC& c, const double* wA, const double* wB, 
   double WLb[5], WRb[5];
   {
     double fl[5];
-    TStat st = {0, 0, 0, 0, 0};
+    TStat st = {0, 0, 0, 0, 0, 0, 0};
     GasRec rec;
     gas_riemann<G75, true>(c, qL[4], frcp(qL[4]), qL[N], qL[T1], qL[T2], qL[3], qR[4], frcp(qR[4]),
                            qR[N], qR[T1], qR[T2], qR[3], fl, st, &rec);

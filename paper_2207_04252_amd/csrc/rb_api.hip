@@ -132,7 +132,7 @@ Layout make_layout(const rb_config& c) {
     int tk = 2;
     const char* env = std::getenv("RB_TK");
     if (env && std::atoi(env) > 0) {
-      tk = std::atoi(env);
+      tk = std::min(std::atoi(env), 4096);  // the Newton histogram's 16-bit bins
     } else {
       // One 512-thread workgroup fills a CU (256 VGPRs: two waves per SIMD), so a launch
       // runs in ceil(blocks / 256) rounds on the 256 CUs of an MI355X; a block marches tk
@@ -685,6 +685,8 @@ rb_status rb_diagnostics(rb_ctx* x, rb_diag* out) {
   }
   out->dt_last = x->dt_last;
   out->fp64_resolves = (int64_t)c.nresolve;
+  for (int b = 0; b < 8; ++b) out->newton_hist[b] = (int64_t)c.newton_hist[b];
+  out->negative_dust = (int64_t)c.nnegd;
   return RB_OK;
 }
 

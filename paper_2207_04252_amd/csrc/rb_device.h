@@ -192,6 +192,8 @@ __device__ __forceinline__ void pfun(double p, const Side& K, const GasC& c, dou
 
 struct TStat {
   int fall, vac, maxit, noconv, resolve;
+  int last;  // Newton iterations of the latest gas solve (0: none was needed)
+  int negd;  // dust densities that came out negative
 };
 
 // Wave pattern taken by the exact gas solver at x/t = 0 (kept by the adjoint, which
@@ -248,6 +250,7 @@ __device__ void gas_riemann(const GasC& c, double rL, double irL, double uL, dou
             rec->branch = GR_LEFT;
             rec->rho = rL; rec->un = uL; rec->t1 = aL; rec->t2 = bL; rec->p = pL;
           }
+          st.last = 0;
           const double m0 = rL * uL;
           const double en = pL * c.inv_gm1 + 0.5 * rL * (uL * uL + aL * aL + bL * bL);
           fl[0] = m0; fl[1] = m0 * uL + pL; fl[2] = m0 * aL; fl[3] = m0 * bL; fl[4] = (en + pL) * uL;
@@ -266,6 +269,7 @@ __device__ void gas_riemann(const GasC& c, double rL, double irL, double uL, dou
             rec->branch = GR_RIGHT;
             rec->rho = rR; rec->un = uR; rec->t1 = aR; rec->t2 = bR; rec->p = pR;
           }
+          st.last = 0;
           const double m0 = rR * uR;
           const double en = pR * c.inv_gm1 + 0.5 * rR * (uR * uR + aR * aR + bR * bR);
           fl[0] = m0; fl[1] = m0 * uR + pR; fl[2] = m0 * aR; fl[3] = m0 * bR; fl[4] = (en + pR) * uR;
@@ -281,6 +285,7 @@ __device__ void gas_riemann(const GasC& c, double rL, double irL, double uL, dou
   if (c.g2m1 * (cL + cR) <= du) {
     // vacuum between two rarefactions
     st.vac++;
+    st.last = 0;
     double sHL = uL - cL, sSL = uL + c.g2m1 * cL, sSR = uR - c.g2m1 * cR, sHR = uR + cR;
     int br;
     if (0.0 <= sHL) { rho = rL; un = uL; t1 = aL; t2 = bL; p = pL; br = GR_LEFT; }
@@ -318,6 +323,7 @@ __device__ void gas_riemann(const GasC& c, double rL, double irL, double uL, dou
       if (done) { conv = true; break; }
     }
     st.maxit = max(st.maxit, it);
+    st.last = it;
     if (!conv) st.noconv = 1;
     // star velocity at the converged p*: the last iterate's f and f' extrapolated over
     // the final (<= 1e-12 relative) Newton update; the neglected term is O(dp^2)

@@ -46,7 +46,8 @@ struct Ctrl {
   unsigned long long nresolve;  // FP32-perturbation faces re-solved in FP64
   double min_ts;          // smallest dust stopping time (init)
   double outflow[5];      // boundary mass outflow of the last second stage
-  double scratch[7];
+  unsigned long long newton_hist[8];  // gas Newton solves by iteration count (7: >= 7)
+  unsigned long long nnegd;           // dust densities negative at the end of a step
 };
 
 // Offsets (in doubles) of the tables inside the work area.

@@ -63,7 +63,22 @@ __global__ void __launch_bounds__(NT) k_march(StageArgs a, int species) {
   const void* in = a.in;
   const double dt = a.dt_idx >= 0 ? a.c.dtlog[a.dt_idx] : 0.0;
 
-  TStat st = {0, 0, 0, 0, 0};
+  TStat st = {0, 0, 0, 0, 0, 0, 0};
+  // histogram of the Newton iteration counts (bins 0..7, 7: seven or more) over the
+  // faces the thread owns (each face of the mesh is owned by one thread of the launch),
+  // 16 bits a bin in LDS slots private to the thread; a thread owns at most 4 faces per
+  // plane and one more
+  __shared__ unsigned s_nh[GAS ? 4 : 1][GAS ? NT : 1];
+  if constexpr (GAS) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) s_nh[q][tid] = 0u;
+  }
+  auto tally = [&](bool own) {
+    if constexpr (GAS) {
+      const int b = min(st.last, 7);
+      if (own) s_nh[b >> 1][tid] += 1u << (16 * (b & 1));
+    }
+  };
   double dtmin = 1e300;
   double tsmin = 1e300;  // smallest stopping time of the new state (drag law 1)
   double ledger = 0.0;
@@ -100,6 +115,7 @@ __global__ void __launch_bounds__(NT) k_march(StageArgs a, int species) {
     const double* bf = a.t.wz + ((size_t)k0 * g.nr + igc) * WB_N;
     face(DZ(), e2, rm, r0, rp, nullptr, nullptr, bf, bg_ptr(a, k0 - 1, igc), bg_ptr(a, k0, igc),
          fzlo);
+    if (GAS) tally(act && k0 == 0);
     if (a.second && k0 == 0 && act) {
       double fm = (double)fzlo[NG - 1];
       if (PG) fm += bf[WB_RHO] * bf[WB_W];  // background normal mass flux rho0 w0
@@ -159,6 +175,7 @@ __global__ void __launch_bounds__(NT) k_march(StageArgs a, int species) {
       {
         const double* bf = a.t.wc + ((size_t)k * g.nr + igc) * WB_N;
         face(DT(), eA, eB, eC, eD, nullptr, nullptr, bf, bf, bf, F);
+        if (GAS) tally(act);
       }
 #pragma unroll
       for (int f = 0; f < NG; ++f) s_ft[f][ti][tj + 1] = F[f];
@@ -172,6 +189,7 @@ __global__ void __launch_bounds__(NT) k_march(StageArgs a, int species) {
         const double* bf = a.t.wr + ((size_t)k * (g.nr + 1) + ifc) * WB_N;
         face(DR(), eA, eB, eC, eD, rco_ptr(a, ig), rco_ptr(a, ig + 1), bf,
              bg_ptr(a, k, min(ig, g.nr)), bg_ptr(a, k, min(ig + 1, g.nr)), F);
+        if (GAS) tally(act);
         if (a.second && act && ig == g.nr - 1) {
           double fm = (double)F[NG - 1];
           if (PG) fm += bf[WB_RHO] * bf[WB_U];  // background normal mass flux rho0 u0
@@ -194,6 +212,9 @@ __global__ void __launch_bounds__(NT) k_march(StageArgs a, int species) {
       const double* bf = a.t.wr + ((size_t)k * (g.nr + 1) + i0) * WB_N;
       face(DR(), eA, eB, eC, eD, rco_ptr(a, i0 - 1), rco_ptr(a, i0), bf, bg_ptr(a, k, i0 - 1),
            bg_ptr(a, k, i0), F);
+      // the tile's lower r face is the upper face of the tile below, except at the inner
+      // boundary
+      if (GAS) tally(i0 == 0 && j0 + col < g.nth);
 #pragma unroll
       for (int f = 0; f < NG; ++f) s_fr[f][0][col] = F[f];
       if (a.second && i0 == 0 && j0 + col < g.nth) {
@@ -224,6 +245,7 @@ __global__ void __launch_bounds__(NT) k_march(StageArgs a, int species) {
       const double* bf = a.t.wz + ((size_t)(k + 1) * g.nr + igc) * WB_N;
       face(DZ(), rm, r0, rp, rn, nullptr, nullptr, bf, bg_ptr(a, k, igc), bg_ptr(a, k + 1, igc),
            fzhi);
+      if (GAS) tally(act);
       if (a.second && act && k == g.nz - 1) {
         double fm = (double)fzhi[NG - 1];
         if (PG) fm += bf[WB_RHO] * bf[WB_W];
@@ -433,6 +455,8 @@ __global__ void __launch_bounds__(NT) k_march(StageArgs a, int species) {
             for (int s2 = 0; s2 < ND; ++s2) tsmin = fmin(tsmin, 1.0 / inv_tstop<EXT>(g, s2, omk, qn[4], pn));
           }
         }
+      } else if (a.second && nvd[3] < 0.0) {
+        st.negd++;
       } else if (a.second && nvd[3] > 0.0) {
         double id = 1.0 / nvd[3];
         double a1 = nvd[0] * id, a2 = nvd[1] * id, a3 = nvd[2] * id;
@@ -455,8 +479,16 @@ __global__ void __launch_bounds__(NT) k_march(StageArgs a, int species) {
   // ---- block reductions: counters, CFL partial, boundary outflow partial
   const int wv = tid / 64, ln = tid & 63;
   int nf_ = wave_isum(st.fall), nv_ = wave_isum(st.vac), mi_ = wave_imax(st.maxit);
-  int nc_ = wave_imax(st.noconv), nr_ = wave_isum(st.resolve);
+  int nc_ = wave_imax(st.noconv), nr_ = wave_isum(st.resolve), nd_ = GAS ? 0 : wave_isum(st.negd);
+  if constexpr (GAS) {
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+      const int hb = wave_isum((int)((s_nh[b >> 1][tid] >> (16 * (b & 1))) & 0xffffu));
+      if (ln == 0 && hb) atomicAdd(&a.c.ctrl->newton_hist[b], (unsigned long long)hb);
+    }
+  }
   if (ln == 0) {
+    if (nd_) atomicAdd(&a.c.ctrl->nnegd, (unsigned long long)nd_);
     if (nf_) atomicAdd(&a.c.ctrl->nfall, (unsigned long long)nf_);
     if (nv_) { atomicAdd(&a.c.ctrl->nvac, (unsigned long long)nv_); atomicOr(&a.c.ctrl->status, FL_VAC); }
     if (mi_) atomicMax(&a.c.ctrl->maxit, mi_);
@@ -998,6 +1030,8 @@ __global__ void k_ctrl_init(Ctrl* c) {
     c->nfall = 0;
     c->nvac = 0;
     c->nresolve = 0;
+    for (int b = 0; b < 8; ++b) c->newton_hist[b] = 0;
+    c->nnegd = 0;
     c->min_ts = 1e300;
   }
 }

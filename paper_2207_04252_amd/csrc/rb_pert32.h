@@ -118,6 +118,7 @@ __device__ __forceinline__ void pfun_p(float q, const SideP& K, float& f, float&
 // FP64 solver must be used instead.
 __device__ __forceinline__ bool riemann_pert(const BgW& b, const PW& WL, const PW& WR, const GasC& g,
                                              PW& W, TStat& st) {
+  st.last = 0;
   // strong perturbations are left to the FP64 solver
   const float p0 = (float)b.p, r0 = (float)b.rho, c0 = (float)b.c;
   if (!(fabsf(WL.p) < 0.1f * p0 && fabsf(WR.p) < 0.1f * p0 && fabsf(WL.rho) < 0.1f * r0 &&
@@ -167,6 +168,7 @@ __device__ __forceinline__ bool riemann_pert(const BgW& b, const PW& WL, const P
     if (fabsf(dq) <= 1e-6f * fabsf(q) + 1e-9f * p0) { conv = true; break; }
   }
   st.maxit = max(st.maxit, it);
+  st.last = it;
   if (!conv) return false;
   const float us = 0.5f * (WL.un + WR.un) + 0.5f * ((fR + dR * dq) - (fL + dL * dq));
   const float usfull = (float)b.un + us;

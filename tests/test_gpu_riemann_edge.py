@@ -7,7 +7,9 @@ the left rarefaction fan (transonic); a pressure ratio of 1e5 (strong shock and 
 rarefaction); colliding and receding streams at u = -+5 (vacuum: reported as RB_EVACUUM
 while the run continues).  Every cell against the oracle after 10 steps.  Error paths:
 a NaN and a negative density set into the state, and a Newton iteration cap of one
-(RB_ENOCONV), each with the step and the first bad cell of the oracle."""
+(RB_ENOCONV), each with the step and the first bad cell of the oracle.  Diagnostics: the
+Newton-iteration histogram of the variants and the count of negative dust densities of a
+forced divergent dust stream, against the oracle's."""
 import sys
 
 import numpy as np
@@ -63,7 +65,25 @@ def test_sod_variant_parity(rb, name, cfg, dt):
     say(f"[riemann edge] {name}: worst {worst(errs)}, Newton max {d1.max_newton} / {d2.max_newton}")
     for k, v in errs.items():
         assert v <= 1e-10, (k, v)
+    check_histogram(d1, d2, exact=name == "transonic")
     sim.close()
+
+
+def check_histogram(d_gpu, d_or, exact):
+    """Both sides count every gas face once per evaluation.  The GPU takes supersonic
+    faces without a Newton solve (bin 0) where the oracle iterates, so faces may only move
+    from the oracle's Newton bins to the GPU's bin 0; where no face is supersonic the
+    histograms agree (up to faces whose last relative change lies within rounding of the
+    1e-12 stopping threshold)."""
+    hg, ho = np.array(d_gpu.newton_hist), np.array(d_or.newton_hist)
+    say(f"[newton histogram] gpu {hg.tolist()} oracle {ho.tolist()}")
+    assert hg.sum() == ho.sum() > 0
+    moved = hg[0] - ho[0]
+    assert moved >= 0
+    slack = max(2, int(1e-5 * ho.sum()))
+    assert np.abs(hg[1:] - ho[1:]).sum() <= moved + slack
+    if exact:
+        assert moved == 0 and np.abs(hg - ho).max() <= slack
 
 
 @pytest.mark.parametrize("what", ["nan", "negative_density"])
@@ -102,4 +122,33 @@ def test_newton_cap_reported(rb):
     sim.close()
     sim = rb.Sim(BASE)
     assert sim.step(3)[0] == rb.RB_OK
+    sim.close()
+
+
+def test_negative_dust_count(rb):
+    """A dust stream split at one radius (inwards below it, outwards above it, at 12 in
+    code units) empties cells next to the split faster than their content allows within
+    one CFL step, so their dust densities end the step negative: the count and every cell
+    match the oracle over two steps."""
+    cfg = synth.C3_BIFLUID.scaled(16, 32, 8).with_(noise_amp=0.0)
+    say("[diagnostics] negative dust")
+    o = oracle.Oracle(cfg)
+    s = o.state()
+    dt = o.cfl_dt()
+    k, i0, j, U = 1, 8, 5, 12.0
+    rd = s[8].copy()
+    s[5, k, i0:, j] = rd[k, i0:, j] * U
+    s[5, k, :i0, j] = -rd[k, :i0, j] * U
+    o.set_state(s)
+    sim = rb.Sim(cfg)
+    sim.set_fields(s)
+    for n in (1, 2):
+        assert o.step(1, dt=dt)[0] == 0
+        assert sim.step(1, dt=dt)[0] == rb.RB_OK
+        d1, d2 = sim.diagnostics(), o.diag()
+        say(f"[diagnostics] step {n}: negative dust {d1.negative_dust} / {d2.negative_dust}")
+        assert d1.negative_dust == d2.negative_dust >= n
+        errs = field_errors(sim.fields(), o.state(), cfg.gamma, cfg.n_dust)
+        for key, v in errs.items():
+            assert v <= 1e-10, (key, v)
     sim.close()
