@@ -40,7 +40,8 @@ def test_struct_sizes_match_header_layout():
     # 4 doubles, 2 int32, 4 doubles
     assert ctypes.sizeof(rossbi.rb_config) == (8 * 4 + (6 + 1 + 3 + 3 + 4 + 6 + 12) * 8 + 2 * 4
                                                + 9 * 8 + 2 * 4 + 4 * 8 + 2 * 4 + 4 * 8)
-    assert ctypes.sizeof(rossbi.rb_diag) == 8 + 8 + 4 + 4 + 8 + 8 + 8 + 4 + 4 + 5 * 8 + 5 * 8 + 8 + 8
+    assert ctypes.sizeof(rossbi.rb_diag) == (8 + 8 + 4 + 4 + 8 + 8 + 8 + 4 + 4 + 5 * 8 + 5 * 8 + 8 + 8
+                                             + 8 * 8 + 8)
 
 
 def test_struct_layout_matches_c_compiler(tmp_path):
