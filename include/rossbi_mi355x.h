@@ -119,6 +119,17 @@ typedef struct {
    * that does not converge within it stops the run with RB_ENOCONV.                     */
   int32_t newton_max_iter;
   double rwi_delta, rwi_dr, rwi_r0, rwi_eps;
+  /* Drag integration (Sect. 2.9 forces).  0: explicit, inside the RK2 stages; a step at or
+   * above the smallest stopping time stops the run with RB_ESTIFF.  1: split off and
+   * integrated exactly (Strang): each step is the drag alone over dt/2, the two RK2
+   * stages of the operator without drag, the drag alone over dt/2.  The drag alone
+   * keeps the densities and stopping times of each cell and the total momentum; the
+   * dust-gas velocity differences relax as exp(tau B), B = -diag(1/t_s) - 1 (eps/t)^T
+   * (eps_s = rho_s/rho_g; dust cells with rho_s <= 0 take no part); the gas energy changes
+   * by the gas kinetic-energy change.  Any step is allowed; rb_eval_operator then
+   * returns the operator without drag.  Not with rb_record.                            */
+  int32_t drag_exact;
+  int32_t pad_end;
 } rb_config;
 
 /* Caller-owned device buffers.  Sizes come from rb_query_sizes; pointers must be

@@ -54,7 +54,7 @@ class OrConfig(ctypes.Structure):
         ("vortex_sig_a", ctypes.c_double), ("noise_amp", ctypes.c_double),
         ("stokes", ctypes.c_double * 4), ("eps_dust", ctypes.c_double * 4),
         ("hd_over_h", ctypes.c_double * 4),
-        ("drag_law", ctypes.c_int32), ("pad1", ctypes.c_int32),
+        ("drag_law", ctypes.c_int32), ("drag_exact", ctypes.c_int32),
         ("grain_size", ctypes.c_double * 4), ("grain_density", ctypes.c_double * 4),
         ("mfp_coef", ctypes.c_double),
         ("bc_r", ctypes.c_int32), ("bc_z", ctypes.c_int32),
@@ -100,6 +100,7 @@ def to_struct(cfg: synth.Config) -> OrConfig:
         s.eps_dust[q] = cfg.eps_dust[q]
         s.hd_over_h[q] = cfg.hd_over_h[q]
     s.drag_law = int(getattr(cfg, "drag_law", 0))
+    s.drag_exact = int(getattr(cfg, "drag_exact", False))
     if s.drag_law:
         for q in range(cfg.n_dust):
             s.grain_size[q] = cfg.grain_size[q]
@@ -152,6 +153,8 @@ def lib() -> ctypes.CDLL:
         L.or_gas_face_flux.restype = ctypes.c_int
         L.or_gas_face_flux.argtypes = [ctypes.POINTER(OrConfig), ctypes.c_int, _D, _D, _D,
                                        ctypes.c_double, _D, _D]
+        L.or_drag_relax.restype = ctypes.c_int
+        L.or_drag_relax.argtypes = [ctypes.POINTER(OrConfig), ctypes.c_double, _D, ctypes.c_double]
         L.or_parabola_increment.restype = ctypes.c_double
         L.or_parabola_increment.argtypes = [ctypes.c_double] * 7
         L.or_equilibrium.argtypes = [ctypes.POINTER(OrConfig), ctypes.c_double, ctypes.c_double, _D]
@@ -319,6 +322,16 @@ def gas_face_flux(cfg: synth.Config, direction, q4, q0, x4, xf, qf):
     n = lib().or_gas_face_flux(ctypes.byref(s), int(direction), _ptr(q4), _ptr(q0), _ptr(x4),
                                float(xf), _ptr(qf), _ptr(out))
     return out, n
+
+
+def drag_relax(cfg: synth.Config, r: float, q, tau: float) -> np.ndarray:
+    """The exact drag relaxation of one cell at radius r over tau: q are its nf
+    conservative variables; returns the relaxed ones."""
+    s = to_struct(cfg)
+    out = _f64(q).copy()
+    if lib().or_drag_relax(ctypes.byref(s), float(r), _ptr(out), float(tau)) != 0:
+        raise ValueError("bad config")
+    return out
 
 
 def parabola_increment(em, e0, ep, xm, x0, xp, xf):

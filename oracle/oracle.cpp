@@ -78,7 +78,7 @@ typedef struct {
   double h0, beta_T, rho_mid0, beta_rho;
   double vortex_amp, vortex_r0, vortex_th0, vortex_sig_r, vortex_sig_a, noise_amp;
   double stokes[4], eps_dust[4], hd_over_h[4];
-  int32_t drag_law, pad1;
+  int32_t drag_law, drag_exact;
   double grain_size[4], grain_density[4], mfp_coef;
   int32_t bc_r, bc_z;
   double damp_r_in, damp_r_out, damp_z, damp_tau;
@@ -1025,8 +1025,11 @@ struct Sim {
                 ud = U[(o + 0) * N + id] / rd; vd = U[(o + 1) * N + id] / rd;
                 wd = U[(o + 2) * N + id] / rd;
               }
-              T ts = stopping_time(s, omk, rho, p);
-              T fx = rd * (ud - u) / ts, fy = rd * (vd - v) / ts, fz = rd * (wd - w) / ts;
+              T fx = 0.0, fy = 0.0, fz = 0.0;
+              if (!c.drag_exact) {
+                T ts = stopping_time(s, omk, rho, p);
+                fx = rd * (ud - u) / ts; fy = rd * (vd - v) / ts; fz = rd * (wd - w) / ts;
+              }
               dragx = dragx + fx; dragy = dragy + fy; dragz = dragz + fz;
               S[o + 0] = rd * vd * vd / r + rd * gr - fx;
               S[o + 1] = -rd * ud * vd / r - fy;
@@ -1133,6 +1136,119 @@ struct Sim {
     return bad;
   }
 
+  /* exp(tau A) of an n x n matrix (row-major), n <= 4: the Taylor series of exp(X),
+   * X = tau A / 2^s with s the smallest such that the largest absolute row sum of X is at
+   * most 1/2, summed to the 20th power (remainder below 1e-25), then squared s times. */
+  static void expm(const T* A, int n, double tau, T* M) {
+    double nrm = 0.0;
+    for (int a = 0; a < n; ++a) {
+      double row = 0.0;
+      for (int b = 0; b < n; ++b) row += std::fabs(val(A[a * n + b]));
+      nrm = std::max(nrm, row * tau);
+    }
+    int sq = 0;
+    while (nrm > 0.5) { nrm *= 0.5; ++sq; }
+    const double scale = std::ldexp(tau, -sq);
+    T X[16], term[16], sum[16], tmp[16];
+    for (int q = 0; q < n * n; ++q) {
+      X[q] = A[q] * scale;
+      term[q] = T((q / n) == (q % n) ? 1.0 : 0.0);
+      sum[q] = term[q];
+    }
+    for (int k = 1; k <= 20; ++k) {
+      for (int a = 0; a < n; ++a)
+        for (int b = 0; b < n; ++b) {
+          T acc = 0.0;
+          for (int m = 0; m < n; ++m) acc = acc + term[a * n + m] * X[m * n + b];
+          tmp[a * n + b] = acc / (double)k;
+        }
+      for (int q = 0; q < n * n; ++q) { term[q] = tmp[q]; sum[q] = sum[q] + term[q]; }
+    }
+    for (int r = 0; r < sq; ++r) {
+      for (int a = 0; a < n; ++a)
+        for (int b = 0; b < n; ++b) {
+          T acc = 0.0;
+          for (int m = 0; m < n; ++m) acc = acc + sum[a * n + m] * sum[m * n + b];
+          tmp[a * n + b] = acc;
+        }
+      for (int q = 0; q < n * n; ++q) sum[q] = tmp[q];
+    }
+    for (int q = 0; q < n * n; ++q) M[q] = sum[q];
+  }
+
+  /* The drag alone over a time tau, exactly (Sect. 2.9 forces; the integration over a
+   * step that may exceed the stopping times).  With the densities and stopping times of
+   * the cell held, each velocity component of the gas and of the dust species with
+   * rho_s > 0 obeys du_s/dt = -(u_s - u_g)/t_s, du_g/dt = sum_s eps_s (u_s - u_g)/t_s,
+   * eps_s = rho_s/rho_g.  The total momentum P = rho_g u_g + sum_s rho_s u_s is constant,
+   * and the relative velocities d_s = u_s - u_g obey the linear system
+   * dd_s/dt = -d_s/t_s - sum_k eps_k d_k/t_k, so d(tau) = exp(tau B) d(0); then
+   * u_g = (P - sum_s rho_s d_s) / (rho_g + sum_s rho_s) and u_s = u_g + d_s.  The gas energy
+   * changes by the change of the gas kinetic energy (the work u_g . f of the force on the
+   * gas, as in the explicit source), so the pressure is unchanged.  Species with
+   * rho_s <= 0 take no part.  q: the cell's conservative variables, updated in place. */
+  void relax_cell(T* q, double omk, double tau) const {
+    const double g = c.gamma;
+    T rho = q[4];
+    T p = (g - 1.0) * (q[3] - 0.5 * (q[0] * q[0] + q[1] * q[1] + q[2] * q[2]) / rho);
+    int sp[4];
+    T ia[4], eps[4];
+    int n = 0;
+    for (int s = 0; s < nd; ++s) {
+      T rd = q[5 + 4 * s + 3];
+      if (!(val(rd) > 0.0)) continue;
+      sp[n] = s;
+      ia[n] = 1.0 / stopping_time(s, omk, rho, p);
+      eps[n] = rd / rho;
+      ++n;
+    }
+    if (n == 0) return;
+    T B[16], M[16];
+    for (int a = 0; a < n; ++a)
+      for (int b = 0; b < n; ++b) B[a * n + b] = -(eps[b] * ia[b]) - (a == b ? ia[a] : T(0.0));
+    expm(B, n, tau, M);
+    T mtot = rho;
+    for (int a = 0; a < n; ++a) mtot = mtot + q[5 + 4 * sp[a] + 3];
+    T dE = 0.0;
+    for (int d = 0; d < 3; ++d) {
+      T ug = q[d] / rho;
+      T P = q[d];
+      T d0[4], d1[4];
+      for (int a = 0; a < n; ++a) {
+        int o = 5 + 4 * sp[a];
+        P = P + q[o + d];
+        d0[a] = q[o + d] / q[o + 3] - ug;
+      }
+      T pd = 0.0;
+      for (int a = 0; a < n; ++a) {
+        d1[a] = 0.0;
+        for (int b = 0; b < n; ++b) d1[a] = d1[a] + M[a * n + b] * d0[b];
+        pd = pd + q[5 + 4 * sp[a] + 3] * d1[a];
+      }
+      T ug1 = (P - pd) / mtot;
+      q[d] = rho * ug1;
+      for (int a = 0; a < n; ++a) {
+        int o = 5 + 4 * sp[a];
+        q[o + d] = q[o + 3] * (ug1 + d1[a]);
+      }
+      dE = dE + 0.5 * rho * (ug1 * ug1 - ug * ug);
+    }
+    q[3] = q[3] + dE;
+  }
+
+  /* relax_cell over every cell of U */
+  void drag_relax(std::vector<T>& U, double tau) const {
+#pragma omp parallel for schedule(static)
+    for (long id = 0; id < (long)N; ++id) {
+      int i = (int)((id / nth) % nr);
+      double r = rce(i);
+      T q[24];
+      for (int f = 0; f < nf; ++f) q[f] = U[(size_t)f * N + id];
+      relax_cell(q, std::sqrt(c.GM / (r * r * r)), tau);
+      for (int f = 0; f < nf; ++f) U[(size_t)f * N + id] = q[f];
+    }
+  }
+
   /* stopping time of species s in a cell (Sect. 2.9).  Law 0: t_s = St / Omega_K.
    * Law 1: Epstein t = rho_s r_p / (rho_g c_s) while r_p <= 9 lambda / 4, else Stokes
    * t = (4/9) (r_p / lambda) t^E, with lambda = mfp_coef / rho_g (the mean free path
@@ -1224,6 +1340,8 @@ struct Sim {
   int one_step(double dt) {
     bool with_dust = nd > 0;
     bool bal = c.balanced != 0;
+    const bool split = c.drag_exact && nd > 0;
+    if (split) drag_relax(E, 0.5 * dt);
     evaluate(E, with_dust, bal, Gb);
     for (int f = 0; f < nf; ++f)
       for (int k = 0; k < nz; ++k)
@@ -1254,6 +1372,7 @@ struct Sim {
     if (flags & F_NOCONV) return OR_ENOCONV;
     bad = first_negative(E);
     if (bad >= 0) { flags |= F_NEG; record_bad(bad); return OR_ENEGATIVE; }
+    if (split) drag_relax(E, 0.5 * dt);
     t += dt;
     ++step;
     return OR_OK;
@@ -1270,7 +1389,7 @@ struct Sim {
       else if (dt_kind == 1) dt = dt_fixed;
       else dt = dt_list[q];
       if (!(dt > 0.0)) return OR_EINVAL;
-      if (nd > 0 && dt >= min_stopping_time(E)) { flags |= F_STIFF; return OR_ESTIFF; }
+      if (nd > 0 && !c.drag_exact && dt >= min_stopping_time(E)) { flags |= F_STIFF; return OR_ESTIFF; }
       if (dt_out) dt_out[q] = dt;
       dt_last = dt;
       int st = one_step(dt);
@@ -1498,6 +1617,15 @@ int or_gas_face_flux(const OrConfig* cfg, int dir, const double* q4, const doubl
               nvac, maxit, noconv, nh);
   for (int f = 0; f < 5; ++f) flux[f] = F[f];
   return (int)nfall;
+}
+
+/* The exact drag relaxation of one cell over tau (Sect. 2.9): q holds the nf conservative
+ * variables of a cell at radius r, updated in place.  Returns -1 on a bad config. */
+int or_drag_relax(const OrConfig* cfg, double r, double* q, double tau) {
+  Sim<double> s;
+  if (!s.setup(*cfg)) return -1;
+  s.relax_cell(q, std::sqrt(cfg->GM / (r * r * r)), tau);
+  return 0;
 }
 
 /* Limited parabola increment for unit tests. */

@@ -84,6 +84,7 @@ bool validate(const rb_config* c, std::string* why) {
   if (!(c->gamma > 1.0)) return bad("gamma must exceed 1");
   if (!(c->cfl > 0.0 && c->cfl <= 1.0)) return bad("cfl must be in (0, 1]");
   if (c->newton_max_iter < 0) return bad("newton_max_iter must be >= 0 (0: the default 50)");
+  if (c->drag_exact != 0 && c->drag_exact != 1) return bad("drag_exact must be 0 or 1");
   if (!(c->r_in > 0.0 && c->r_out > c->r_in)) return bad("need 0 < r_in < r_out");
   if (c->nz > 1 && !(c->z_half > 0.0)) return bad("z_half must be positive in 3D");
   if (c->init_kind != RB_INIT_SOD && c->init_kind != RB_INIT_DISC) return bad("unknown init_kind");
@@ -202,6 +203,7 @@ Geo make_geo(const rb_config& c) {
   g.indirect = c.indirect != 0;
   g.drag_law = c.drag_law;
   g.newton_max = c.newton_max_iter > 0 ? c.newton_max_iter : 50;
+  g.drag_exact = (c.drag_exact && c.n_dust > 0) ? 1 : 0;
   g.bc_z = c.nz > 1 ? c.bc_z : 0;
   g.damp = c.bc_r == 1 || (c.bc_z == 2 && c.nz > 1);
   g.mfp = c.drag_law ? c.mfp_coef : 0.0;
@@ -480,13 +482,26 @@ rb_status rb_step(rb_ctx* x, int n, const rb_dt_policy* policy, double* dt_out) 
       a.dt_idx = q;
       a.mode = MODE_UPDATE;
       a.gas_only = 0;
+      const bool split = x->g.drag_exact != 0;
+      // split drag: the drag alone over dt/2 before the stages
+      if (split) HIPCHK(x, launch_drag(a, x->state, 0.5, x->L.ncfl, x->stream), "drag");
       // first stage: E* = E^n + (dt/2V) (G(E^n) - R0)
       a.in = x->state; a.base = x->state; a.out = x->stage; a.coef = 0.5; a.second = 0;
       HIPCHK(x, run_stage(x, a), "stage 1");
       // second stage: E^{n+1} = E^n + (dt/V) (G(E*) - R0), in place
       a.in = x->stage; a.base = x->state; a.out = x->state; a.coef = 1.0; a.second = 1;
       HIPCHK(x, run_stage(x, a), "stage 2");
-      {
+      if (split) {
+        // boundary ledger of the stages, then the drag alone over dt/2 and the CFL step of
+        // the relaxed state (which replaces the one the second stage formed)
+        ProfScope ps(x, 2);
+        HIPCHK(x, launch_reduce(a, x->L.nblocks, q + 1, 0, 1, x->stream), "ledger");
+        HIPCHK(x, launch_drag(a, x->state, 0.5, x->L.ncfl, x->stream), "drag");
+        a.step = (int)(x->step + q + 1);
+        HIPCHK(x, launch_cfl(a, x->state, x->L.ncfl, 0, x->stream), "cfl");
+        HIPCHK(x, launch_reduce(a, x->L.ncfl, q + 1, cfl ? 1 : 0, 0, x->stream), "reduce");
+        a.step = (int)(x->step + q);
+      } else {
         ProfScope ps(x, 2);
         HIPCHK(x, launch_reduce(a, x->L.nblocks, q + 1, cfl ? 1 : 0, 1, x->stream), "reduce");
       }
@@ -755,6 +770,7 @@ rb_status rb_record(rb_ctx* x, int n, int ckpt_every, const rb_dt_policy* policy
   if (x->g.p32) return fail(x, RB_EINVAL, "the adjoint is FP64 only");
   if (x->g.indirect) return fail(x, RB_EINVAL, "the adjoint does not cover indirect gravity");
   if (x->g.drag_law) return fail(x, RB_EINVAL, "the adjoint covers the constant-Stokes drag only");
+  if (x->g.drag_exact) return fail(x, RB_EINVAL, "the adjoint covers the explicit drag only");
   if (x->g.bc_z || x->g.damp) return fail(x, RB_EINVAL, "the adjoint covers the stationary ghosts only");
   const int k = std::min(ckpt_every, n);
   const AdjLayout A = adj_layout(x, n, k);

@@ -68,6 +68,7 @@ struct Geo {
   int bc_z;      // 0 stationary z ghosts, 1 outflow (ghosts repeat the boundary cell), 2 damped
   int damp;      // boundary damping zones present (rate table)
   int newton_max;  // Newton iteration cap of the exact gas solver
+  int drag_exact;  // drag split off the stages and integrated exactly (dust present)
   size_t N;
   double gamma, GM, cfl;
   double inv_st[4];
@@ -157,6 +158,7 @@ hipError_t launch_stage(const StageArgs& a, int blocks, hipStream_t s);
 // one group of a stage: 0 the gas, 1 + s dust species s
 hipError_t launch_stage_group(const StageArgs& a, int blocks, int group, hipStream_t s);
 hipError_t launch_cfl(const StageArgs& a, const void* state, int blocks, int dt_idx, hipStream_t s);
+hipError_t launch_drag(const StageArgs& a, void* state, double frac, int blocks, hipStream_t s);
 hipError_t launch_reduce(const StageArgs& a, int nparts, int dt_idx_next, int want_dt,
                          int want_ledger, hipStream_t s);
 hipError_t launch_fill(double* p, size_t n, double v, hipStream_t s);

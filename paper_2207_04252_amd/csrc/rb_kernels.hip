@@ -59,7 +59,7 @@ __global__ void __launch_bounds__(NT) k_march(StageArgs a, int species) {
   const int ig = i0 + ti;
   const bool act = jg < g.nth && ig < g.nr;
   const int igc = min(ig, g.nr - 1);
-  const bool drag = !a.gas_only && ND > 0;
+  const bool drag = !a.gas_only && ND > 0 && !g.drag_exact;
   const void* in = a.in;
   const double dt = a.dt_idx >= 0 ? a.c.dtlog[a.dt_idx] : 0.0;
 
@@ -574,6 +574,151 @@ __global__ void __launch_bounds__(256) k_cfl(StageArgs a, const void* state) {
   }
 }
 
+// ------------------------------------------------------------------------------------
+// the drag alone over a part of the step, exactly (split integration of the Sect. 2.9
+// forces for steps that may exceed the stopping times)
+//
+// With the densities and the stopping times of a cell held, the total momentum of each
+// velocity component is constant and the dust-gas velocity differences d_s = u_s - u_g
+// (species with rho_s > 0) obey dd/dt = B d, B_ab = -eps_b / t_b - [a == b] / t_a,
+// eps_b = rho_b / rho_g, so d(tau) = exp(tau B) d(0).  exp(tau B) is taken by scaling
+// and squaring: X = tau B / 2^s with |X| (largest absolute row sum) <= 1/8, the Taylor
+// polynomial of degree 12 in Horner form (remainder below 1e-21), then s squarings; B's
+// eigenvalues are negative, so the squarings do not amplify rounding.  New velocities:
+// u_g = (P - sum rho_s d_s) / (rho_g + sum rho_s), u_s = u_g + d_s; the gas energy changes
+// by the gas kinetic-energy change (the pressure is unchanged).
+
+template <int ND>
+__device__ __forceinline__ void mat_mul(const double* A, const double* B, double* C) {
+#pragma unroll
+  for (int r = 0; r < ND; ++r)
+#pragma unroll
+    for (int c = 0; c < ND; ++c) {
+      double acc = 0.0;
+#pragma unroll
+      for (int m = 0; m < ND; ++m) acc = fma(A[r * ND + m], B[m * ND + c], acc);
+      C[r * ND + c] = acc;
+    }
+}
+
+template <int ND, bool P32>
+__global__ void __launch_bounds__(256) k_drag(StageArgs a, void* state, double frac) {
+  __shared__ int s_stop;
+  if (threadIdx.x == 0) s_stop = __atomic_load_n(&a.c.ctrl->status, __ATOMIC_RELAXED);
+  __syncthreads();
+  if (s_stop & FL_HARD) return;
+  const Geo& g = a.g;
+  const double tau = frac * a.c.dtlog[a.dt_idx];
+  const double gm1 = g.gamma - 1.0;
+  for (size_t c = (size_t)blockIdx.x * blockDim.x + threadIdx.x; c < g.N;
+       c += (size_t)gridDim.x * blockDim.x) {
+    const size_t ki = c / g.nth;
+    const int i = (int)(ki % g.nr);
+    const int k = (int)(ki / g.nr);
+    const double* bgc = a.t.bgc + ki * 5;
+    double q[5];
+#pragma unroll
+    for (int f = 0; f < 5; ++f) q[f] = bgc[f] + ld_cell<P32>(a, state, f, k, i, c);
+    const double rho = q[4], ir = 1.0 / rho;
+    double ug[3] = {q[0] * ir, q[1] * ir, q[2] * ir};
+    const double p = gm1 * (q[3] - 0.5 * (q[0] * ug[0] + q[1] * ug[1] + q[2] * ug[2]));
+    const double omk = a.t.rt[(size_t)i * RT_N + RT_OMK];
+    const double v0 = a.t.wc[ki * WB_N + WB_V];
+    double rd[ND], ia[ND], ud[ND][3];
+    double mtot = rho;
+    bool any = false;
+#pragma unroll
+    for (int s = 0; s < ND; ++s) {
+      const int o = 5 + 4 * s;
+      rd[s] = ld_cell<P32>(a, state, o + 3, k, i, c);
+      const bool on = rd[s] > 0.0;
+      any = any || on;
+      if constexpr (P32) {
+        const float* vel = (const float*)state + (size_t)(5 + 3 * s) * g.N + c;
+        ud[s][0] = (double)vel[0];
+        ud[s][1] = v0 + (double)vel[g.N];
+        ud[s][2] = (double)vel[2 * g.N];
+      } else {
+        const double id = on ? 1.0 / rd[s] : 0.0;
+#pragma unroll
+        for (int d = 0; d < 3; ++d) ud[s][d] = ((const double*)state)[(size_t)(o + d) * g.N + c] * id;
+      }
+      ia[s] = on ? inv_tstop<true>(g, s, omk, rho, p) : 0.0;
+      if (on) mtot += rd[s];
+      else rd[s] = 0.0;
+    }
+    if (!any) continue;
+    // exp(tau B)
+    double X[ND * ND], M[ND * ND], T[ND * ND];
+    double nrm = 0.0;
+#pragma unroll
+    for (int r = 0; r < ND; ++r) {
+      double row = 0.0;
+#pragma unroll
+      for (int b = 0; b < ND; ++b) {
+        X[r * ND + b] = -(rd[b] * ir) * ia[b] - (r == b ? ia[r] : 0.0);
+        row += fabs(X[r * ND + b]);
+      }
+      nrm = fmax(nrm, row * tau);
+    }
+    int sq = 0;
+    while (nrm > 0.125) { nrm *= 0.5; ++sq; }
+    const double sc = ldexp(tau, -sq);
+#pragma unroll
+    for (int e = 0; e < ND * ND; ++e) X[e] *= sc;
+    // Horner: M = I + X/12, then M = I + (X/k) M for k = 11 .. 1
+#pragma unroll
+    for (int e = 0; e < ND * ND; ++e) M[e] = X[e] * (1.0 / 12.0) + ((e / ND) == (e % ND) ? 1.0 : 0.0);
+#pragma unroll
+    for (int kk = 11; kk >= 1; --kk) {
+      mat_mul<ND>(X, M, T);
+      const double ik = 1.0 / (double)kk;
+#pragma unroll
+      for (int e = 0; e < ND * ND; ++e) M[e] = fma(T[e], ik, (e / ND) == (e % ND) ? 1.0 : 0.0);
+    }
+    for (int r = 0; r < sq; ++r) {
+      mat_mul<ND>(M, M, T);
+#pragma unroll
+      for (int e = 0; e < ND * ND; ++e) M[e] = T[e];
+    }
+    // relax each component
+    double dke = 0.0;
+    const double imt = 1.0 / mtot;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      double P = q[d], d0[ND];
+#pragma unroll
+      for (int s = 0; s < ND; ++s) {
+        P += rd[s] * ud[s][d];
+        d0[s] = rd[s] > 0.0 ? ud[s][d] - ug[d] : 0.0;
+      }
+      double pd = 0.0, d1[ND];
+#pragma unroll
+      for (int s = 0; s < ND; ++s) {
+        double acc = 0.0;
+#pragma unroll
+        for (int b = 0; b < ND; ++b) acc = fma(M[s * ND + b], d0[b], acc);
+        d1[s] = acc;
+        pd += rd[s] * acc;
+      }
+      const double ug1 = (P - pd) * imt;
+      dke += 0.5 * rho * (ug1 * ug1 - ug[d] * ug[d]);
+      st_cell<P32>(a, state, d, k, i, c, rho * ug1 - bgc[d]);
+#pragma unroll
+      for (int s = 0; s < ND; ++s) {
+        if (!(rd[s] > 0.0)) continue;
+        if constexpr (P32) {
+          const double u1 = ug1 + d1[s] - (d == 1 ? v0 : 0.0);
+          ((float*)state)[(size_t)(5 + 3 * s + d) * g.N + c] = (float)u1;
+        } else {
+          ((double*)state)[(size_t)(5 + 4 * s + d) * g.N + c] = rd[s] * (ug1 + d1[s]);
+        }
+      }
+    }
+    st_cell<P32>(a, state, 3, k, i, c, q[3] + dke - bgc[3]);
+  }
+}
+
 // final reduction after a step: next dt (CFL), stiffness check, boundary outflow ledger
 __global__ void __launch_bounds__(256) k_reduce(StageArgs a, int nparts, int dt_next, int want_dt,
                                                 int want_ledger) {
@@ -623,7 +768,7 @@ __global__ void __launch_bounds__(256) k_reduce(StageArgs a, int nparts, int dt_
     // law 1: over the cells of the state the step starts from)
     const double tsmin = dyn_ts ? fmin(fmin(s_ts[0], s_ts[1]), fmin(s_ts[2], s_ts[3]))
                                 : a.c.ctrl->min_ts;
-    if (a.g.nd > 0 && dtn >= tsmin) {
+    if (a.g.nd > 0 && !a.g.drag_exact && dtn >= tsmin) {
       atomicOr(&a.c.ctrl->status, FL_STIFF);
       // dt_next 0: the first step of the call (a.step); else the step after a.step
       atomicCAS(&a.c.ctrl->bad_step, -1, dt_next == 0 ? a.step : a.step + 1);
@@ -1230,6 +1375,23 @@ hipError_t launch_cfl(const StageArgs& a, const void* state, int blocks, int dt_
     case 2: cfl_nd<2>(a, state, blocks, s); break;
     case 3: cfl_nd<3>(a, state, blocks, s); break;
     case 4: cfl_nd<4>(a, state, blocks, s); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+template <int ND>
+static void drag_nd(const StageArgs& a, void* state, double frac, int blocks, hipStream_t s) {
+  if (a.g.p32) hipLaunchKernelGGL((k_drag<ND, true>), dim3(blocks), dim3(256), 0, s, a, state, frac);
+  else hipLaunchKernelGGL((k_drag<ND, false>), dim3(blocks), dim3(256), 0, s, a, state, frac);
+}
+
+hipError_t launch_drag(const StageArgs& a, void* state, double frac, int blocks, hipStream_t s) {
+  switch (a.g.nd) {
+    case 1: drag_nd<1>(a, state, frac, blocks, s); break;
+    case 2: drag_nd<2>(a, state, frac, blocks, s); break;
+    case 3: drag_nd<3>(a, state, frac, blocks, s); break;
+    case 4: drag_nd<4>(a, state, frac, blocks, s); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

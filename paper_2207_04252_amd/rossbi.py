@@ -53,6 +53,7 @@ class rb_config(ctypes.Structure):
         ("rwi_m", ctypes.c_int32), ("newton_max_iter", ctypes.c_int32),
         ("rwi_delta", ctypes.c_double), ("rwi_dr", ctypes.c_double),
         ("rwi_r0", ctypes.c_double), ("rwi_eps", ctypes.c_double),
+        ("drag_exact", ctypes.c_int32), ("pad_end", ctypes.c_int32),
     ]
 
 
@@ -165,6 +166,7 @@ def to_config(cfg: synth.Config, precision: int = RB_FP64) -> rb_config:
                                                        cfg.damp_z, cfg.damp_tau)
     c.rwi_m = int(cfg.rwi_m)
     c.newton_max_iter = int(cfg.newton_max_iter)
+    c.drag_exact = int(cfg.drag_exact)
     c.rwi_delta, c.rwi_dr, c.rwi_r0, c.rwi_eps = (cfg.rwi_delta, cfg.rwi_dr, cfg.rwi_r0,
                                                   cfg.rwi_eps)
     return c

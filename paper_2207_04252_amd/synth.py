@@ -69,6 +69,10 @@ class Config:
     # Stokes regimes from the grain radius and material density, with the gas mean free
     # path lambda = mfp_coef / rho_g (code units)
     drag_law: int = 0
+    # drag integration: False, explicit in the RK2 stages (the step must stay below the
+    # smallest stopping time); True, the drag is split off and integrated exactly over
+    # half steps before and after the stages (Strang), so any step is allowed
+    drag_exact: bool = False
     grain_size: Tuple[float, ...] = ()
     grain_density: Tuple[float, ...] = ()
     mfp_coef: float = 0.0

@@ -37,9 +37,9 @@ def test_library_exports_every_declared_symbol(lib):
 
 def test_struct_sizes_match_header_layout():
     # rb_config: 8 int32 + 6 + 1 + 3 + 3 + 4 + 6 + 12 doubles, 2 int32, 9 doubles, 2 int32,
-    # 4 doubles, 2 int32, 4 doubles
+    # 4 doubles, 2 int32, 4 doubles, 2 int32
     assert ctypes.sizeof(rossbi.rb_config) == (8 * 4 + (6 + 1 + 3 + 3 + 4 + 6 + 12) * 8 + 2 * 4
-                                               + 9 * 8 + 2 * 4 + 4 * 8 + 2 * 4 + 4 * 8)
+                                               + 9 * 8 + 2 * 4 + 4 * 8 + 2 * 4 + 4 * 8 + 2 * 4)
     assert ctypes.sizeof(rossbi.rb_diag) == (8 + 8 + 4 + 4 + 8 + 8 + 8 + 4 + 4 + 5 * 8 + 5 * 8 + 8 + 8
                                              + 8 * 8 + 8)
 

@@ -1,0 +1,98 @@
+"""The split, exact drag integration (Sect. 2.9 forces over steps longer than the
+stopping times) on the GPU against the oracle: one species at St = 0.0015 (CFL steps of ten
+to twenty stopping times at the inner edge) and three species at St = 0.001, 0.01 and 0.3,
+free CFL runs in FP64 compared cell by cell (gas everywhere, dust off the two midplane
+layers and through the midplane pair sums, as the free-run parity does); the
+FP32-perturbation step map from the same states; no RB_ESTIFF where the explicit stages
+would refuse the step."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2207_04252_amd import synth
+from tests.parity import field_errors
+from tests.test_gpu_fp32p import errors32
+
+pytestmark = pytest.mark.gpu
+
+CASES = [
+    ("one_species", synth.C3_BIFLUID.scaled(24, 64, 16).with_(stokes=(0.0015,), drag_exact=True), 20),
+    ("three_species", synth.C4_LARGE.scaled(24, 32, 16).with_(stokes=(0.001, 0.01, 0.3),
+                                                             drag_exact=True), 10),
+]
+TOL = 1e-10
+
+
+@pytest.fixture(scope="module")
+def rb():
+    import torch
+    assert torch.cuda.is_available(), "GPU test on a machine without a GPU"
+    from paper_2207_04252_amd import rossbi
+    rossbi.load()
+    return rossbi
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.mark.parametrize("name,cfg,n", CASES, ids=[c[0] for c in CASES])
+def test_exact_drag_free_run(rb, name, cfg, n):
+    say(f"[exact drag] {name} {cfg.nr}x{cfg.nth}x{cfg.nz}, {n} steps")
+    xi = synth.noise(cfg)
+    o = oracle.Oracle(cfg, noise=xi)
+    ratio = o.cfl_dt() / o.min_stopping_time()
+    sim = rb.Sim(cfg, noise=xi)
+    st, dts = sim.step(n)
+    st2, dts2 = o.step(n)
+    assert st == rb.RB_OK and st2 == 0, (st, st2, sim.error())
+    assert ratio > 5.0
+    assert np.allclose(dts, dts2, rtol=1e-12, atol=0), np.max(np.abs(dts / dts2 - 1))
+    mid = {}
+    errs = field_errors(sim.fields(), o.state(), cfg.gamma, cfg.n_dust, mid=mid)
+    say(f"[exact drag] {name}: dt / t_s,min = {ratio:.1f}; "
+        + " ".join(f"{k}={v:.1e}" for k, v in errs.items()))
+    for k, v in errs.items():
+        assert v <= TOL, (k, v)
+    assert np.allclose(sim.mass(), o.mass(), rtol=1e-13, atol=0)
+    sim.close()
+    # the explicit stages refuse the same step
+    e = rb.Sim(cfg.with_(drag_exact=False), noise=xi)
+    assert e.step(1)[0] == rb.RB_ESTIFF
+    e.close()
+
+
+@pytest.mark.parametrize("name,cfg,n", CASES, ids=[c[0] for c in CASES])
+def test_exact_drag_fp32p_step_map(rb, name, cfg, n):
+    """From states of the oracle's run, one step of the FP32-perturbation form against the
+    oracle's step: gas density and pressure to 1e-5 relative, dust densities to 1e-5 off
+    the midplane layers."""
+    say(f"[exact drag fp32p] {name}")
+    xi = synth.noise(cfg)
+    o = oracle.Oracle(cfg, noise=xi)
+    sim = rb.Sim(cfg, precision=rb.RB_FP32_PERT, noise=xi)
+    kh = cfg.nz // 2
+    for q in range(3):
+        E = o.state()
+        sim.set_fields(E)
+        dt = o.cfl_dt()
+        st, _ = sim.step(1, dt=dt)
+        assert st == rb.RB_OK, sim.error()
+        assert o.step(1, dt=dt)[0] == 0
+        ref = o.state()
+        errs = errors32(sim.fields(), ref, cfg)
+        worst = {k: float(np.max(v)) for k, v in errs.items() if not k.startswith("dust")}
+        for s in range(cfg.n_dust):
+            f = 5 + 4 * s + 3
+            rel = np.abs(sim.fields()[f] - ref[f]) / np.maximum(ref[f], 1e-300)
+            keep = ref[f] >= 1e-6 * ref[f].max()
+            keep[kh - 1:kh + 1] = False
+            worst[f"dust{s}"] = float(np.max(rel[keep]))
+        say(f"[exact drag fp32p] {name} step {q}: "
+            + " ".join(f"{k}={v:.1e}" for k, v in worst.items()))
+        for k in ["rho", "p_rel"] + [f"dust{s}" for s in range(cfg.n_dust)]:
+            assert worst[k] <= 1e-5, (q, k, worst[k])
+    sim.close()
