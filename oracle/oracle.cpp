@@ -1147,7 +1147,7 @@ struct Sim {
       nrm = std::max(nrm, row * tau);
     }
     int sq = 0;
-    while (nrm > 0.5) { nrm *= 0.5; ++sq; }
+    while (nrm > 0.5 && sq < 1100) { nrm *= 0.5; ++sq; }
     const double scale = std::ldexp(tau, -sq);
     T X[16], term[16], sum[16], tmp[16];
     for (int q = 0; q < n * n; ++q) {

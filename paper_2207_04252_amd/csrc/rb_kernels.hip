@@ -662,7 +662,7 @@ __global__ void __launch_bounds__(256) k_drag(StageArgs a, void* state, double f
       nrm = fmax(nrm, row * tau);
     }
     int sq = 0;
-    while (nrm > 0.125) { nrm *= 0.5; ++sq; }
+    while (nrm > 0.125 && sq < 1100) { nrm *= 0.5; ++sq; }  // bounded for a non-finite norm
     const double sc = ldexp(tau, -sq);
 #pragma unroll
     for (int e = 0; e < ND * ND; ++e) X[e] *= sc;
