@@ -1,10 +1,15 @@
 """The split, exact drag integration (Sect. 2.9 forces over steps longer than the
-stopping times) on the GPU against the oracle: one species at St = 0.0015 (CFL steps of ten
-to twenty stopping times at the inner edge) and three species at St = 0.001, 0.01 and 0.3,
-free CFL runs in FP64 compared cell by cell (gas everywhere, dust off the two midplane
-layers and through the midplane pair sums, as the free-run parity does); the
+stopping times) on the GPU against the oracle: one species at St = 0.0015 and three species
+at St = 0.0015, 0.02 and 0.3 (CFL steps of about twelve of the smallest stopping times),
+free CFL runs in FP64 compared cell by cell to 1e-10 (gas everywhere, dust off the two
+midplane layers and through the midplane pair sums, as the free-run parity does); the
 FP32-perturbation step map from the same states; no RB_ESTIFF where the explicit stages
-would refuse the step."""
+would refuse the step.
+
+One exception, measured: with a single strongly coupled species the dust pair sums at the
+midplane (the standing delta shock) amplify rounding by about 1e6 within ten steps; the
+oracle itself moves them by 6e-10 when its input changes by 1e-15 relative.  There the
+pair sums are gated at ten times that self-divergence, taken in the test."""
 import sys
 
 import numpy as np
@@ -19,7 +24,7 @@ pytestmark = pytest.mark.gpu
 
 CASES = [
     ("one_species", synth.C3_BIFLUID.scaled(24, 64, 16).with_(stokes=(0.0015,), drag_exact=True), 20),
-    ("three_species", synth.C4_LARGE.scaled(24, 32, 16).with_(stokes=(0.001, 0.01, 0.3),
+    ("three_species", synth.C4_LARGE.scaled(24, 32, 16).with_(stokes=(0.0015, 0.02, 0.3),
                                                              drag_exact=True), 10),
 ]
 TOL = 1e-10
@@ -51,12 +56,22 @@ def test_exact_drag_free_run(rb, name, cfg, n):
     assert st == rb.RB_OK and st2 == 0, (st, st2, sim.error())
     assert ratio > 5.0
     assert np.allclose(dts, dts2, rtol=1e-12, atol=0), np.max(np.abs(dts / dts2 - 1))
-    mid = {}
-    errs = field_errors(sim.fields(), o.state(), cfg.gamma, cfg.n_dust, mid=mid)
+    ref = o.state()
+    errs = field_errors(sim.fields(), ref, cfg.gamma, cfg.n_dust, mid={})
     say(f"[exact drag] {name}: dt / t_s,min = {ratio:.1f}; "
         + " ".join(f"{k}={v:.1e}" for k, v in errs.items()))
+    pair_tol = TOL
+    if cfg.n_dust == 1:
+        o2 = oracle.Oracle(cfg, noise=xi)
+        s = o2.state()
+        o2.set_state(s * (1.0 + 1e-15 * np.sin(np.arange(s.size)).reshape(s.shape)))
+        assert o2.step(n, dt_list=dts2)[0] == 0
+        self_div = field_errors(o2.state(), ref, cfg.gamma, cfg.n_dust)
+        floor = max(v for k, v in self_div.items() if k.endswith("_midpair"))
+        pair_tol = max(TOL, 10.0 * floor)
+        say(f"[exact drag] {name}: oracle midplane pair self-divergence {floor:.1e}")
     for k, v in errs.items():
-        assert v <= TOL, (k, v)
+        assert v <= (pair_tol if k.endswith("_midpair") else TOL), (k, v)
     assert np.allclose(sim.mass(), o.mass(), rtol=1e-13, atol=0)
     sim.close()
     # the explicit stages refuse the same step
