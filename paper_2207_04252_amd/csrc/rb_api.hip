@@ -127,6 +127,7 @@ Layout make_layout(const rb_config& c) {
   const size_t N = nr * nth * nz;
   L.ntj = (int)((nth + TJ - 1) / TJ);
   L.nti = (int)((nr + TI - 1) / TI);
+  L.ntm = (int)((nr + TM - 1) / TM);
   if (nz == 1) {
     L.tk = 1;
   } else {
@@ -135,24 +136,27 @@ Layout make_layout(const rb_config& c) {
     if (env && std::atoi(env) > 0) {
       tk = std::min(std::atoi(env), 4096);  // the Newton histogram's 16-bit bins
     } else {
-      // One 512-thread workgroup fills a CU (256 VGPRs: two waves per SIMD), so a launch
-      // runs in ceil(blocks / 256) rounds on the 256 CUs of an MI355X; a block marches tk
-      // planes plus about 1.5 planes of set-up (initial ring, first z face).  Take the
+      // A stage-kernel workgroup of 64 x TM threads holds at most 256 VGPRs per lane (two
+      // waves per SIMD), so 8 / TM workgroups fill a CU and a launch runs in
+      // ceil(blocks / (256 * 8 / TM)) rounds on the 256 CUs of an MI355X; a block marches
+      // tk planes plus about 1.5 planes of set-up (initial ring, first z face).  Take the
       // chunk length with the fewest plane-times.
-      const size_t tiles = (size_t)L.ntj * L.nti;
+      const size_t tiles = (size_t)L.ntj * L.ntm;
+      const size_t conc = 256 * (8 / TM);
       const int cand[7] = {128, 64, 32, 16, 8, 4, 2};
       double best = 1e300;
       for (int q = 0; q < 7; ++q) {
         const size_t c = std::min<size_t>(cand[q], nz);
         const size_t blocks = tiles * ((nz + c - 1) / c);
-        const double t = (double)((blocks + 255) / 256) * ((double)c + 1.5);
+        const double t = (double)((blocks + conc - 1) / conc) * ((double)c + 1.5);
         if (t < best) { best = t; tk = (int)c; }
       }
     }
     L.tk = (int)std::min<size_t>(tk, nz);
   }
   L.nkc = (int)((nz + L.tk - 1) / L.tk);
-  L.nblocks = L.ntj * L.nti * L.nkc;
+  L.nblocks = L.ntj * L.ntm * L.nkc;
+  L.nblocks_adj = L.ntj * L.nti * L.nkc;
   L.ncfl = (int)std::min<size_t>((N + 255) / 256, 2048);
   size_t o = 0;
   auto take = [&](size_t n) { size_t at = o; o += up32(n); return at; };
@@ -232,7 +236,7 @@ StageArgs base_args(rb_ctx* x) {
   a.c.ctrl = reinterpret_cast<Ctrl*>(w + L.ctrl);
   a.c.dtlog = w + L.dtlog; a.c.cflp = w + L.cflp; a.c.outp = w + L.outp; a.c.r0w = w + L.r0;
   a.c.tsp = w + L.tsp;
-  a.tk = L.tk; a.ntj = L.ntj; a.nti = L.nti; a.nkc = L.nkc;
+  a.tk = L.tk; a.ntj = L.ntj; a.nti = L.nti; a.nkc = L.nkc; a.ntm = L.ntm;
   a.dt_idx = -1;
   return a;
 }
@@ -737,7 +741,7 @@ AdjLayout adj_layout(const rb_ctx* x, int n, int k) {
   // the in-plane adjoint kernel uses the forward stage kernel's tiles and z chunks
   A.tk = L.tk;
   A.nkc = L.nkc;
-  A.nblocks = L.nblocks;
+  A.nblocks = L.nblocks_adj;
   A.S = (size_t)x->g.nf * x->g.N;
   A.nseg = (n + k - 1) / k;
   size_t o = 0;

@@ -10,11 +10,22 @@
 
 namespace rb {
 
-// Stage kernel tile: 64 cells along theta (one wavefront per radial row) x 8 rows in r,
-// marching through a chunk of z planes.
+// Tiles: 64 cells along theta (one wavefront per radial row) x TI rows in r, marching
+// through a chunk of z planes; TM rows for the stage kernel (RB_TM at build time), TI for
+// the in-plane adjoint kernel.
 constexpr int TJ = 64;
 constexpr int TI = 8;
 constexpr int NT = TJ * TI;
+#ifndef RB_TM
+#define RB_TM 8
+#endif
+constexpr int TM = RB_TM;
+#ifndef RB_WPE
+#define RB_WPE 2
+#endif
+constexpr int WPE = RB_WPE;  // stage-kernel waves per SIMD the register budget is set for
+constexpr int NTM = TJ * TM;
+static_assert(TM == 4 || TM == 8, "stage-kernel tiles of 4 or 8 rows");
 constexpr int MAXF = 21;
 constexpr int DTLOG = 4096;  // device dt log entries per rb_step chunk
 
@@ -57,6 +68,8 @@ struct Layout {
   int nind;      // blocks of the indirect-gravity sums
   int nblocks;   // stage-kernel blocks
   int ntj, nti, nkc, tk;
+  int ntm;       // stage-kernel tiles in r (TM rows each)
+  int nblocks_adj;  // in-plane adjoint kernel blocks (TI-row tiles)
   int ncfl;      // blocks of the standalone CFL / conversion kernels
 };
 
@@ -125,6 +138,7 @@ struct StageArgs {
   int second;           // second stage: CFL partials, ledger, checks
   int step;             // global step index (error reporting)
   int tk, ntj, nti, nkc;
+  int ntm;              // stage-kernel tiles in r (rows of TM)
 };
 
 struct InitArgs {

@@ -18,7 +18,7 @@ namespace rb {
 // the other group's centre state of the same stage input.
 
 template <bool GAS, int ND, bool G75, bool P32, bool EXT>
-__global__ void __launch_bounds__(NT) k_march(StageArgs a, int species) {
+__global__ void __launch_bounds__(NTM, WPE) k_march(StageArgs a, int species) {
   constexpr int NG = GAS ? 5 : 4;
   constexpr bool PG = GAS && P32;  // gas in the FP32 perturbation form
   using T = typename std::conditional<PG, float, double>::type;
@@ -28,16 +28,16 @@ __global__ void __launch_bounds__(NT) k_march(StageArgs a, int species) {
   if (threadIdx.x == 0) s_stop = __atomic_load_n(&a.c.ctrl->status, __ATOMIC_RELAXED);
   __syncthreads();
   if (s_stop & FL_HARD) return;
-  __shared__ T s_pl[NG][TI + 4][TJ + 4];
-  __shared__ T s_ft[NG][TI][TJ + 1];
-  __shared__ T s_fr[NG][TI + 1][TJ];
-  __shared__ double s_red[NT / 64][3];
+  __shared__ T s_pl[NG][TM + 4][TJ + 4];
+  __shared__ T s_ft[NG][TM][TJ + 1];
+  __shared__ T s_fr[NG][TM + 1][TJ];
+  __shared__ double s_red[NTM / 64][3];
   // FP64 gas: per-thread slots (no sharing) for the column's cell below the current plane
   // and the flux of the z face below, kept in LDS between their uses (without them the
   // face solves spill registers); the other kernels keep both in registers
   constexpr bool LR = GAS && !P32;
-  __shared__ T s_rm[LR ? NG : 1][LR ? NT : 1];
-  __shared__ T s_fz[LR ? NG : 1][LR ? NT : 1];
+  __shared__ T s_rm[LR ? NG : 1][LR ? NTM : 1];
+  __shared__ T s_fz[LR ? NG : 1][LR ? NTM : 1];
 
   const Geo& g = a.g;
   const GasC gc = gas_consts(g.gamma, g.newton_max);
@@ -45,14 +45,14 @@ __global__ void __launch_bounds__(NT) k_march(StageArgs a, int species) {
   const int slot = GAS ? 0 : 1 + species;
   const int tile = xcd_tile(blockIdx.x, gridDim.x);
   const int tjb = tile % a.ntj;
-  const int tib = (tile / a.ntj) % a.nti;
-  const int kcb = tile / (a.ntj * a.nti);
+  const int tib = (tile / a.ntj) % a.ntm;
+  const int kcb = tile / (a.ntj * a.ntm);
   // one wavefront per radial row (TJ = 64 lanes of a 1D workgroup): the row index is
   // wavefront-uniform, and saying so puts the per-row tables in scalar registers and
   // scalar loads (without it the FP64 gas kernel spills)
   const int tid = threadIdx.x, tj = tid & (TJ - 1);
   const int ti = __builtin_amdgcn_readfirstlane(tid / TJ);
-  const int j0 = tjb * TJ, i0 = tib * TI;
+  const int j0 = tjb * TJ, i0 = tib * TM;
   const int k0 = kcb * a.tk, k1 = min(g.nz, k0 + a.tk);
   const int jg = j0 + tj;
   const int jw = jg % g.nth;
@@ -68,7 +68,7 @@ __global__ void __launch_bounds__(NT) k_march(StageArgs a, int species) {
   // faces the thread owns (each face of the mesh is owned by one thread of the launch),
   // 16 bits a bin in LDS slots private to the thread; a thread owns at most 4 faces per
   // plane and one more
-  __shared__ unsigned s_nh[GAS ? 4 : 1][GAS ? NT : 1];
+  __shared__ unsigned s_nh[GAS ? 4 : 1][GAS ? NTM : 1];
   if constexpr (GAS) {
 #pragma unroll
     for (int q = 0; q < 4; ++q) s_nh[q][tid] = 0u;
@@ -133,19 +133,30 @@ __global__ void __launch_bounds__(NT) k_march(StageArgs a, int species) {
     }
   }
 
-  // the halo ring of the LDS plane, one cell per thread: two rows below and above the
-  // tile, then two columns on each side of its rows.  PF: each plane's halo is loaded one
-  // plane ahead, so that its latency hides behind the previous plane's face solves (not in
-  // the FP32-perturbation gas kernel, where the held registers cost more than they hide).
-  constexpr int HW = TJ + 4, NHALO = 4 * HW + 4 * TI;
-  static_assert(NHALO <= NT, "one halo cell per thread");
+  // the halo ring of the LDS plane: two rows below and above the tile, then two columns
+  // on each side of its rows; slot tid for every thread, and slot tid + NTM for the first
+  // threads when the ring is larger than the workgroup (4-row tiles).  PF: the first slot
+  // of each plane is loaded one plane ahead, so that its latency hides behind the previous
+  // plane's face solves (not in the FP32-perturbation gas kernel, where the held registers
+  // cost more than they hide).
+  constexpr int HW = TJ + 4, NHALO = 4 * HW + 4 * TM;
+  constexpr int NH2 = NHALO > NTM ? NHALO - NTM : 0;
+  static_assert(NHALO <= 2 * NTM, "two halo cells per thread at most");
+  auto halo_pos = [&](int h, int& rr, int& cc) {
+    if (h < 2 * HW) { rr = h / HW; cc = h % HW; }
+    else if (h < 4 * HW) { rr = TM + 2 + (h - 2 * HW) / HW; cc = (h - 2 * HW) % HW; }
+    else { const int e = h - 4 * HW; rr = 2 + e / 4; cc = (e & 3) < 2 ? (e & 3) : TJ + (e & 3); }
+  };
   const bool halo_t = tid < NHALO;
   int h_rr = 0, h_cc = 0;
-  if (tid < 2 * HW) { h_rr = tid / HW; h_cc = tid % HW; }
-  else if (tid < 4 * HW) { h_rr = TI + 2 + (tid - 2 * HW) / HW; h_cc = (tid - 2 * HW) % HW; }
-  else if (halo_t) { const int e = tid - 4 * HW; h_rr = 2 + e / 4; h_cc = (e & 3) < 2 ? (e & 3) : TJ + (e & 3); }
+  if (halo_t) halo_pos(tid, h_rr, h_cc);
   const int h_ii = i0 + h_rr - 2;
   const int h_jj = (j0 + h_cc - 2 + g.nth) % g.nth;
+  const bool halo2 = NH2 > 0 && tid < NH2;
+  int h2_rr = 0, h2_cc = 0;
+  if (halo2) halo_pos(tid + NTM, h2_rr, h2_cc);
+  const int h2_ii = i0 + h2_rr - 2;
+  const int h2_jj = (j0 + h2_cc - 2 + g.nth) % g.nth;
   constexpr bool PF = !PG;
   T hv[NG];
   if (PF && halo_t) load_recon<P32, EXT, NG>(a, in, F0, k0, h_ii, h_jj, hv);
@@ -153,6 +164,31 @@ __global__ void __launch_bounds__(NT) k_march(StageArgs a, int species) {
   for (int k = k0; k < k1; ++k) {
     if (!twod) {
       load_recon<P32, EXT, NG>(a, in, F0, k + 2, ig, jw, rn);
+    }
+    // the update's base values of this plane's cell and (dust) the gas state the drag
+    // needs, requested here so that their latency hides behind the face solves.  Stage 1
+    // of the FP32 dust layout reads its base from r0 (the same cell of the same state).
+    const size_t cell = ((size_t)k * g.nr + ig) * g.nth + jg;
+    const size_t cellw = ((size_t)k * g.nr + igc) * g.nth + jw;
+    const bool upd = a.mode == MODE_UPDATE && act;
+    const bool base_r0 = P32 && !GAS && a.base == a.in;
+    using BT = typename std::conditional<PG, float, double>::type;
+    BT pb[NG];
+    if (upd && !base_r0) {
+      if constexpr (PG) {
+#pragma unroll
+        for (int f = 0; f < NG; ++f) pb[f] = ((const float*)a.base)[(size_t)f * g.N + cell];
+      } else {
+        load_cons<P32, NG>(a, a.base, F0, k, ig, jg, pb);
+      }
+    }
+    using GT = typename std::conditional<P32, float, double>::type;
+    GT pg[GAS ? 1 : 5];
+    if constexpr (!GAS) {
+      if (drag) {
+#pragma unroll
+        for (int f = 0; f < 5; ++f) pg[f] = ((const GT*)in)[(size_t)f * g.N + cellw];
+      }
     }
     // ---- stage the plane (with halo) in LDS
 #pragma unroll
@@ -162,6 +198,14 @@ __global__ void __launch_bounds__(NT) k_march(StageArgs a, int species) {
 #pragma unroll
       for (int f = 0; f < NG; ++f) s_pl[f][h_rr][h_cc] = hv[f];
       if (PF && k + 1 < k1) load_recon<P32, EXT, NG>(a, in, F0, k + 1, h_ii, h_jj, hv);
+    }
+    if constexpr (NH2 > 0) {
+      if (halo2) {
+        T hv2[NG];
+        load_recon<P32, EXT, NG>(a, in, F0, k, h2_ii, h2_jj, hv2);
+#pragma unroll
+        for (int f = 0; f < NG; ++f) s_pl[f][h2_rr][h2_cc] = hv2[f];
+      }
     }
     __syncthreads();
     // ---- theta face j+1/2 and r face i+1/2 of this cell
@@ -222,7 +266,7 @@ __global__ void __launch_bounds__(NT) k_march(StageArgs a, int species) {
         if (PG) fm += bf[WB_RHO] * bf[WB_U];
         ledger -= a.t.ar[0] * fm;
       }
-    } else if (tid < TJ + TI) {
+    } else if (tid < TJ + TM) {
       T eA[NG], eB[NG], eC[NG], eD[NG], F[NG];
       const int row = tid - TJ;
       const int irow = min(i0 + row, g.nr - 1);
@@ -262,8 +306,6 @@ __global__ void __launch_bounds__(NT) k_march(StageArgs a, int species) {
       T dz = twod ? T(0) : T(Az) * (fzhi[f] - (LR ? s_fz[f][tslot] : fzlo[f]));
       Gd[f] = -((dr + dth) + dz);
     }
-    const size_t cell = ((size_t)k * g.nr + ig) * g.nth + jg;
-    const size_t cellw = ((size_t)k * g.nr + igc) * g.nth + jw;
     const double gr = a.t.grav[((size_t)k * g.nr + igc) * 2 + 0];
     const double gz = a.t.grav[((size_t)k * g.nr + igc) * 2 + 1];
     const double* bgc = a.t.bgc + ((size_t)k * g.nr + igc) * 5;
@@ -348,7 +390,7 @@ __global__ void __launch_bounds__(NT) k_march(StageArgs a, int species) {
       if (drag) {
         double q[5];
 #pragma unroll
-        for (int f = 0; f < 5; ++f) q[f] = bgc[f] + ld_cell<P32>(a, in, f, k, igc, cellw);
+        for (int f = 0; f < 5; ++f) q[f] = bgc[f] + (double)pg[f];
         const double inv = 1.0 / q[4];
         const double u = q[0] * inv, v = q[1] * inv, w = q[2] * inv;
         const double pq = (EXT && g.drag_law) ? gc.gm1 * (q[3] - 0.5 * (q[0] * u + q[1] * v + q[2] * w)) : 0.0;
@@ -414,7 +456,7 @@ __global__ void __launch_bounds__(NT) k_march(StageArgs a, int species) {
         float nv[NG];
         // all loads before any store: the second stage updates in place
 #pragma unroll
-        for (int f = 0; f < NG; ++f) nv[f] = fma(cdt, Gt[f], ((const float*)a.base)[(size_t)f * g.N + cell]);
+        for (int f = 0; f < NG; ++f) nv[f] = fma(cdt, Gt[f], pb[f]);
 #pragma unroll
         for (int f = 0; f < NG; ++f) {
           ((float*)a.out)[(size_t)f * g.N + cell] = nv[f];
@@ -423,7 +465,20 @@ __global__ void __launch_bounds__(NT) k_march(StageArgs a, int species) {
       } else {
         const double cdt = a.coef * dt * invV;
         double bv[NG];
-        load_cons<P32, NG>(a, a.base, F0, k, ig, jg, bv);
+        if (base_r0) {
+          // load_cons of the FP32 dust layout: density times (stored velocity deviation +
+          // stationary velocity), the stored deviation being zero where the density is not
+          // positive
+          const double rd = (double)r0[3];
+          const double v0 = bw[WB_V];
+          bv[0] = rd * (double)r0[0];
+          bv[1] = rd * (rd > 0.0 ? (double)r0[1] : v0);
+          bv[2] = rd * (double)r0[2];
+          bv[3] = rd;
+        } else {
+#pragma unroll
+          for (int f = 0; f < NG; ++f) bv[f] = (double)pb[f];
+        }
 #pragma unroll
         for (int f = 0; f < NG; ++f) nvd[f] = fma(cdt, (double)Gt[f], bv[f]);
         if (!P32 || GAS) {
@@ -503,7 +558,7 @@ __global__ void __launch_bounds__(NT) k_march(StageArgs a, int species) {
     __syncthreads();
     if (tid == 0) {
       double mm = s_red[0][0], lsum = s_red[0][1], tmm = s_red[0][2];
-      for (int w2 = 1; w2 < NT / 64; ++w2) {
+      for (int w2 = 1; w2 < NTM / 64; ++w2) {
         mm = fmin(mm, s_red[w2][0]);
         lsum += s_red[w2][1];
         tmm = fmin(tmm, s_red[w2][2]);
@@ -1313,11 +1368,11 @@ template <int ND, bool P32, bool EXT>
 static void group_nd3(const StageArgs& a, int blocks, int group, hipStream_t s) {
   if (group == 0) {
     if (a.g.gamma == 1.4)
-      hipLaunchKernelGGL((k_march<true, ND, true, P32, EXT>), dim3(blocks), dim3(NT), 0, s, a, 0);
+      hipLaunchKernelGGL((k_march<true, ND, true, P32, EXT>), dim3(blocks), dim3(NTM), 0, s, a, 0);
     else
-      hipLaunchKernelGGL((k_march<true, ND, false, P32, EXT>), dim3(blocks), dim3(NT), 0, s, a, 0);
+      hipLaunchKernelGGL((k_march<true, ND, false, P32, EXT>), dim3(blocks), dim3(NTM), 0, s, a, 0);
   } else {
-    hipLaunchKernelGGL((k_march<false, ND, true, P32, EXT>), dim3(blocks), dim3(NT), 0, s, a,
+    hipLaunchKernelGGL((k_march<false, ND, true, P32, EXT>), dim3(blocks), dim3(NTM), 0, s, a,
                        group - 1);
   }
 }
