@@ -79,6 +79,47 @@ __global__ void __launch_bounds__(NTM, WPE) k_march(StageArgs a, int species) {
       if (own) s_nh[b >> 1][tid] += 1u << (16 * (b & 1));
     }
   };
+
+  // The per-plane tables of the tile's rows, staged in LDS one plane ahead (double
+  // buffered): the stationary flow at the cell centres (wc) and, for the gas, at the r
+  // faces i0-1/2 .. i0+TM-1/2 (wr) and the z face above the plane (wz); the cells'
+  // stationary conservative state (bgc) and gravity.  Thread t stages entry t: its
+  // address is tab_p0 + plane * tab_stride.
+  constexpr int T_WC = 0;
+  constexpr int T_WR = T_WC + TM * WB_N;
+  constexpr int T_WZ = T_WR + (GAS ? (TM + 1) * WB_N : 0);
+  constexpr int T_BG = T_WZ + (GAS ? TM * WB_N : 0);
+  constexpr int T_GR = T_BG + TM * 5;
+  constexpr int NTAB = T_GR + TM * 2;
+  static_assert(NTAB <= NTM, "one table entry per thread");
+  __shared__ double s_tab[2][NTAB];
+  const bool tab_t = tid < NTAB;
+  const double* tab_p0 = nullptr;
+  size_t tab_stride = 0;
+  if (tab_t) {
+    const size_t nr = (size_t)g.nr;
+    if (tid < T_WR) {
+      const int r = tid / WB_N, e = tid % WB_N;
+      tab_p0 = a.t.wc + (size_t)min(i0 + r, g.nr - 1) * WB_N + e;
+      tab_stride = nr * WB_N;
+    } else if (tid < T_WZ) {
+      const int f = (tid - T_WR) / WB_N, e = (tid - T_WR) % WB_N;
+      tab_p0 = a.t.wr + (size_t)min(i0 + f, g.nr) * WB_N + e;
+      tab_stride = (nr + 1) * WB_N;
+    } else if (tid < T_BG) {
+      const int r = (tid - T_WZ) / WB_N, e = (tid - T_WZ) % WB_N;
+      tab_p0 = a.t.wz + (nr + (size_t)min(i0 + r, g.nr - 1)) * WB_N + e;
+      tab_stride = nr * WB_N;
+    } else if (tid < T_GR) {
+      const int r = (tid - T_BG) / 5, e = (tid - T_BG) % 5;
+      tab_p0 = a.t.bgc + (size_t)min(i0 + r, g.nr - 1) * 5 + e;
+      tab_stride = nr * 5;
+    } else {
+      const int r = (tid - T_GR) / 2, e = (tid - T_GR) % 2;
+      tab_p0 = a.t.grav + (size_t)min(i0 + r, g.nr - 1) * 2 + e;
+      tab_stride = nr * 2;
+    }
+  }
   double dtmin = 1e300;
   double tsmin = 1e300;  // smallest stopping time of the new state (drag law 1)
   double ledger = 0.0;
@@ -161,10 +202,15 @@ __global__ void __launch_bounds__(NTM, WPE) k_march(StageArgs a, int species) {
   T hv[NG];
   if (PF && halo_t) load_recon<P32, EXT, NG>(a, in, F0, k0, h_ii, h_jj, hv);
 
+  if (tab_t) s_tab[k0 & 1][tid] = tab_p0[(size_t)k0 * tab_stride];
+
   for (int k = k0; k < k1; ++k) {
     if (!twod) {
       load_recon<P32, EXT, NG>(a, in, F0, k + 2, ig, jw, rn);
     }
+    const int kb = k & 1;
+    double tab_next = 0.0;
+    if (tab_t && k + 1 < k1) tab_next = tab_p0[(size_t)(k + 1) * tab_stride];
     // the update's base values of this plane's cell and (dust) the gas state the drag
     // needs, requested here so that their latency hides behind the face solves.  Stage 1
     // of the FP32 dust layout reads its base from r0 (the same cell of the same state).
@@ -217,7 +263,7 @@ __global__ void __launch_bounds__(NTM, WPE) k_march(StageArgs a, int species) {
         eC[f] = s_pl[f][ti + 2][tj + 3]; eD[f] = s_pl[f][ti + 2][tj + 4];
       }
       {
-        const double* bf = a.t.wc + ((size_t)k * g.nr + igc) * WB_N;
+        const double* bf = &s_tab[kb][T_WC + ti * WB_N];
         face(DT(), eA, eB, eC, eD, nullptr, nullptr, bf, bf, bf, F);
         if (GAS) tally(act);
       }
@@ -229,8 +275,7 @@ __global__ void __launch_bounds__(NTM, WPE) k_march(StageArgs a, int species) {
         eC[f] = s_pl[f][ti + 3][tj + 2]; eD[f] = s_pl[f][ti + 4][tj + 2];
       }
       {
-        const int ifc = min(ig + 1, g.nr);
-        const double* bf = a.t.wr + ((size_t)k * (g.nr + 1) + ifc) * WB_N;
+        const double* bf = GAS ? &s_tab[kb][T_WR + (ti + 1) * WB_N] : nullptr;
         face(DR(), eA, eB, eC, eD, rco_ptr(a, ig), rco_ptr(a, ig + 1), bf,
              bg_ptr(a, k, min(ig, g.nr)), bg_ptr(a, k, min(ig + 1, g.nr)), F);
         if (GAS) tally(act);
@@ -253,7 +298,7 @@ __global__ void __launch_bounds__(NTM, WPE) k_march(StageArgs a, int species) {
         eA[f] = s_pl[f][0][col + 2]; eB[f] = s_pl[f][1][col + 2];
         eC[f] = s_pl[f][2][col + 2]; eD[f] = s_pl[f][3][col + 2];
       }
-      const double* bf = a.t.wr + ((size_t)k * (g.nr + 1) + i0) * WB_N;
+      const double* bf = GAS ? &s_tab[kb][T_WR] : nullptr;
       face(DR(), eA, eB, eC, eD, rco_ptr(a, i0 - 1), rco_ptr(a, i0), bf, bg_ptr(a, k, i0 - 1),
            bg_ptr(a, k, i0), F);
       // the tile's lower r face is the upper face of the tile below, except at the inner
@@ -269,13 +314,12 @@ __global__ void __launch_bounds__(NTM, WPE) k_march(StageArgs a, int species) {
     } else if (tid < TJ + TM) {
       T eA[NG], eB[NG], eC[NG], eD[NG], F[NG];
       const int row = tid - TJ;
-      const int irow = min(i0 + row, g.nr - 1);
 #pragma unroll
       for (int f = 0; f < NG; ++f) {
         eA[f] = s_pl[f][row + 2][0]; eB[f] = s_pl[f][row + 2][1];
         eC[f] = s_pl[f][row + 2][2]; eD[f] = s_pl[f][row + 2][3];
       }
-      const double* bf = a.t.wc + ((size_t)k * g.nr + irow) * WB_N;
+      const double* bf = &s_tab[kb][T_WC + row * WB_N];
       face(DT(), eA, eB, eC, eD, nullptr, nullptr, bf, bf, bf, F);
 #pragma unroll
       for (int f = 0; f < NG; ++f) s_ft[f][row][0] = F[f];
@@ -286,7 +330,7 @@ __global__ void __launch_bounds__(NTM, WPE) k_march(StageArgs a, int species) {
 #pragma unroll
         for (int f = 0; f < NG; ++f) rm[f] = s_rm[f][tslot];
       }
-      const double* bf = a.t.wz + ((size_t)(k + 1) * g.nr + igc) * WB_N;
+      const double* bf = GAS ? &s_tab[kb][T_WZ + ti * WB_N] : nullptr;
       face(DZ(), rm, r0, rp, rn, nullptr, nullptr, bf, bg_ptr(a, k, igc), bg_ptr(a, k + 1, igc),
            fzhi);
       if (GAS) tally(act);
@@ -306,10 +350,10 @@ __global__ void __launch_bounds__(NTM, WPE) k_march(StageArgs a, int species) {
       T dz = twod ? T(0) : T(Az) * (fzhi[f] - (LR ? s_fz[f][tslot] : fzlo[f]));
       Gd[f] = -((dr + dth) + dz);
     }
-    const double gr = a.t.grav[((size_t)k * g.nr + igc) * 2 + 0];
-    const double gz = a.t.grav[((size_t)k * g.nr + igc) * 2 + 1];
-    const double* bgc = a.t.bgc + ((size_t)k * g.nr + igc) * 5;
-    const double* bw = a.t.wc + ((size_t)k * g.nr + igc) * WB_N;
+    const double gr = s_tab[kb][T_GR + ti * 2 + 0];
+    const double gz = s_tab[kb][T_GR + ti * 2 + 1];
+    const double* bgc = &s_tab[kb][T_BG + ti * 5];
+    const double* bw = &s_tab[kb][T_WC + ti * WB_N];
     T S[NG];
     if constexpr (PG) {
       // source change S(E) - S(E0), every term formed from the perturbations W' (the
@@ -519,6 +563,9 @@ __global__ void __launch_bounds__(NTM, WPE) k_march(StageArgs a, int species) {
         dtmin = fmin(dtmin, g.cfl * Vc / (spd * maxA));
       }
     }
+    // ---- the next plane's tables (read after the next plane's first barrier; buffer
+    //      (k + 1) & 1 was last read in the previous plane)
+    if (tab_t && k + 1 < k1) s_tab[(k + 1) & 1][tid] = tab_next;
     // ---- shift the ring
 #pragma unroll
     for (int f = 0; f < NG; ++f) {
