@@ -766,13 +766,15 @@ __device__ __forceinline__ void load_recon(const StageArgs& a, const void* st, i
     const int sp = (F0 - 5) >> 2;
     if constexpr (P32) {
       // the FP32 layout stores the dust velocity deviations from the stationary flow
+      // (all requested before the density decides: a load made conditional on it would wait)
       const float* vel = (const float*)st + (size_t)(5 + 3 * sp) * g.N + cell;
       const double v0 = a.t.wc[((size_t)kc * g.nr + i) * WB_N + WB_V];
       const double rd = ((const double*)st)[p32_f64_base(g) + (size_t)sp * g.N + cell];
+      const float v[3] = {vel[0], vel[g.N], vel[2 * g.N]};
       const bool full = rd > 0.0;
-      out[0] = full ? (T)vel[0] : T(0);
-      out[1] = full ? (T)(v0 + (double)vel[g.N]) : T(0);
-      out[2] = full ? (T)vel[2 * g.N] : T(0);
+      out[0] = full ? (T)v[0] : T(0);
+      out[1] = full ? (T)(v0 + (double)v[1]) : T(0);
+      out[2] = full ? (T)v[2] : T(0);
       out[3] = (T)rd;
     } else {
       const double* d = (const double*)st + (size_t)F0 * g.N + cell;

@@ -218,12 +218,20 @@ __global__ void __launch_bounds__(NTM, WPE) k_march(StageArgs a, int species) {
     const size_t cellw = ((size_t)k * g.nr + igc) * g.nth + jw;
     const bool upd = a.mode == MODE_UPDATE && act;
     const bool base_r0 = P32 && !GAS && a.base == a.in;
+    // (raw stored values: any arithmetic on them here would wait for the loads)
     using BT = typename std::conditional<PG, float, double>::type;
     BT pb[NG];
+    float pvel[P32 && !GAS ? 3 : 1];  // FP32 dust layout: stored velocity deviations
     if (upd && !base_r0) {
       if constexpr (PG) {
 #pragma unroll
         for (int f = 0; f < NG; ++f) pb[f] = ((const float*)a.base)[(size_t)f * g.N + cell];
+      } else if constexpr (P32 && !GAS) {
+        const float* vel = (const float*)a.base + (size_t)(5 + 3 * species) * g.N + cell;
+        pb[3] = ((const double*)a.base)[p32_f64_base(g) + (size_t)species * g.N + cell];
+        pvel[0] = vel[0];
+        pvel[1] = vel[g.N];
+        pvel[2] = vel[2 * (size_t)g.N];
       } else {
         load_cons<P32, NG>(a, a.base, F0, k, ig, jg, pb);
       }
@@ -373,17 +381,27 @@ __global__ void __launch_bounds__(NTM, WPE) k_march(StageArgs a, int species) {
         const double u = (double)up, v = bw[WB_V] + (double)vp, w2 = (double)wp;
         const double pq = (EXT && g.drag_law) ? bw[WB_P] + (double)pp : 0.0;
         double dx = 0.0, dy = 0.0, dzz = 0.0;
+        // every species' density and velocities requested together (loads made
+        // conditional on the density would each wait for it)
+        double rds[ND > 0 ? ND : 1];
+        float vds[ND > 0 ? ND : 1][3];
 #pragma unroll
         for (int s2 = 0; s2 < ND; ++s2) {
-          const int o = 5 + 4 * s2;
+          const float* vel = (const float*)in + (size_t)(5 + 3 * s2) * g.N + cellw;
+          rds[s2] = ld_cell<P32>(a, in, 5 + 4 * s2 + 3, k, igc, cellw);
+          vds[s2][0] = vel[0];
+          vds[s2][1] = vel[g.N];
+          vds[s2][2] = vel[2 * (size_t)g.N];
+        }
+#pragma unroll
+        for (int s2 = 0; s2 < ND; ++s2) {
           // the FP32 layout stores the dust velocities as deviations from the stationary
           // flow's, as the gas W' is: the velocity difference is formed from the deviations
-          const double rd = ld_cell<P32>(a, in, o + 3, k, igc, cellw);
-          const float* vel = (const float*)in + (size_t)(5 + 3 * s2) * g.N + cellw;
+          const double rd = rds[s2];
           const bool full = rd > 0.0;
-          const double dud = full ? (double)vel[0] - (double)up : -u;
-          const double dvd = full ? (double)vel[g.N] - (double)vp : -v;
-          const double dwd = full ? (double)vel[2 * (size_t)g.N] - (double)wp : -w2;
+          const double dud = full ? (double)vds[s2][0] - (double)up : -u;
+          const double dvd = full ? (double)vds[s2][1] - (double)vp : -v;
+          const double dwd = full ? (double)vds[s2][2] - (double)wp : -w2;
           const double its = inv_tstop<EXT>(g, s2, omk, rg, pq);
           dx += rd * dud * its;
           dy += rd * dvd * its;
@@ -406,16 +424,21 @@ __global__ void __launch_bounds__(NTM, WPE) k_march(StageArgs a, int species) {
       S[4] = 0.0;
       if (drag) {
         double dx = 0.0, dy = 0.0, dzz = 0.0;
+        // every species' variables requested together (see the FP32 branch)
+        double dvar[ND > 0 ? ND : 1][4];
+#pragma unroll
+        for (int s2 = 0; s2 < ND; ++s2)
+#pragma unroll
+          for (int c = 0; c < 4; ++c) dvar[s2][c] = ld_cell<P32>(a, in, 5 + 4 * s2 + c, k, igc, cellw);
 #pragma unroll
         for (int s2 = 0; s2 < ND; ++s2) {
-          const int o = 5 + 4 * s2;
-          const double rd = ld_cell<P32>(a, in, o + 3, k, igc, cellw);
+          const double rd = dvar[s2][3];
           double ud = 0.0, vd = 0.0, wd = 0.0;
           if (rd > 0.0) {
             double id = 1.0 / rd;
-            ud = ld_cell<P32>(a, in, o, k, igc, cellw) * id;
-            vd = ld_cell<P32>(a, in, o + 1, k, igc, cellw) * id;
-            wd = ld_cell<P32>(a, in, o + 2, k, igc, cellw) * id;
+            ud = dvar[s2][0] * id;
+            vd = dvar[s2][1] * id;
+            wd = dvar[s2][2] * id;
           }
           const double its = inv_tstop<EXT>(g, s2, omk, rho, p);
           dx += rd * (ud - u) * its;
@@ -519,6 +542,12 @@ __global__ void __launch_bounds__(NTM, WPE) k_march(StageArgs a, int species) {
           bv[1] = rd * (rd > 0.0 ? (double)r0[1] : v0);
           bv[2] = rd * (double)r0[2];
           bv[3] = rd;
+        } else if constexpr (P32 && !GAS) {
+          // load_cons of the FP32 dust layout
+          bv[0] = pb[3] * (double)pvel[0];
+          bv[1] = pb[3] * (bw[WB_V] + (double)pvel[1]);
+          bv[2] = pb[3] * (double)pvel[2];
+          bv[3] = pb[3];
         } else {
 #pragma unroll
           for (int f = 0; f < NG; ++f) bv[f] = (double)pb[f];
