@@ -203,6 +203,10 @@ __global__ void __launch_bounds__(NTM, WPE) k_march(StageArgs a, int species) {
   if (PF && halo_t) load_recon<P32, EXT, NG>(a, in, F0, k0, h_ii, h_jj, hv);
 
   if (tab_t) s_tab[k0 & 1][tid] = tab_p0[(size_t)k0 * tab_stride];
+  // the radial parabola weights and limiter bounds of rows i0-1 .. i0+TM (plane
+  // invariant), read by the r faces
+  __shared__ double s_rco[(TM + 2) * RC_N];
+  if (tid < (TM + 2) * RC_N) s_rco[tid] = rco_ptr(a, i0 - 1 + tid / RC_N)[tid % RC_N];
 
   for (int k = k0; k < k1; ++k) {
     if (!twod) {
@@ -284,7 +288,7 @@ __global__ void __launch_bounds__(NTM, WPE) k_march(StageArgs a, int species) {
       }
       {
         const double* bf = GAS ? &s_tab[kb][T_WR + (ti + 1) * WB_N] : nullptr;
-        face(DR(), eA, eB, eC, eD, rco_ptr(a, ig), rco_ptr(a, ig + 1), bf,
+        face(DR(), eA, eB, eC, eD, &s_rco[(ti + 1) * RC_N], &s_rco[(ti + 2) * RC_N], bf,
              bg_ptr(a, k, min(ig, g.nr)), bg_ptr(a, k, min(ig + 1, g.nr)), F);
         if (GAS) tally(act);
         if (a.second && act && ig == g.nr - 1) {
@@ -307,7 +311,7 @@ __global__ void __launch_bounds__(NTM, WPE) k_march(StageArgs a, int species) {
         eC[f] = s_pl[f][2][col + 2]; eD[f] = s_pl[f][3][col + 2];
       }
       const double* bf = GAS ? &s_tab[kb][T_WR] : nullptr;
-      face(DR(), eA, eB, eC, eD, rco_ptr(a, i0 - 1), rco_ptr(a, i0), bf, bg_ptr(a, k, i0 - 1),
+      face(DR(), eA, eB, eC, eD, &s_rco[0], &s_rco[RC_N], bf, bg_ptr(a, k, i0 - 1),
            bg_ptr(a, k, i0), F);
       // the tile's lower r face is the upper face of the tile below, except at the inner
       // boundary
