@@ -55,9 +55,14 @@
  *     bump's amplitude, width and centre are configuration values);
  *   - drag uses a constant Stokes number, t_s = St / Omega_K(r), or (drag_law 1) the
  *     Epstein / Stokes law of Sect. 2.9 with c_s the isothermal sound speed sqrt(p/rho)
- *     of the cell's gas (the c_s of App. A) and lambda = mfp_coef / rho_g.
- * Parity unpinned (no external value exists for them): the limiter variant,
- * the dust tie rule, the vortex recipe of the initial state.
+ *     of the cell's gas (the c_s of App. A) and lambda = mfp_coef / rho_g;
+ *   - the drag is explicit inside the RK2 stages (a step at or above the smallest
+ *     stopping time is refused), or (drag_exact) split off: the drag alone over dt/2,
+ *     the two stages without it, the drag alone over dt/2, each drag part solved exactly
+ *     for the cell's held densities and stopping times;
+ *   - the density noise of the initial state is one seeded field per fluid.
+ * Parity unpinned (no external value exists for them): the limiter variant and the
+ * dust tie rule.
  */
 #include <algorithm>
 #include <cmath>
