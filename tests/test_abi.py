@@ -96,3 +96,19 @@ def test_null_arguments_rejected(lib):
     assert lib.rb_step(None, 1, None, None) == rossbi.RB_EINVAL
     assert lib.rb_get_fields(None, None, 0) == rossbi.RB_EINVAL
     assert lib.rb_last_error(None) == b"null context"
+
+
+def test_fp32_form_needs_a_disc_background(lib):
+    """The FP32-perturbation form stores deviations from a stationary flow: the Sod
+    annulus (no stationary flow) and gamma other than 7/5 are refused; drag_exact takes
+    0 or 1 only."""
+    b = rossbi.rb_buffers()
+    sod = rossbi.to_config(synth.C1_SOD, precision=rossbi.RB_FP32_PERT)
+    assert lib.rb_query_sizes(ctypes.byref(sod), ctypes.byref(b)) == rossbi.RB_EINVAL
+    g53 = rossbi.to_config(synth.C2_DISC.with_(gamma=5.0 / 3.0), precision=rossbi.RB_FP32_PERT)
+    assert lib.rb_query_sizes(ctypes.byref(g53), ctypes.byref(b)) == rossbi.RB_EINVAL
+    ok = rossbi.to_config(synth.C2_DISC, precision=rossbi.RB_FP32_PERT)
+    assert lib.rb_query_sizes(ctypes.byref(ok), ctypes.byref(b)) == rossbi.RB_OK
+    bad = rossbi.to_config(synth.C3_BIFLUID)
+    bad.drag_exact = 2
+    assert lib.rb_query_sizes(ctypes.byref(bad), ctypes.byref(b)) == rossbi.RB_EINVAL

@@ -70,35 +70,6 @@ def test_sod_variant_parity(rb, name, cfg, dt):
     sim.close()
 
 
-@pytest.mark.parametrize("name,cfg,dt", VARIANTS, ids=[v[0] for v in VARIANTS])
-def test_sod_variant_fp32p(rb, name, cfg, dt):
-    """The same variants in the FP32-perturbation form: the annulus has no stationary flow,
-    so every face goes to the FP64 solver (all counted as re-solves) and only the storage
-    is FP32; the status codes match, density and pressure stay within 1e-5 of the FP64
-    oracle (pressure relative to (gamma - 1) E, the scale it is a difference on)."""
-    from tests.test_gpu_fp32p import errors32
-    say(f"[riemann edge fp32p] {name}")
-    n = 10
-    sim = rb.Sim(cfg, precision=rb.RB_FP32_PERT)
-    o = oracle.Oracle(cfg)
-    if dt is None:
-        st2, dts2 = o.step(n)
-        st, _ = sim.step(n, dt_list=dts2)
-    else:
-        st, _ = sim.step(n, dt=dt)
-        st2, _ = o.step(n, dt=dt)
-    expect = oracle.EVACUUM if name == "vacuum" else 0
-    assert st2 == expect and st == expect, (st, st2)
-    d = sim.diagnostics()
-    faces = 2 * n * ((cfg.nr + 1) * cfg.nth + cfg.nr * cfg.nth)
-    assert d.fp64_resolves == faces, (d.fp64_resolves, faces)
-    errs = errors32(sim.fields(), o.state(), cfg)
-    worst = {k: float(np.max(v)) for k, v in errs.items()}
-    say(f"[riemann edge fp32p] {name}: " + " ".join(f"{k}={v:.1e}" for k, v in worst.items()))
-    assert worst["rho"] <= 1e-5 and worst["p"] <= 1e-5, worst
-    sim.close()
-
-
 def check_histogram(d_gpu, d_or):
     """Both sides count every gas face once per evaluation.  The GPU takes supersonic
     faces without a Newton solve (bin 0) where the oracle iterates, so faces may only move
