@@ -408,10 +408,16 @@ __device__ void dust_riemann(double rL, double uL, double aL, double bL, double 
     else if (uR < 0.0) side = 1;
     else return;
   } else {
-    double xa = sqrt(rL) * uL;
-    double xb = sqrt(rR) * uR;
-    double num = xa + xb;
-    side = num > 0.0 ? -1 : (num < 0.0 ? 1 : 0);
+    // delta shock: its speed has the sign of sqrt(rL) uL + sqrt(rR) uR.  With uL > uR,
+    // both terms share a sign unless uL > 0 > uR, where the sign is that of
+    // rL uL^2 - rR uR^2 (both sides squared, no square root); mirror-symmetric states
+    // give exactly zero either way
+    if (uR >= 0.0 && uL > 0.0) side = -1;
+    else if (uL <= 0.0 && uR < 0.0) side = 1;
+    else {
+      const double d = rL * uL * uL - rR * uR * uR;
+      side = d > 0.0 ? -1 : (d < 0.0 ? 1 : 0);
+    }
   }
   if constexpr (REC) *rec = side;
   double mL = rL * uL, mR = rR * uR;
