@@ -435,6 +435,26 @@ struct AdjCtx {
     return A.cw * a.t.rt[(size_t)i * RT_N + RT_INVV] *
            A.cot[(size_t)(F0 + f) * g.N + ((size_t)k * g.nr + i) * g.nth + j];
   }
+  // the difference w(k1, i1, j1) - w(k0, i0, j0) of every field, times s, with all loads
+  // requested before any arithmetic (loads under per-field conditions each waited)
+  __device__ void wc_diff(int k1, int i1, int j1, int k0, int i0, int j0, double s,
+                          double* out) const {
+    const bool in1 = !(k1 < 0 || k1 >= g.nz || i1 < 0 || i1 >= g.nr);
+    const bool in0 = !(k0 < 0 || k0 >= g.nz || i0 < 0 || i0 >= g.nr);
+    const size_t c1 = in1 ? ((size_t)k1 * g.nr + i1) * g.nth + j1 : 0;
+    const size_t c0 = in0 ? ((size_t)k0 * g.nr + i0) * g.nth + j0 : 0;
+    const double v1 = in1 ? a.t.rt[(size_t)i1 * RT_N + RT_INVV] : 0.0;
+    const double v0 = in0 ? a.t.rt[(size_t)i0 * RT_N + RT_INVV] : 0.0;
+    double x1[NG], x0[NG];
+#pragma unroll
+    for (int f = 0; f < NG; ++f) {
+      x1[f] = A.cot[(size_t)(F0 + f) * g.N + c1];
+      x0[f] = A.cot[(size_t)(F0 + f) * g.N + c0];
+    }
+#pragma unroll
+    for (int f = 0; f < NG; ++f)
+      out[f] = s * ((in1 ? A.cw * v1 * x1[f] : 0.0) - (in0 ? A.cw * v0 * x0[f] : 0.0));
+  }
 };
 
 template <int D, bool GAS, bool G75>
@@ -502,11 +522,11 @@ __global__ void __launch_bounds__(NT) k_adj_plane(AdjArgs A, int species) {
     const int i = i0 + r;
     const int jb = X.jwrap(j0 + cb), jc = X.jwrap(j0 + cb + 1);
     const double ath = a.t.rt[(size_t)i * RT_N + RT_ATH];
+    X.wc_diff(k, i, jc, k, i, jb, ath, Fb);
 #pragma unroll
     for (int f = 0; f < NG; ++f) {
       eA[f] = s_e[f][r + H][cb + H - 1]; eB[f] = s_e[f][r + H][cb + H];
       eC[f] = s_e[f][r + H][cb + H + 1]; eD[f] = s_e[f][r + H][cb + H + 2];
-      Fb[f] = ath * (X.wc(f, k, i, jc) - X.wc(f, k, i, jb));
       oA[f] = 0.0; oB[f] = 0.0; oC[f] = 0.0; oD[f] = 0.0;
     }
     const double* bf = a.t.wc + ((size_t)k * g.nr + i) * WB_N;
@@ -519,11 +539,11 @@ __global__ void __launch_bounds__(NT) k_adj_plane(AdjArgs A, int species) {
     const int ib = i0 + rb;
     const int j = X.jwrap(j0 + cl);
     const double ar = a.t.ar[ib + 1];
+    X.wc_diff(k, ib + 1, j, k, ib, j, ar, Fb);
 #pragma unroll
     for (int f = 0; f < NG; ++f) {
       eA[f] = s_e[f][rb + H - 1][cl + H]; eB[f] = s_e[f][rb + H][cl + H];
       eC[f] = s_e[f][rb + H + 1][cl + H]; eD[f] = s_e[f][rb + H + 2][cl + H];
-      Fb[f] = ar * (X.wc(f, k, ib + 1, j) - X.wc(f, k, ib, j));
       oA[f] = 0.0; oB[f] = 0.0; oC[f] = 0.0; oD[f] = 0.0;
     }
     const double* bf = a.t.wr + ((size_t)k * (g.nr + 1) + (ib + 1)) * WB_N;
@@ -650,21 +670,30 @@ __global__ void __launch_bounds__(NT) k_adj_plane(AdjArgs A, int species) {
       // drag D_s = rho_d (v_d - v) Omega_K / St on the gas (+) and the dust (-), and
       // v . D in the gas energy
       double Ub[3] = {0.0, 0.0, 0.0}, Dt[3] = {0.0, 0.0, 0.0};
+      // every species' variables and cotangents requested together (loads made
+      // conditional on the density would each wait for it)
+      double ev[ND > 0 ? ND : 1][4], cv[ND > 0 ? ND : 1][3];
+#pragma unroll
+      for (int s = 0; s < ND; ++s)
+#pragma unroll
+        for (int c2 = 0; c2 < 4; ++c2) {
+          ev[s][c2] = E[(size_t)(5 + 4 * s + c2) * N + cell];
+          if (c2 < 3) cv[s][c2] = cot[(size_t)(5 + 4 * s + c2) * N + cell];
+        }
 #pragma unroll
       for (int s = 0; s < ND; ++s) {
-        const int o = 5 + 4 * s;
-        const double rdn = E[(size_t)(o + 3) * N + cell];
+        const double rdn = ev[s][3];
         double vd[3] = {0.0, 0.0, 0.0};
         if (rdn > 0.0) {
           const double id = 1.0 / rdn;
 #pragma unroll
-          for (int c2 = 0; c2 < 3; ++c2) vd[c2] = E[(size_t)(o + c2) * N + cell] * id;
+          for (int c2 = 0; c2 < 3; ++c2) vd[c2] = ev[s][c2] * id;
         }
         const double its = omk * g.inv_st[s];
 #pragma unroll
         for (int c2 = 0; c2 < 3; ++c2) {
           Dt[c2] += rdn * (vd[c2] - U[c2]) * its;
-          const double Db = sg[c2] + sg[3] * U[c2] - cw * cot[(size_t)(o + c2) * N + cell];
+          const double Db = sg[c2] + sg[3] * U[c2] - cw * cv[s][c2];
           Ub[c2] -= its * rdn * Db;
         }
       }
@@ -759,8 +788,7 @@ __global__ void __launch_bounds__(256) k_adj_z(AdjArgs A, int species, int tkz) 
   // adds the face's contributions into oA..oD
   auto zface = [&](int kf, double* oA, double* oB, double* oC, double* oD) {
     double Fb[NG];
-#pragma unroll
-    for (int f = 0; f < NG; ++f) Fb[f] = Az * (X.wc(f, kf + 1, ig, jg) - X.wc(f, kf, ig, jg));
+    X.wc_diff(kf + 1, ig, jg, kf, ig, jg, Az, Fb);
     const double* bf = a.t.wz + ((size_t)(kf + 1) * g.nr + ig) * WB_N;
     face_vjp<2, GAS, G75>(X.gc, ra, rb, rc, rd, nullptr, nullptr, bf, bg_ptr(a, kf, ig),
                           bg_ptr(a, kf + 1, ig), Fb, oA, oB, oC, oD);
