@@ -736,14 +736,22 @@ __global__ void __launch_bounds__(NT) k_adj_plane(AdjArgs A, int species) {
       cur[3] -= its * dotU;
       stb -= dotD / st;
     }
-    // all loads before any store (out may be one of the bases)
-    double v[NG];
+    // all loads before any store (out may be one of the bases), each base's fields
+    // requested together
+    double v[NG], b1[NG], b2[NG];
+    if (A.base1) {
+#pragma unroll
+      for (int f = 0; f < NG; ++f) b1[f] = A.base1[(size_t)(F0 + f) * N + cell];
+    }
+    if (A.base2) {
+#pragma unroll
+      for (int f = 0; f < NG; ++f) b2[f] = A.base2[(size_t)(F0 + f) * N + cell];
+    }
 #pragma unroll
     for (int f = 0; f < NG; ++f) {
-      const size_t o = (size_t)(F0 + f) * N + cell;
       v[f] = cur[f];
-      if (A.base1) v[f] += A.base1[o];
-      if (A.base2) v[f] += A.base2[o];
+      if (A.base1) v[f] += b1[f];
+      if (A.base2) v[f] += b2[f];
     }
 #pragma unroll
     for (int f = 0; f < NG; ++f) A.out[(size_t)(F0 + f) * N + cell] = v[f];
