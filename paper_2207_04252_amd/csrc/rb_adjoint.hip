@@ -773,7 +773,7 @@ __global__ void __launch_bounds__(NT) k_adj_plane(AdjArgs A, int species) {
 // contributions of every z face to the output written by k_adj_plane (each cell
 // completed in order: its faces k-3/2 .. k+3/2, lower first).
 template <bool GAS, int ND, bool G75>
-__global__ void __launch_bounds__(256) k_adj_z(AdjArgs A, int species, int tkz) {
+__global__ void __launch_bounds__(256, 2) k_adj_z(AdjArgs A, int species, int tkz) {
   using C = AdjCtx<GAS>;
   constexpr int NG = C::NG;
   const C X(A, species);
