@@ -49,11 +49,13 @@ KERNEL_SOURCES = ("rb_kernels.hip", "rb_device.h", "rb_pert32.h", "rb_internal.h
 
 
 def kernel_hash():
-    """Hash of the sources the stage kernels are compiled from."""
+    """Hash of the sources the stage kernels are compiled from and of the compiler flags."""
+    from paper_2207_04252_amd import build as hipbuild
     h = hashlib.sha256()
     for name in KERNEL_SOURCES:
         with open(os.path.join(ROOT, "paper_2207_04252_amd", "csrc", name), "rb") as f:
             h.update(f.read())
+    h.update(" ".join(hipbuild.HIPCC_FLAGS).encode())
     return h.hexdigest()[:16]
 
 

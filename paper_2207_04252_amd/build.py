@@ -14,11 +14,14 @@ LIB_PATH = os.path.join(HERE, LIB_NAME)
 SOURCES = ["rb_kernels.hip", "rb_adjoint.hip", "rb_api.hip"]
 
 # Device code: no packed FP32 instructions (-packed-fp32-ops), contraction only within
-# an expression, no fast-math.
+# an expression, no fast-math.  The machine scheduler groups memory instructions into
+# clauses (max-memory-clause): the stage kernels run at a fixed two waves per SIMD and are
+# latency-bound, and clustering their loads measured 4% faster per step than the default.
 HIPCC_FLAGS = [
     "-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC", "-shared",
     "-ffp-contract=on", "-fno-fast-math",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    "-mllvm", "-amdgpu-sched-strategy=max-memory-clause",
     "-Wall", "-Wno-unused-function", "-Wno-unused-variable", "-Wno-unused-but-set-variable",
 ]
 
