@@ -644,15 +644,15 @@ __device__ __forceinline__ void st_cell(const StageArgs& a, void* st, int f, int
   }
 }
 
-// A whole dust cell (momenta r, theta, z, density) of cell (k, i) into the FP32 layout from
-// registers: the density, then the velocity deviations formed with it (the same values
-// st_cell stores field by field, without reading the density back)
-__device__ __forceinline__ void st_dust32(const StageArgs& a, void* st, int sp, int k, int i,
-                                          size_t cell, const double v[4]) {
+// A whole dust cell (momenta r, theta, z, density) into the FP32 layout from registers:
+// the density, then the velocity deviations formed with it (the same values st_cell
+// stores field by field, without reading the density back); v0 is the stationary
+// azimuthal velocity of the cell
+__device__ __forceinline__ void st_dust32(const StageArgs& a, void* st, int sp, size_t cell,
+                                          const double v[4], double v0) {
   const Geo& g = a.g;
   ((double*)st)[p32_f64_base(g) + (size_t)sp * g.N + cell] = v[3];
   const double ir = v[3] > 1e-300 ? frcp(v[3]) : 0.0;
-  const double v0 = a.t.wc[((size_t)k * g.nr + i) * WB_N + WB_V];
   float* vel = (float*)st + (size_t)(5 + 3 * sp) * g.N + cell;
   const bool full = v[3] > 1e-300;
   vel[0] = full ? (float)(v[0] * ir) : 0.0f;
@@ -792,6 +792,85 @@ __device__ __forceinline__ void load_recon(const StageArgs& a, const void* st, i
       out[3] = (T)rd;
     }
   }
+}
+
+// A dust cell's reconstructed variables in two steps: dust_fetch issues the loads and does
+// no arithmetic on what they return, dust_finish forms the variables (the same values as
+// load_recon).  A wavefront waits for a load where its result is first used, so a fetch
+// made a phase or a plane ahead of its finish keeps that wait off the critical path.
+// Ghost cells carry their table values in d; interior cells carry the stored fields (FP64
+// layout: momenta and density in d) or (FP32 layout) the density in d[3], the stationary
+// azimuthal velocity in d[1] and the stored velocity deviations in v.
+template <bool P32>
+struct DustRaw {
+  double d[4];
+  float v[P32 ? 3 : 1];
+  bool ghost;
+};
+template <bool P32, bool EXT>
+__device__ __forceinline__ void dust_fetch(const StageArgs& a, const void* st, int F0, int k, int i,
+                                           int j, DustRaw<P32>& R) {
+  // the same loads on every path, from addresses chosen by selects (loads on separate
+  // branches land in separate registers, and the copy that merges them waits for them)
+  const Geo& g = a.g;
+  const double* gt = nullptr;  // the ghost table row, if the cell is a ghost
+  int kc = k;
+  if (k < 0 || k >= g.nz) {
+    const int ii = min(max(i, 0), g.nr - 1);
+    if (!(EXT && g.bc_z == 1)) {
+      const int side = k < 0 ? 0 : 1;
+      const int layer = min(k < 0 ? -1 - k : k - g.nz, 1);
+      gt = a.t.ghz + ((size_t)(side * 2 + layer) * g.nr + ii) * g.nf + F0;
+    }
+    kc = k < 0 ? 0 : g.nz - 1;  // outflow: the boundary cell's dust variables
+  } else if (i < 0 || i >= g.nr) {
+    const int side = i < 0 ? 0 : 1;
+    const int layer = min(i < 0 ? -1 - i : i - g.nr, 1);
+    gt = a.t.ghr + ((size_t)(side * 2 + layer) * g.nz + k) * g.nf + F0;
+  }
+  const int ic = min(max(i, 0), g.nr - 1);  // a valid cell for the loads a ghost ignores
+  const bool gh = gt != nullptr;
+  R.ghost = gh;
+  const size_t cell = ((size_t)kc * g.nr + ic) * g.nth + j;
+  if constexpr (P32) {
+    const int sp = (F0 - 5) >> 2;
+    const float* vel = (const float*)st + (size_t)(5 + 3 * sp) * g.N + cell;
+    const double* v0 = a.t.wc + ((size_t)kc * g.nr + ic) * WB_N + WB_V;
+    const double* rd = (const double*)st + p32_f64_base(g) + (size_t)sp * g.N + cell;
+    const double* p0 = gh ? gt : v0;
+    const double* p1 = gh ? gt + 1 : v0;
+    const double* p2 = gh ? gt + 2 : v0;
+    const double* p3 = gh ? gt + 3 : rd;
+    R.d[0] = *p0;
+    R.d[1] = *p1;
+    R.d[2] = *p2;
+    R.d[3] = *p3;
+    R.v[0] = vel[0];
+    R.v[1] = vel[g.N];
+    R.v[2] = vel[2 * (size_t)g.N];
+  } else {
+    const double* d = (const double*)st + (size_t)F0 * g.N + cell;
+#pragma unroll
+    for (int f = 0; f < 4; ++f) {
+      const double* p = gh ? gt + f : d + (size_t)f * g.N;
+      R.d[f] = *p;
+    }
+  }
+}
+template <bool P32>
+__device__ __forceinline__ void dust_finish(const DustRaw<P32>& R, double* out) {
+  const double rd = R.d[3];
+  const bool full = rd > 0.0;
+  if constexpr (P32) {
+    out[0] = R.ghost ? R.d[0] : (full ? (double)R.v[0] : 0.0);
+    out[1] = R.ghost ? R.d[1] : (full ? R.d[1] + (double)R.v[1] : 0.0);
+    out[2] = R.ghost ? R.d[2] : (full ? (double)R.v[2] : 0.0);
+  } else {
+    const double id = full ? 1.0 / rd : 0.0;
+#pragma unroll
+    for (int f = 0; f < 3; ++f) out[f] = R.ghost ? R.d[f] : R.d[f] * id;
+  }
+  out[3] = rd;
 }
 
 // stationary-flow primitives (WB_N entry) of an interior cell or of the ghost next to the

@@ -128,6 +128,7 @@ __global__ void __launch_bounds__(NTM, WPE) k_march(StageArgs a, int species) {
   const double Vc = rt[RT_V], invV = rt[RT_INVV], Ath = rt[RT_ATH], Az = rt[RT_AZ];
   const double invrc = rt[RT_INVRC], omk = rt[RT_OMK], maxA = rt[RT_MAXA];
   const double Arlo = a.t.ar[igc], Arhi = a.t.ar[igc + 1];
+  const double Ar0 = a.t.ar[0];  // inner boundary face (ledger)
 
   // gas face: FP64 full states, or FP32 perturbations about the face background; the
   // cells' reconstructed variables, the stationary flow at the face (bf) and at the
@@ -200,7 +201,18 @@ __global__ void __launch_bounds__(NTM, WPE) k_march(StageArgs a, int species) {
   const int h2_jj = (j0 + h2_cc - 2 + g.nth) % g.nth;
   constexpr bool PF = !PG;
   T hv[NG];
-  if (PF && halo_t) load_recon<P32, EXT, NG>(a, in, F0, k0, h_ii, h_jj, hv);
+  // dust: the next plane's first-slot halo and the column's cell k+2 are fetched raw at
+  // the top of a plane and formed after the faces (the halo after the second barrier, the
+  // column cell before the z face), so that no wait for them precedes the faces
+  DustRaw<P32> hraw, nraw;
+  if constexpr (GAS) {
+    if (PF && halo_t) load_recon<P32, EXT, NG>(a, in, F0, k0, h_ii, h_jj, hv);
+  } else {
+    if (halo_t) {
+      dust_fetch<P32, EXT>(a, in, F0, k0, h_ii, h_jj, hraw);
+      dust_finish<P32>(hraw, hv);
+    }
+  }
 
   if (tab_t) s_tab[k0 & 1][tid] = tab_p0[(size_t)k0 * tab_stride];
   // the radial parabola weights and limiter bounds of rows i0-1 .. i0+TM (plane
@@ -208,9 +220,14 @@ __global__ void __launch_bounds__(NTM, WPE) k_march(StageArgs a, int species) {
   __shared__ double s_rco[(TM + 2) * RC_N];
   if (tid < (TM + 2) * RC_N) s_rco[tid] = rco_ptr(a, i0 - 1 + tid / RC_N)[tid % RC_N];
 
+  // every load of the set-up done before the march: a load still in flight at the loop's
+  // entry makes the compiler wait for all memory operations at the top of every plane,
+  // the previous plane's stores included
+  __builtin_amdgcn_s_waitcnt(0);
   for (int k = k0; k < k1; ++k) {
     if (!twod) {
-      load_recon<P32, EXT, NG>(a, in, F0, k + 2, ig, jw, rn);
+      if constexpr (GAS) load_recon<P32, EXT, NG>(a, in, F0, k + 2, ig, jw, rn);
+      else dust_fetch<P32, EXT>(a, in, F0, k + 2, ig, jw, nraw);
     }
     const int kb = k & 1;
     double tab_next = 0.0;
@@ -252,10 +269,16 @@ __global__ void __launch_bounds__(NTM, WPE) k_march(StageArgs a, int species) {
 #pragma unroll
     for (int f = 0; f < NG; ++f) s_pl[f][ti + 2][tj + 2] = r0[f];
     if (halo_t) {
-      if (!PF) load_recon<P32, EXT, NG>(a, in, F0, k, h_ii, h_jj, hv);
+      if constexpr (GAS) {
+        if (!PF) load_recon<P32, EXT, NG>(a, in, F0, k, h_ii, h_jj, hv);
+      }
 #pragma unroll
       for (int f = 0; f < NG; ++f) s_pl[f][h_rr][h_cc] = hv[f];
-      if (PF && k + 1 < k1) load_recon<P32, EXT, NG>(a, in, F0, k + 1, h_ii, h_jj, hv);
+      if constexpr (GAS) {
+        if (PF && k + 1 < k1) load_recon<P32, EXT, NG>(a, in, F0, k + 1, h_ii, h_jj, hv);
+      } else {
+        if (k + 1 < k1) dust_fetch<P32, EXT>(a, in, F0, k + 1, h_ii, h_jj, hraw);
+      }
     }
     if constexpr (NH2 > 0) {
       if (halo2) {
@@ -321,7 +344,7 @@ __global__ void __launch_bounds__(NTM, WPE) k_march(StageArgs a, int species) {
       if (a.second && i0 == 0 && j0 + col < g.nth) {
         double fm = (double)F[NG - 1];
         if (PG) fm += bf[WB_RHO] * bf[WB_U];
-        ledger -= a.t.ar[0] * fm;
+        ledger -= Ar0 * fm;
       }
     } else if (tid < TJ + TM) {
       T eA[NG], eB[NG], eC[NG], eD[NG], F[NG];
@@ -338,6 +361,7 @@ __global__ void __launch_bounds__(NTM, WPE) k_march(StageArgs a, int species) {
     }
     // ---- z face k+1/2 from the register ring
     if (!twod) {
+      if constexpr (!GAS) dust_finish<P32>(nraw, rn);
       if constexpr (LR) {
 #pragma unroll
         for (int f = 0; f < NG; ++f) rm[f] = s_rm[f][tslot];
@@ -353,6 +377,13 @@ __global__ void __launch_bounds__(NTM, WPE) k_march(StageArgs a, int species) {
       }
     }
     __syncthreads();
+    // ---- the next plane's tables (read after the next plane's first barrier; buffer
+    //      (k + 1) & 1 was last read before this plane's first barrier) and the dust halo;
+    //      both here, before this plane's stores, so that waiting for them waits for no store
+    if (tab_t && k + 1 < k1) s_tab[(k + 1) & 1][tid] = tab_next;
+    if constexpr (!GAS) {
+      if (halo_t && k + 1 < k1) dust_finish<P32>(hraw, hv);
+    }
     // ---- divergence -sum_s A_s F.n_s (Sect. 2.2), sources (App. B), drag (Sect. 2.9)
     T Gd[NG];
 #pragma unroll
@@ -564,7 +595,7 @@ __global__ void __launch_bounds__(NTM, WPE) k_march(StageArgs a, int species) {
         } else {
           // FP32 dust velocities are formed with the new density (all values above were
           // read before any store, the update may be in place)
-          st_dust32(a, a.out, species, k, ig, cell, nvd);
+          st_dust32(a, a.out, species, cell, nvd, bw[WB_V]);
         }
       }
       if (GAS) {
@@ -596,9 +627,6 @@ __global__ void __launch_bounds__(NTM, WPE) k_march(StageArgs a, int species) {
         dtmin = fmin(dtmin, g.cfl * Vc / (spd * maxA));
       }
     }
-    // ---- the next plane's tables (read after the next plane's first barrier; buffer
-    //      (k + 1) & 1 was last read in the previous plane)
-    if (tab_t && k + 1 < k1) s_tab[(k + 1) & 1][tid] = tab_next;
     // ---- shift the ring
 #pragma unroll
     for (int f = 0; f < NG; ++f) {
