@@ -857,6 +857,54 @@ __device__ __forceinline__ void dust_fetch(const StageArgs& a, const void* st, i
     }
   }
 }
+// The same two steps for a gas cell in the FP32-perturbation layout (base boundary
+// options): the stored deviations e and the cell's stationary density and azimuthal
+// velocity (the form runs on the disc background, whose stationary flow has no radial or
+// vertical velocity).  Ghost cells (tiles at the radial boundaries, the last planes) are
+// formed at once.
+struct GasRaw32 {
+  double rho0, v0;
+  float e[5];
+  bool ghost;
+};
+__device__ __forceinline__ void gas_fetch32(const StageArgs& a, const void* st, int k, int i, int j,
+                                            GasRaw32& R) {
+  const Geo& g = a.g;
+  const double* gt = nullptr;
+  if (k < 0 || k >= g.nz) {
+    const int ii = min(max(i, 0), g.nr - 1);
+    const int side = k < 0 ? 0 : 1;
+    const int layer = min(k < 0 ? -1 - k : k - g.nz, 1);
+    gt = a.t.ghz + ((size_t)(side * 2 + layer) * g.nr + ii) * g.nf;
+  } else if (i < 0 || i >= g.nr) {
+    const int side = i < 0 ? 0 : 1;
+    const int layer = min(i < 0 ? -1 - i : i - g.nr, 1);
+    gt = a.t.ghr + ((size_t)(side * 2 + layer) * g.nz + k) * g.nf;
+  }
+  R.ghost = gt != nullptr;
+  if (gt) {
+#pragma unroll
+    for (int f = 0; f < 5; ++f) R.e[f] = (float)gt[f];
+  } else {
+    const size_t cell = ((size_t)k * g.nr + i) * g.nth + j;
+    const double* bw = a.t.wc + ((size_t)k * g.nr + i) * WB_N;
+#pragma unroll
+    for (int f = 0; f < 5; ++f) R.e[f] = ((const float*)st)[(size_t)f * g.N + cell];
+    R.rho0 = bw[WB_RHO];
+    R.v0 = bw[WB_V];
+  }
+}
+__device__ __forceinline__ void gas_finish32(const GasRaw32& R, float gm1, float* out) {
+  double bw[WB_N];
+  bw[WB_RHO] = R.rho0;
+  bw[WB_U] = 0.0;
+  bw[WB_V] = R.v0;
+  bw[WB_W] = 0.0;
+  float w[5];
+  cell_w(R.e, bw, gm1, w);
+#pragma unroll
+  for (int f = 0; f < 5; ++f) out[f] = R.ghost ? R.e[f] : w[f];
+}
 template <bool P32>
 __device__ __forceinline__ void dust_finish(const DustRaw<P32>& R, double* out) {
   const double rd = R.d[3];

@@ -205,7 +205,18 @@ __global__ void __launch_bounds__(NTM, WPE) k_march(StageArgs a, int species) {
   // the top of a plane and formed after the faces (the halo after the second barrier, the
   // column cell before the z face), so that no wait for them precedes the faces
   DustRaw<P32> hraw, nraw;
-  if constexpr (GAS) {
+  // FP32 gas (base boundary options): the column's cell k+2 the same way; the next plane's
+  // halo is requested after the second barrier, ahead of the drag's dust loads (one wait
+  // for both), and formed before the update's stores
+  constexpr bool RAWG = PG && !EXT;
+  const float gm1f = (float)(g.gamma - 1.0);
+  GasRaw32 gnraw, ghraw;
+  if constexpr (RAWG) {
+    if (halo_t) {
+      gas_fetch32(a, in, k0, h_ii, h_jj, ghraw);
+      gas_finish32(ghraw, gm1f, hv);
+    }
+  } else if constexpr (GAS) {
     if (PF && halo_t) load_recon<P32, EXT, NG>(a, in, F0, k0, h_ii, h_jj, hv);
   } else {
     if (halo_t) {
@@ -226,7 +237,8 @@ __global__ void __launch_bounds__(NTM, WPE) k_march(StageArgs a, int species) {
   __builtin_amdgcn_s_waitcnt(0);
   for (int k = k0; k < k1; ++k) {
     if (!twod) {
-      if constexpr (GAS) load_recon<P32, EXT, NG>(a, in, F0, k + 2, ig, jw, rn);
+      if constexpr (RAWG) gas_fetch32(a, in, k + 2, ig, jw, gnraw);
+      else if constexpr (GAS) load_recon<P32, EXT, NG>(a, in, F0, k + 2, ig, jw, rn);
       else dust_fetch<P32, EXT>(a, in, F0, k + 2, ig, jw, nraw);
     }
     const int kb = k & 1;
@@ -269,7 +281,7 @@ __global__ void __launch_bounds__(NTM, WPE) k_march(StageArgs a, int species) {
 #pragma unroll
     for (int f = 0; f < NG; ++f) s_pl[f][ti + 2][tj + 2] = r0[f];
     if (halo_t) {
-      if constexpr (GAS) {
+      if constexpr (GAS && !RAWG) {
         if (!PF) load_recon<P32, EXT, NG>(a, in, F0, k, h_ii, h_jj, hv);
       }
 #pragma unroll
@@ -361,7 +373,8 @@ __global__ void __launch_bounds__(NTM, WPE) k_march(StageArgs a, int species) {
     }
     // ---- z face k+1/2 from the register ring
     if (!twod) {
-      if constexpr (!GAS) dust_finish<P32>(nraw, rn);
+      if constexpr (RAWG) gas_finish32(gnraw, gm1f, rn);
+      else if constexpr (!GAS) dust_finish<P32>(nraw, rn);
       if constexpr (LR) {
 #pragma unroll
         for (int f = 0; f < NG; ++f) rm[f] = s_rm[f][tslot];
@@ -383,6 +396,9 @@ __global__ void __launch_bounds__(NTM, WPE) k_march(StageArgs a, int species) {
     if (tab_t && k + 1 < k1) s_tab[(k + 1) & 1][tid] = tab_next;
     if constexpr (!GAS) {
       if (halo_t && k + 1 < k1) dust_finish<P32>(hraw, hv);
+    }
+    if constexpr (RAWG) {
+      if (halo_t && k + 1 < k1) gas_fetch32(a, in, k + 1, h_ii, h_jj, ghraw);
     }
     // ---- divergence -sum_s A_s F.n_s (Sect. 2.2), sources (App. B), drag (Sect. 2.9)
     T Gd[NG];
@@ -529,6 +545,9 @@ __global__ void __launch_bounds__(NTM, WPE) k_march(StageArgs a, int species) {
       load_cons<P32, NG>(a, in, F0, k, igc, jw, e);
 #pragma unroll
       for (int f = 0; f < NG; ++f) S[f] -= (T)(kd * e[f]);
+    }
+    if constexpr (RAWG) {
+      if (halo_t && k + 1 < k1) gas_finish32(ghraw, gm1f, hv);
     }
     T Gt[NG];
 #pragma unroll
