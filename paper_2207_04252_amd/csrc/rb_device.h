@@ -15,22 +15,19 @@ namespace rb {
 // small helpers
 
 // minmod of three: when all three share a sign, the one of smallest magnitude, else zero.
-// Branch-free: the sign test on the sign bits, the magnitude from two minima (a zero
-// argument gives a zero magnitude, so only the sign of that zero can differ).
-__device__ __forceinline__ bool same_sign3(double x, double y, double z) {
-  const unsigned bx = (unsigned)(__double_as_longlong(x) >> 32);
-  const unsigned by = (unsigned)(__double_as_longlong(y) >> 32);
-  const unsigned bz = (unsigned)(__double_as_longlong(z) >> 32);
-  return (int)((bx ^ by) | (bx ^ bz)) >= 0;
-}
-__device__ __forceinline__ bool same_sign3(float x, float y, float z) {
-  const unsigned bx = __float_as_uint(x), by = __float_as_uint(y), bz = __float_as_uint(z);
-  return (int)((bx ^ by) | (bx ^ bz)) >= 0;
-}
+// Branch-free: all positive, the smallest (first term); all negative, the largest (second
+// term); otherwise both terms are zero.  One term is always zero, so the sum is exact (only
+// the sign of a zero result can differ from a select).
 template <class T>
 __device__ __forceinline__ T minmod3(T x, T y, T z) {
-  const T m = fmin(fabs(x), fmin(fabs(y), fabs(z)));
-  return same_sign3(x, y, z) ? copysign(m, x) : T(0);
+  return fmax(fmin(x, fmin(y, z)), T(0)) + fmin(fmax(x, fmax(y, z)), T(0));
+}
+// FP32: minmod(a, b) is the median of a, b and 0 (same signs: the one nearer zero; opposite
+// signs: zero), and minmod of three is minmod(x, minmod(y, z)): two hardware medians, each
+// returning one of its arguments exactly (only the sign of a zero result can differ)
+template <>
+__device__ __forceinline__ float minmod3<float>(float x, float y, float z) {
+  return __builtin_amdgcn_fmed3f(x, __builtin_amdgcn_fmed3f(y, z, 0.0f), 0.0f);
 }
 
 // Uniform direction (index coordinates): the three-point parabola gives the upper-face

@@ -255,10 +255,17 @@ __global__ void __launch_bounds__(NTM, WPE) k_march(StageArgs a, int species) {
     using BT = typename std::conditional<PG, float, double>::type;
     BT pb[NG];
     float pvel[P32 && !GAS ? 3 : 1];  // FP32 dust layout: stored velocity deviations
-    if (upd && !base_r0) {
-      if constexpr (PG) {
+    // (the FP32 gas kernel requests them after the second barrier instead, with the drag's
+    // loads: held across the faces they would spill)
+    auto load_base_pg = [&]() {
+      if (upd) {
 #pragma unroll
         for (int f = 0; f < NG; ++f) pb[f] = ((const float*)a.base)[(size_t)f * g.N + cell];
+      }
+    };
+    if (upd && !base_r0) {
+      if constexpr (PG) {
+        if constexpr (!RAWG) load_base_pg();
       } else if constexpr (P32 && !GAS) {
         const float* vel = (const float*)a.base + (size_t)(5 + 3 * species) * g.N + cell;
         pb[3] = ((const double*)a.base)[p32_f64_base(g) + (size_t)species * g.N + cell];
@@ -398,6 +405,7 @@ __global__ void __launch_bounds__(NTM, WPE) k_march(StageArgs a, int species) {
       if (halo_t && k + 1 < k1) dust_finish<P32>(hraw, hv);
     }
     if constexpr (RAWG) {
+      load_base_pg();
       if (halo_t && k + 1 < k1) gas_fetch32(a, in, k + 1, h_ii, h_jj, ghraw);
     }
     // ---- divergence -sum_s A_s F.n_s (Sect. 2.2), sources (App. B), drag (Sect. 2.9)
@@ -571,16 +579,29 @@ __global__ void __launch_bounds__(NTM, WPE) k_march(StageArgs a, int species) {
         }
       }
     } else if (act) {
+      // all loads before any store (the second stage updates in place).  The FP32 gas
+      // kernel stores after its positivity and CFL arithmetic, so that a wait there (a
+      // register reload) comes before the stores rather than waiting for them; the others
+      // store first (their registers prefer it)
       double nvd[NG];
+      float nv[PG ? NG : 1];
+      auto store_new = [&]() {
+        if constexpr (PG) {
+#pragma unroll
+          for (int f = 0; f < NG; ++f) ((float*)a.out)[(size_t)f * g.N + cell] = nv[f];
+        } else if constexpr (!P32 || GAS) {
+#pragma unroll
+          for (int f = 0; f < NG; ++f) st_cell<P32>(a, a.out, F0 + f, k, ig, cell, nvd[f]);
+        } else {
+          // FP32 dust velocities are formed with the new density
+          st_dust32(a, a.out, species, cell, nvd, bw[WB_V]);
+        }
+      };
       if constexpr (PG) {
         const float cdt = (float)(a.coef * dt * invV);
-        float nv[NG];
-        // all loads before any store: the second stage updates in place
-#pragma unroll
-        for (int f = 0; f < NG; ++f) nv[f] = fma(cdt, Gt[f], pb[f]);
 #pragma unroll
         for (int f = 0; f < NG; ++f) {
-          ((float*)a.out)[(size_t)f * g.N + cell] = nv[f];
+          nv[f] = fma(cdt, Gt[f], pb[f]);
           nvd[f] = (double)nv[f];
         }
       } else {
@@ -608,14 +629,7 @@ __global__ void __launch_bounds__(NTM, WPE) k_march(StageArgs a, int species) {
         }
 #pragma unroll
         for (int f = 0; f < NG; ++f) nvd[f] = fma(cdt, (double)Gt[f], bv[f]);
-        if (!P32 || GAS) {
-#pragma unroll
-          for (int f = 0; f < NG; ++f) st_cell<P32>(a, a.out, F0 + f, k, ig, cell, nvd[f]);
-        } else {
-          // FP32 dust velocities are formed with the new density (all values above were
-          // read before any store, the update may be in place)
-          st_dust32(a, a.out, species, cell, nvd, bw[WB_V]);
-        }
+        store_new();
       }
       if (GAS) {
         // positivity of the new gas state; CFL of the new state (second stage)
@@ -645,6 +659,7 @@ __global__ void __launch_bounds__(NTM, WPE) k_march(StageArgs a, int species) {
         double spd = sqrt(a1 * a1 + a2 * a2 + a3 * a3);
         dtmin = fmin(dtmin, g.cfl * Vc / (spd * maxA));
       }
+      if constexpr (PG) store_new();
     }
     // ---- shift the ring
 #pragma unroll
