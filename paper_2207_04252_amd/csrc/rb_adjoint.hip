@@ -256,11 +256,11 @@ __device__ __forceinline__ void gas_face_states(const double* wA, const double* 
   for (int f = 0; f < 5; ++f) {
     double iB, iC;
     if (DIR == 0) {
-      iB = inc_up_c(wA[f], wB[f], wC[f], coB);
-      iC = inc_lo_c(wB[f], wC[f], wD[f], coC);
+      iB = inc_up_c<double, true>(wA[f], wB[f], wC[f], coB);
+      iC = inc_lo_c<double, true>(wB[f], wC[f], wD[f], coC);
     } else {
-      iB = inc_up_u(wA[f], wB[f], wC[f]);
-      iC = inc_lo_u(wB[f], wC[f], wD[f]);
+      iB = inc_up_u<double, true>(wA[f], wB[f], wC[f]);
+      iC = inc_lo_u<double, true>(wB[f], wC[f], wD[f]);
     }
     qL[f] = bf[f] + (wB[f] + iB);
     qR[f] = bf[f] + (wC[f] + iC);
@@ -345,13 +345,13 @@ __device__ void dust_face_vjp(const double* wA, const double* wB, const double* 
   for (int f = 0; f < 4; ++f) {
     double iB, iC;
     if (DIR == 0) {
-      iB = inc_up_c(wA[f], wB[f], wC[f], coB);
-      iC = inc_lo_c(wB[f], wC[f], wD[f], coC);
+      iB = inc_up_c<double, true>(wA[f], wB[f], wC[f], coB);
+      iC = inc_lo_c<double, true>(wB[f], wC[f], wD[f], coC);
       dinc_up_c(wA[f], wB[f], wC[f], coB, cmB[f], cpB[f]);
       dinc_lo_c(wB[f], wC[f], wD[f], coC, cmC[f], cpC[f]);
     } else {
-      iB = inc_up_u(wA[f], wB[f], wC[f]);
-      iC = inc_lo_u(wB[f], wC[f], wD[f]);
+      iB = inc_up_u<double, true>(wA[f], wB[f], wC[f]);
+      iC = inc_lo_u<double, true>(wB[f], wC[f], wD[f]);
       dinc_up_u(wA[f], wB[f], wC[f], cmB[f], cpB[f]);
       dinc_lo_u(wB[f], wC[f], wD[f], cmC[f], cpC[f]);
     }
@@ -435,6 +435,17 @@ struct AdjCtx {
     return A.cw * a.t.rt[(size_t)i * RT_N + RT_INVV] *
            A.cot[(size_t)(F0 + f) * g.N + ((size_t)k * g.nr + i) * g.nth + j];
   }
+  // w of every field of a cell (zero outside the grid), all loads requested together
+  __device__ void wc_all(int k, int i, int j, double* out) const {
+    const bool in = !(k < 0 || k >= g.nz || i < 0 || i >= g.nr);
+    const size_t c = in ? ((size_t)k * g.nr + i) * g.nth + j : 0;
+    const double v = in ? a.t.rt[(size_t)i * RT_N + RT_INVV] : 0.0;
+    double x[NG];
+#pragma unroll
+    for (int f = 0; f < NG; ++f) x[f] = A.cot[(size_t)(F0 + f) * g.N + c];
+#pragma unroll
+    for (int f = 0; f < NG; ++f) out[f] = in ? A.cw * v * x[f] : 0.0;
+  }
   // the difference w(k1, i1, j1) - w(k0, i0, j0) of every field, times s, with all loads
   // requested before any arithmetic (loads under per-field conditions each waited)
   __device__ void wc_diff(int k1, int i1, int j1, int k0, int i0, int j0, double s,
@@ -483,6 +494,9 @@ __global__ void __launch_bounds__(NT) k_adj_plane(AdjArgs A, int species) {
   constexpr int NG = C::NG;
   constexpr int H = 3;
   __shared__ double s_e[NG][TI + 2 * H][TJ + 2 * H];
+  // w = cw V^-1 lambda of the staged cells (zero outside the grid), staged with the plane
+  // so that the faces read no global memory
+  __shared__ double s_w[NG][TI + 2 * H][TJ + 2 * H];
   __shared__ double s_at[NG][TI][TJ];
   __shared__ double s_ar[NG][TI][TJ];
   __shared__ double s_red[NT / 64];
@@ -520,9 +534,9 @@ __global__ void __launch_bounds__(NT) k_adj_plane(AdjArgs A, int species) {
   auto theta_face = [&](int k, int r, int cb, double* oA, double* oB, double* oC, double* oD) {
     double eA[NG], eB[NG], eC[NG], eD[NG], Fb[NG];
     const int i = i0 + r;
-    const int jb = X.jwrap(j0 + cb), jc = X.jwrap(j0 + cb + 1);
     const double ath = a.t.rt[(size_t)i * RT_N + RT_ATH];
-    X.wc_diff(k, i, jc, k, i, jb, ath, Fb);
+#pragma unroll
+    for (int f = 0; f < NG; ++f) Fb[f] = ath * (s_w[f][r + H][cb + 1 + H] - s_w[f][r + H][cb + H]);
 #pragma unroll
     for (int f = 0; f < NG; ++f) {
       eA[f] = s_e[f][r + H][cb + H - 1]; eB[f] = s_e[f][r + H][cb + H];
@@ -537,9 +551,9 @@ __global__ void __launch_bounds__(NT) k_adj_plane(AdjArgs A, int species) {
   auto r_face = [&](int k, int rb, int cl, double* oA, double* oB, double* oC, double* oD) {
     double eA[NG], eB[NG], eC[NG], eD[NG], Fb[NG];
     const int ib = i0 + rb;
-    const int j = X.jwrap(j0 + cl);
     const double ar = a.t.ar[ib + 1];
-    X.wc_diff(k, ib + 1, j, k, ib, j, ar, Fb);
+#pragma unroll
+    for (int f = 0; f < NG; ++f) Fb[f] = ar * (s_w[f][rb + 1 + H][cl + H] - s_w[f][rb + H][cl + H]);
 #pragma unroll
     for (int f = 0; f < NG; ++f) {
       eA[f] = s_e[f][rb + H - 1][cl + H]; eB[f] = s_e[f][rb + H][cl + H];
@@ -559,14 +573,24 @@ __global__ void __launch_bounds__(NT) k_adj_plane(AdjArgs A, int species) {
       constexpr int W = TJ + 2 * H, NC = (TI + 2 * H) * W;
       static_assert(NC <= 2 * NT, "two staged cells per thread");
       const int h0 = tid, h1 = tid + NT;
-      double v0[NG], v1[NG];
-      load_recon<false, false, NG>(a, E, F0, k, i0 + h0 / W - H, X.jwrap(j0 + h0 % W - H), v0);
-      if (h1 < NC) load_recon<false, false, NG>(a, E, F0, k, i0 + h1 / W - H, X.jwrap(j0 + h1 % W - H), v1);
+      const int ia = i0 + h0 / W - H, ja = X.jwrap(j0 + h0 % W - H);
+      const int ib = i0 + h1 / W - H, jb = X.jwrap(j0 + h1 % W - H);
+      double v0[NG], v1[NG], c0[NG], c1[NG];
+      X.wc_all(k, ia, ja, c0);
+      if (h1 < NC) X.wc_all(k, ib, jb, c1);
+      load_recon<false, false, NG>(a, E, F0, k, ia, ja, v0);
+      if (h1 < NC) load_recon<false, false, NG>(a, E, F0, k, ib, jb, v1);
 #pragma unroll
-      for (int f = 0; f < NG; ++f) s_e[f][h0 / W][h0 % W] = v0[f];
+      for (int f = 0; f < NG; ++f) {
+        s_e[f][h0 / W][h0 % W] = v0[f];
+        s_w[f][h0 / W][h0 % W] = c0[f];
+      }
       if (h1 < NC) {
 #pragma unroll
-        for (int f = 0; f < NG; ++f) s_e[f][h1 / W][h1 % W] = v1[f];
+        for (int f = 0; f < NG; ++f) {
+          s_e[f][h1 / W][h1 % W] = v1[f];
+          s_w[f][h1 / W][h1 % W] = c1[f];
+        }
       }
     }
 #pragma unroll

@@ -15,47 +15,57 @@ namespace rb {
 // small helpers
 
 // minmod of three: when all three share a sign, the one of smallest magnitude, else zero.
-// Branch-free: all positive, the smallest (first term); all negative, the largest (second
-// term); otherwise both terms are zero.  One term is always zero, so the sum is exact (only
-// the sign of a zero result can differ from a select).
-template <class T>
-__device__ __forceinline__ T minmod3(T x, T y, T z) {
-  return fmax(fmin(x, fmin(y, z)), T(0)) + fmin(fmax(x, fmax(y, z)), T(0));
+// Three branch-free forms giving the same value (only the sign of a zero result can
+// differ):
+//  * FP32: minmod(a, b) is the median of a, b and 0, and minmod of three is
+//    minmod(x, minmod(y, z)): two hardware medians, each returning one of its arguments;
+//  * FP64: all positive, the smallest (first term); all negative, the largest (second
+//    term); otherwise both terms are zero, and one term always is, so the sum is exact;
+//  * FP64 with SEL: the sign test on the sign bits and the magnitude from two minima
+//    (fewer live registers: the adjoint's face kernels take it).
+__device__ __forceinline__ double minmod3_sel(double x, double y, double z) {
+  const unsigned bx = (unsigned)(__double_as_longlong(x) >> 32);
+  const unsigned by = (unsigned)(__double_as_longlong(y) >> 32);
+  const unsigned bz = (unsigned)(__double_as_longlong(z) >> 32);
+  const double m = fmin(fabs(x), fmin(fabs(y), fabs(z)));
+  return (int)((bx ^ by) | (bx ^ bz)) >= 0 ? copysign(m, x) : 0.0;
 }
-// FP32: minmod(a, b) is the median of a, b and 0 (same signs: the one nearer zero; opposite
-// signs: zero), and minmod of three is minmod(x, minmod(y, z)): two hardware medians, each
-// returning one of its arguments exactly (only the sign of a zero result can differ)
-template <>
-__device__ __forceinline__ float minmod3<float>(float x, float y, float z) {
-  return __builtin_amdgcn_fmed3f(x, __builtin_amdgcn_fmed3f(y, z, 0.0f), 0.0f);
+template <class T, bool SEL = false>
+__device__ __forceinline__ T minmod3(T x, T y, T z) {
+  if constexpr (std::is_same<T, float>::value)
+    return __builtin_amdgcn_fmed3f(x, __builtin_amdgcn_fmed3f(y, z, 0.0f), 0.0f);
+  else if constexpr (SEL)
+    return minmod3_sel(x, y, z);
+  else
+    return fmax(fmin(x, fmin(y, z)), T(0)) + fmin(fmax(x, fmax(y, z)), T(0));
 }
 
 // Uniform direction (index coordinates): the three-point parabola gives the upper-face
 // increment (dm + 3 dp)/8 and the lower-face increment -(3 dm + dp)/8, limited by the
 // one-sided differences (Sect. 2.7).  Written so that mirrored data give exactly
 // opposite increments.
-template <class T>
+template <class T, bool SEL = false>
 __device__ __forceinline__ T inc_up_u(T em, T e0, T ep) {
   T dm = e0 - em, dp = ep - e0;
-  return minmod3<T>(fma(T(3), dp, dm) * T(0.125), dm, dp);
+  return minmod3<T, SEL>(fma(T(3), dp, dm) * T(0.125), dm, dp);
 }
-template <class T>
+template <class T, bool SEL = false>
 __device__ __forceinline__ T inc_lo_u(T em, T e0, T ep) {
   T dm = e0 - em, dp = ep - e0;
-  return minmod3<T>(-(fma(T(3), dm, dp) * T(0.125)), -dm, -dp);
+  return minmod3<T, SEL>(-(fma(T(3), dm, dp) * T(0.125)), -dm, -dp);
 }
 // Non-uniform r: precomputed parabola weights and limiter bounds of the cell.
-template <class T>
+template <class T, bool SEL = false>
 __device__ __forceinline__ T inc_up_c(T em, T e0, T ep, const double* co) {
   T dm = e0 - em, dp = ep - e0;
-  return minmod3<T>(fma(T(co[RC_WPP]), dp, T(co[RC_WPM]) * dm), T(co[RC_LPM]) * dm,
-                    T(co[RC_LPP]) * dp);
+  return minmod3<T, SEL>(fma(T(co[RC_WPP]), dp, T(co[RC_WPM]) * dm), T(co[RC_LPM]) * dm,
+                         T(co[RC_LPP]) * dp);
 }
-template <class T>
+template <class T, bool SEL = false>
 __device__ __forceinline__ T inc_lo_c(T em, T e0, T ep, const double* co) {
   T dm = e0 - em, dp = ep - e0;
-  return minmod3<T>(fma(T(co[RC_WMP]), dp, T(co[RC_WMM]) * dm), T(co[RC_LMM]) * dm,
-                    T(co[RC_LMP]) * dp);
+  return minmod3<T, SEL>(fma(T(co[RC_WMP]), dp, T(co[RC_WMM]) * dm), T(co[RC_LMM]) * dm,
+                         T(co[RC_LMP]) * dp);
 }
 
 // x^(-1/7) for x > 0: FP32 hardware log2/exp2 seed (relative error ~1e-7 for x in the
