@@ -121,6 +121,11 @@ __global__ void __launch_bounds__(NTM, WPE) k_march(StageArgs a, int species) {
     }
   }
   double dtmin = 1e300;
+  // the largest signal speed of the thread's new cells (dust: its square).  The thread's
+  // row (so its volume and largest face area) is fixed, and the CFL bound decreases with
+  // the speed, so the bound of the largest speed, formed once after the march, is the
+  // smallest one
+  double smax = 0.0, vmax2 = 0.0;
   double tsmin = 1e300;  // smallest stopping time of the new state (drag law 1)
   double ledger = 0.0;
 
@@ -645,7 +650,7 @@ __global__ void __launch_bounds__(NTM, WPE) k_march(StageArgs a, int species) {
           atomicCAS(&a.c.ctrl->bad_step, -1, a.step);
         } else if (a.second) {
           double spd = sqrt(un * un + vn * vn + wn * wn) + sqrt(gc.g * pn * in2);
-          dtmin = fmin(dtmin, g.cfl * Vc / (spd * maxA));
+          smax = fmax(smax, spd);
           if (EXT && g.drag_law) {
 #pragma unroll
             for (int s2 = 0; s2 < ND; ++s2) tsmin = fmin(tsmin, 1.0 / inv_tstop<EXT>(g, s2, omk, qn[4], pn));
@@ -656,8 +661,7 @@ __global__ void __launch_bounds__(NTM, WPE) k_march(StageArgs a, int species) {
       } else if (a.second && nvd[3] > 0.0) {
         double id = 1.0 / nvd[3];
         double a1 = nvd[0] * id, a2 = nvd[1] * id, a3 = nvd[2] * id;
-        double spd = sqrt(a1 * a1 + a2 * a2 + a3 * a3);
-        dtmin = fmin(dtmin, g.cfl * Vc / (spd * maxA));
+        vmax2 = fmax(vmax2, a1 * a1 + a2 * a2 + a3 * a3);
       }
       if constexpr (PG) store_new();
     }
@@ -674,6 +678,8 @@ __global__ void __launch_bounds__(NTM, WPE) k_march(StageArgs a, int species) {
   }
 
   // ---- block reductions: counters, CFL partial, boundary outflow partial
+  if constexpr (!GAS) smax = sqrt(vmax2);
+  if (smax > 0.0) dtmin = g.cfl * Vc / (smax * maxA);
   const int wv = tid / 64, ln = tid & 63;
   int nf_ = wave_isum(st.fall), nv_ = wave_isum(st.vac), mi_ = wave_imax(st.maxit);
   int nc_ = wave_imax(st.noconv), nr_ = wave_isum(st.resolve), nd_ = GAS ? 0 : wave_isum(st.negd);
