@@ -861,15 +861,80 @@ __global__ void __launch_bounds__(256, 2) k_adj_z(AdjArgs A, int species, int tk
 #pragma unroll
     for (int f = 0; f < NG; ++f) { za[f] = 0.0; zd[f] = 0.0; }
   }
-  for (int k = k0; k <= k1; ++k) {
+  if constexpr (GAS) {
+    for (int k = k0; k <= k1; ++k) {
 #pragma unroll
-    for (int f = 0; f < NG; ++f) { ra[f] = rb[f]; rb[f] = rc[f]; rc[f] = rd[f]; }
-    load(rd, k + 2);
-    // face k+1/2 (cells k-1, k, k+1, k+2)
-    if (real(k)) zface(k, za, zb, zc, zd);
-    if (k - 1 >= k0) add_out(k - 1, ra, za);
+      for (int f = 0; f < NG; ++f) { ra[f] = rb[f]; rb[f] = rc[f]; rc[f] = rd[f]; }
+      load(rd, k + 2);
+      // face k+1/2 (cells k-1, k, k+1, k+2)
+      if (real(k)) zface(k, za, zb, zc, zd);
+      if (k - 1 >= k0) add_out(k - 1, ra, za);
 #pragma unroll
-    for (int f = 0; f < NG; ++f) { za[f] = zb[f]; zb[f] = zc[f]; zc[f] = zd[f]; zd[f] = 0.0; }
+      for (int f = 0; f < NG; ++f) { za[f] = zb[f]; zb[f] = zc[f]; zc[f] = zd[f]; zd[f] = 0.0; }
+    }
+  } else {
+    // dust (registers to spare): the next plane's loads are requested one plane ahead and
+    // used raw a plane later — the column's next cell, the cotangent of the next face's
+    // upper cell and the output cell of the next step — so that no plane waits for memory
+    const double vinv = a.t.rt[(size_t)ig * RT_N + RT_INVV];
+    // w of a cell of the column from its cotangent (zero outside the grid)
+    auto wcell = [&](int k, const double* x, double* w) {
+      const bool in = k >= 0 && k < g.nz;
+#pragma unroll
+      for (int f = 0; f < NG; ++f) w[f] = in ? A.cw * vinv * x[f] : 0.0;
+    };
+    // a field group of cell k of the column (k clamped into the grid: a cell outside it is
+    // never used)
+    auto col_fetch = [&](const double* src, int k, double* x) {
+      const size_t c = ((size_t)min(max(k, 0), g.nz - 1) * g.nr + ig) * g.nth + jg;
+#pragma unroll
+      for (int f = 0; f < NG; ++f) x[f] = src[(size_t)(F0 + f) * g.N + c];
+    };
+    double wlo[NG], xr[NG], orw[NG];
+    {
+      double x[NG];
+      col_fetch(A.cot, k0, x);
+      wcell(k0, x, wlo);
+    }
+    col_fetch(A.cot, k0 + 1, xr);
+    DustRaw<false> nraw;
+    dust_fetch<false, false>(a, E, F0, k0 + 2, ig, jg, nraw);
+#pragma unroll
+    for (int f = 0; f < NG; ++f) orw[f] = 0.0;
+    for (int k = k0; k <= k1; ++k) {
+#pragma unroll
+      for (int f = 0; f < NG; ++f) { ra[f] = rb[f]; rb[f] = rc[f]; rc[f] = rd[f]; }
+      dust_finish<false>(nraw, rd);  // cell k+2
+      double whi[NG], ocur[NG];
+      wcell(k + 1, xr, whi);
+#pragma unroll
+      for (int f = 0; f < NG; ++f) ocur[f] = orw[f];  // the output of cell k-1
+      if (k + 1 <= k1) {
+        dust_fetch<false, false>(a, E, F0, k + 3, ig, jg, nraw);
+        col_fetch(A.cot, k + 2, xr);
+        col_fetch(A.out, k, orw);
+      }
+      // face k+1/2 (cells k-1, k, k+1, k+2)
+      if (real(k)) {
+        double Fb[NG];
+#pragma unroll
+        for (int f = 0; f < NG; ++f) Fb[f] = Az * (whi[f] - wlo[f]);
+        face_vjp<2, GAS, G75>(X.gc, ra, rb, rc, rd, nullptr, nullptr, nullptr, nullptr, nullptr,
+                              Fb, za, zb, zc, zd);
+      }
+      if (k - 1 >= k0) {
+        const size_t cell = ((size_t)(k - 1) * g.nr + ig) * g.nth + jg;
+        double ec[NG];
+        cot_to_cons<GAS>(ra, nullptr, X.gc.gm1, za, ec);
+#pragma unroll
+        for (int f = 0; f < NG; ++f) A.out[(size_t)(F0 + f) * g.N + cell] = ocur[f] + ec[f];
+      }
+#pragma unroll
+      for (int f = 0; f < NG; ++f) {
+        wlo[f] = whi[f];
+        za[f] = zb[f]; zb[f] = zc[f]; zc[f] = zd[f]; zd[f] = 0.0;
+      }
+    }
   }
 }
 
